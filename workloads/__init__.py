@@ -1,0 +1,329 @@
+"""Seeded synthetic inputs shaped like the paper's benchmark problems (§4).
+
+This module is shared by the GPU path's callers (tests, bench, smoke) and by the CPU
+oracle. It holds problem definitions only and none of the FR-PCPF method's arithmetic:
+
+* box meshes: grid planes (uniform, or interior planes shifted by a seeded uniform
+  perturbation), the element corner and the constant Jacobian of each affine element,
+  and the element adjacency of the box (including periodic wrap);
+* the initial condition of §4 (tanh profile of a signed distance, Eq. initialCond with the
+  disc/sphere distance of Eq. discEq), evaluated at coordinates the caller supplies;
+* velocity-field identifiers and the parameter values the paper fixes (§2, §3.2, §4);
+* the benchmark configurations (2D rotation/vortex and 3D deformation shapes).
+
+Coordinates of solution points are NOT computed here: each side maps its own reference
+nodes.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field, replace
+from typing import Optional, Sequence
+
+import numpy as np
+
+# velocity kinds (same numbering as the C-ABI enum)
+VEL_UNIFORM = 0
+VEL_ROTATION = 1
+VEL_SINGLE_VORTEX = 2
+VEL_LEVEQUE3D = 3
+
+RESET_LINEAR = 0
+RESET_LOGIT = 1
+
+
+# --------------------------------------------------------------------------------------
+# meshes
+# --------------------------------------------------------------------------------------
+@dataclass
+class BoxMesh:
+    """Axis-aligned (optionally x-sheared in 2D) box mesh of affine quads/hexes.
+
+    Element index e = ex + nx*(ey + ny*ez). Face f = 2k + s: s = 0 is the face at
+    reference coordinate xi_k = -1, s = 1 the face at xi_k = +1. nbr[e, f] is the element
+    across face f (-1 on a non-periodic boundary); the face across from face 2k+1 of e is
+    face 2k of nbr[e, 2k+1].
+    """
+    ndims: int
+    shape: tuple
+    planes: list              # per dim: array of n_k + 1 plane coordinates
+    periodic: tuple
+    x0: np.ndarray            # [E, d] physical image of the reference corner (-1, ..., -1)
+    jac: np.ndarray           # [E, d, d] J[i, j] = dx_i / dxi_j (constant per element)
+    nbr: np.ndarray           # [E, 2d] int32
+    period: np.ndarray        # [d] domain length per dim (used for periodic wrap)
+    shear: float = 0.0
+
+    @property
+    def nelem(self) -> int:
+        return int(np.prod(self.shape))
+
+
+def uniform_planes(n: int, lo: float = 0.0, hi: float = 1.0) -> np.ndarray:
+    return lo + (hi - lo) * np.arange(n + 1, dtype=np.float64) / n
+
+
+def perturbed_planes(n: int, amp_frac: float, rng: np.random.Generator,
+                     lo: float = 0.0, hi: float = 1.0) -> np.ndarray:
+    """Interior planes shifted by U(-amp_frac*h, amp_frac*h); the two end planes fixed."""
+    p = uniform_planes(n, lo, hi)
+    h = (hi - lo) / n
+    p[1:-1] += rng.uniform(-amp_frac * h, amp_frac * h, size=n - 1)
+    return p
+
+
+def box_mesh(planes: Sequence[np.ndarray], periodic: Sequence[bool], shear: float = 0.0) -> BoxMesh:
+    """Build the element maps and adjacency of a box mesh from its grid planes.
+
+    ``shear`` (2D only) maps (x, y) -> (x + shear*y, y); with periodic y the wrap then
+    connects column ex to column ex + shear*nx, so shear*nx must be an integer and the x
+    planes uniform.
+    """
+    d = len(planes)
+    shape = tuple(len(p) - 1 for p in planes)
+    E = int(np.prod(shape))
+    idx = np.arange(E)
+    coords = []
+    rem = idx.copy()
+    for k in range(d):
+        coords.append(rem % shape[k])
+        rem = rem // shape[k]
+    x0 = np.zeros((E, d))
+    jac = np.zeros((E, d, d))
+    for k in range(d):
+        lo = planes[k][coords[k]]
+        hi = planes[k][coords[k] + 1]
+        x0[:, k] = lo
+        jac[:, k, k] = 0.5 * (hi - lo)
+    period = np.array([planes[k][-1] - planes[k][0] for k in range(d)])
+    shift = 0
+    if shear != 0.0:
+        if d != 2:
+            raise ValueError("shear is a 2D option")
+        x0[:, 0] += shear * x0[:, 1]
+        jac[:, 0, 1] = shear * jac[:, 1, 1]
+        nx = shape[0]
+        s = shear * nx * (period[1] / period[0])
+        if periodic[1] and abs(s - round(s)) > 1e-12:
+            raise ValueError("shear*nx must be an integer for a periodic y direction")
+        shift = int(round(s))
+    strides = [int(np.prod(shape[:k])) for k in range(d)]
+    nbr = np.full((E, 2 * d), -1, dtype=np.int32)
+    for k in range(d):
+        for s, step in ((0, -1), (1, 1)):
+            c = coords[k] + step
+            ok = (c >= 0) & (c < shape[k])
+            if periodic[k]:
+                c = c % shape[k]
+                ok = np.ones(E, dtype=bool)
+            e2 = idx + (c - coords[k]) * strides[k]
+            if shear != 0.0 and k == 1 and periodic[1]:
+                # crossing the y wrap moves the column by the shear shift
+                ex = coords[0].copy()
+                wrap_up = (coords[1] + step) >= shape[1]
+                wrap_dn = (coords[1] + step) < 0
+                ex = np.where(wrap_up, (ex + shift) % shape[0], ex)
+                ex = np.where(wrap_dn, (ex - shift) % shape[0], ex)
+                e2 = ex + shape[0] * c
+            nbr[:, 2 * k + s] = np.where(ok, e2, -1).astype(np.int32)
+    return BoxMesh(ndims=d, shape=shape, planes=[np.asarray(p) for p in planes],
+                   periodic=tuple(bool(x) for x in periodic), x0=x0, jac=jac, nbr=nbr,
+                   period=period, shear=shear)
+
+
+# --------------------------------------------------------------------------------------
+# initial condition (§4, Eq. initialCond with the distance of Eq. discEq)
+# --------------------------------------------------------------------------------------
+def signed_distance_ball(x: np.ndarray, centre: Sequence[float], radius: float) -> np.ndarray:
+    """psi_d = r - |x - x_c| (positive inside); x has shape [..., d]."""
+    c = np.asarray(centre, dtype=np.float64)
+    return radius - np.sqrt(np.sum((x - c) ** 2, axis=-1))
+
+
+def tanh_profile(psi_d: np.ndarray, eps_w: float) -> np.ndarray:
+    """phi = (1 + tanh(psi_d / (2 eps_w))) / 2, i.e. Eq. initialCond with beta = 1/(2 eps_w)."""
+    return 0.5 * (1.0 + np.tanh(psi_d / (2.0 * eps_w)))
+
+
+def ic_phi(x: np.ndarray, centre, radius, eps_w) -> np.ndarray:
+    return tanh_profile(signed_distance_ball(x, centre, radius), eps_w)
+
+
+def random_state(shape, rng: np.random.Generator, lo=0.0, hi=1.0) -> np.ndarray:
+    return rng.uniform(lo, hi, size=shape)
+
+
+# --------------------------------------------------------------------------------------
+# parameters and configurations
+# --------------------------------------------------------------------------------------
+@dataclass
+class Params:
+    """Method parameters. Values from §2 (gamma, eps), §3.2 (s0, kappa, nu_max, reset
+    interval N) and §4 (IC sharpness); the rest are readings of silent points."""
+    gamma: float
+    eps: float
+    eps_w: float
+    tau: float = 0.1
+    nu_max: float = 0.0
+    s0: float = -5.0
+    kappa: float = 5.0
+    dtau: float = 0.0
+    delta_n: float = 1e-12
+    delta_g: float = 1e-12
+    delta_phi: float = 1e-12
+    reset_every: int = 1000
+    precond_iters: int = 10
+    reset_mode: int = RESET_LINEAR
+    vel_kind: int = VEL_UNIFORM
+    vel_amp: float = 1.0
+    vel_period: float = 1.0
+    vel_u0: tuple = (0.0, 0.0, 0.0)
+
+
+def default_params(ndims: int, order: int, h: float, *, eps_w: Optional[float] = None,
+                   dtau_coeff: Optional[float] = None, **over) -> Params:
+    """gamma = 0.09, eps = 0.06 h/p (§2); nu_max = 0.15 h/p, s0 = -5 (§3.2);
+    eps_w = 2h/(3p), the width of the IC with beta = 3p/(4h) (§4)."""
+    if dtau_coeff is None:
+        dtau_coeff = {(2, 1): 0.05, (2, 2): 0.04, (2, 3): 0.025, (2, 4): 0.015, (2, 5): 0.01,
+                      (3, 1): 0.04, (3, 2): 0.025, (3, 3): 0.015, (3, 4): 0.010,
+                      (3, 5): 0.007}.get((ndims, order), 0.01)
+    p = Params(gamma=0.09, eps=0.06 * h / order,
+               eps_w=(2.0 * h / (3.0 * order)) if eps_w is None else eps_w,
+               nu_max=0.15 * h / order, dtau=dtau_coeff * h)
+    return replace(p, **over)
+
+
+VMAX = {VEL_UNIFORM: None, VEL_ROTATION: None, VEL_SINGLE_VORTEX: 1.0, VEL_LEVEQUE3D: 2.0}
+
+
+@dataclass
+class Config:
+    name: str
+    ndims: int
+    order: int
+    n: int                       # elements per direction
+    periodic: bool = True
+    perturb: float = 0.0         # interior-plane perturbation as a fraction of h
+    perturb_seed: int = 1
+    centre: tuple = (0.5, 0.5)
+    radius: float = 0.15
+    cfl: float = 0.1
+    steps: int = 200
+    params: Params = None
+    vmax: float = 1.0
+    description: str = ""
+
+    @property
+    def h(self) -> float:
+        return 1.0 / self.n
+
+    @property
+    def nelem(self) -> int:
+        return self.n ** self.ndims
+
+    @property
+    def nupts(self) -> int:
+        return (self.order + 1) ** self.ndims
+
+    @property
+    def dof(self) -> int:
+        return self.nelem * self.nupts
+
+    def mesh(self) -> BoxMesh:
+        rng = np.random.default_rng(self.perturb_seed)
+        planes = []
+        for _ in range(self.ndims):
+            if self.perturb > 0:
+                planes.append(perturbed_planes(self.n, self.perturb, rng))
+            else:
+                planes.append(uniform_planes(self.n))
+        return box_mesh(planes, [self.periodic] * self.ndims)
+
+    def hmin(self, mesh: Optional[BoxMesh] = None) -> float:
+        mesh = mesh or self.mesh()
+        return float(min(np.min(np.diff(p)) for p in mesh.planes))
+
+    def dt(self, mesh: Optional[BoxMesh] = None) -> float:
+        """dt = CFL * h_min / |v|_max (|v|_max the analytic peak of the field)."""
+        return self.cfl * self.hmin(mesh) / self.vmax
+
+
+def _cfg_c1() -> Config:
+    h = 1.0 / 16
+    prm = default_params(2, 3, h, eps_w=h / 4, dtau_coeff=0.025, vel_kind=VEL_UNIFORM,
+                         vel_u0=(1.0, 0.5, 0.0))
+    return Config("advect2d_16x16_p3", 2, 3, 16, centre=(0.5, 0.5), cfl=0.1, steps=200,
+                  params=prm, vmax=math.hypot(1.0, 0.5),
+                  description="2D periodic unit square, 16x16 quads, p=3, uniform velocity "
+                              "(1,0.5), tanh circle r=0.15 at (0.5,0.5), eps_w=h/(p+1), RK4 "
+                              "CFL 0.1, 200 steps")
+
+
+def _cfg_c2() -> Config:
+    h = 1.0 / 128
+    prm = default_params(2, 4, h, dtau_coeff=0.015, vel_kind=VEL_SINGLE_VORTEX,
+                         vel_period=8.0)
+    return Config("vortex2d_128x128_p4", 2, 4, 128, centre=(0.5, 0.75), cfl=0.05,
+                  steps=20480, params=prm, vmax=1.0,
+                  description="2D 128x128 quads, p=4, time-reversing single vortex T=8, "
+                              "circle r=0.15 at (0.5,0.75)")
+
+
+def _cfg_c3() -> Config:
+    h = 1.0 / 64
+    prm = default_params(3, 3, h, dtau_coeff=0.015, vel_kind=VEL_LEVEQUE3D, vel_period=3.0)
+    return Config("deform3d_64cube_p3", 3, 3, 64, centre=(0.35, 0.35, 0.35), cfl=0.05,
+                  steps=100, params=prm, vmax=2.0,
+                  description="3D periodic unit cube, 64^3 hexes, p=3, LeVeque deformation "
+                              "T=3, sphere r=0.15 at (0.35,0.35,0.35), 100 RK4 steps")
+
+
+def _cfg_c4() -> Config:
+    h = 1.0 / 64
+    prm = default_params(2, 3, h, dtau_coeff=0.025, vel_kind=VEL_SINGLE_VORTEX,
+                         vel_period=4.0)
+    return Config("adjoint2d_64x64_p3", 2, 3, 64, centre=(0.5, 0.75), cfl=0.1, steps=512,
+                  params=prm, vmax=1.0,
+                  description="2D 64x64 quads, p=3, single vortex T=4, 512 RK4 steps, "
+                              "checkpoint every 32")
+
+
+def _cfg_c5() -> Config:
+    h = 1.0 / 96
+    prm = default_params(3, 4, h, dtau_coeff=0.010, vel_kind=VEL_LEVEQUE3D, vel_period=3.0)
+    return Config("deform3d_96cube_p4_perturbed", 3, 4, 96, perturb=0.2, perturb_seed=1,
+                  centre=(0.35, 0.35, 0.35), cfl=0.03, steps=100, params=prm, vmax=2.0,
+                  description="3D 96^3 hexes, interior planes perturbed +-20% h, p=4, "
+                              "LeVeque deformation, 100 RK4 steps")
+
+
+CONFIGS = {"C1": _cfg_c1, "C2": _cfg_c2, "C3": _cfg_c3, "C4": _cfg_c4, "C5": _cfg_c5}
+
+
+def config(name: str) -> Config:
+    return CONFIGS[name]()
+
+
+def adjoint_target_centre(cfg: Config, seed: int = 0) -> np.ndarray:
+    """Centre of the target profile of the adjoint workload: the IC centre moved by a
+    seeded U(-2h, 2h) offset per coordinate."""
+    rng = np.random.default_rng(seed)
+    return np.asarray(cfg.centre) + rng.uniform(-2 * cfg.h, 2 * cfg.h, cfg.ndims)
+
+
+def small_case(ndims: int, order: int, shape: Sequence[int], *, vel_kind=VEL_UNIFORM,
+               vel_u0=(1.0, 0.5, 0.25), vel_period=8.0, perturb: float = 0.0,
+               periodic=True, seed: int = 3, shear: float = 0.0, **over):
+    """A small mesh + parameter set for parity tests (non-cubic shapes give ragged
+    element chunks)."""
+    rng = np.random.default_rng(seed)
+    planes = []
+    for n in shape:
+        planes.append(perturbed_planes(n, perturb, rng) if perturb > 0 else uniform_planes(n))
+    per = periodic if isinstance(periodic, (list, tuple)) else [periodic] * ndims
+    mesh = box_mesh(planes, per, shear=shear)
+    h = 1.0 / max(shape)
+    prm = default_params(ndims, order, h, vel_kind=vel_kind, vel_u0=tuple(vel_u0),
+                         vel_period=vel_period, **over)
+    return mesh, prm
