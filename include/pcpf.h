@@ -1,0 +1,201 @@
+/*
+ * pcpf.h -- C ABI of the MI355X (gfx950) FR-PCPF library.
+ *
+ * The library evaluates the Flux Reconstruction (FR) residual of the preconditioned,
+ * localized conservative phase-field system of Al-Salami, Kamra & Hu (arXiv 2006.10967)
+ * on affine quadrilateral / hexahedral tensor-product elements and advances it with the
+ * classic four-stage Runge-Kutta scheme on one GPU:
+ *
+ *   u = [phi, psi],  du/dt + div f(u, grad u) = 0                      (§3.1)
+ *   f = [phi v - max(gamma,|v|) (eps grad phi - gamma phi (1-phi) n); psi v],
+ *   n = grad psi / |grad psi|                                          (§2)
+ *   psi reset to phi - 1/2 every N steps, then preconditioned by pseudo-time iterations of
+ *   dpsi/dtau = div(nu_s grad psi) + sgn(psi0) (1 - |grad psi|)         (§2, §3.2)
+ *
+ * Conventions
+ *   - All functions return pcpf_status; no C++ exception crosses the ABI.
+ *   - "host" pointers point to CPU memory, "d_" pointers to device memory of the GPU that is
+ *     current when pcpf_create is called. Host arrays are copied; the caller may free them
+ *     when the call returns.
+ *   - Work is enqueued on the HIP stream given to pcpf_create (borrowed, not owned) and is
+ *     asynchronous unless stated otherwise.
+ *   - One context may not be used from two threads at once. Identical inputs give bitwise
+ *     identical outputs (no floating-point atomics).
+ *   - Element e, solution point i: i = sum_k i_k n^k over the n = p+1 Gauss-Legendre
+ *     points per direction (i_0 fastest). A per-point field is an array [E][N_u],
+ *     N_u = n^d, in the state type of the context (double for PCPF_FP64, float for
+ *     PCPF_FP32).
+ *   - Face f = 2k + s of an element is the face at reference coordinate xi_k = -1 (s = 0)
+ *     or +1 (s = 1). Face 2k+1 of element e must meet face 2k of nbr[e][2k+1] with the
+ *     tangential reference axes of both faces pointing the same way in space.
+ */
+#ifndef PCPF_H
+#define PCPF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PCPF_ABI_VERSION 1
+#define PCPF_MAX_ORDER 6
+
+typedef enum pcpf_status {
+    PCPF_OK = 0,
+    PCPF_EINVAL = 1,        /* invalid argument: sizes, pointers, parameters, connectivity */
+    PCPF_EDEVICE = 2,       /* a HIP runtime call failed; pcpf_last_error has its message */
+    PCPF_EUNSUPPORTED = 3,  /* valid but not built (e.g. order above the compiled range) */
+    PCPF_ESTATE = 4,        /* call out of order (no state set, ...) */
+    PCPF_ENONFINITE = 5     /* the state became non-finite or |phi| > 10; state kept */
+} pcpf_status;
+
+enum { PCPF_FP64 = 0, PCPF_FP32 = 1 };                       /* precision of the form */
+enum { PCPF_VEL_UNIFORM = 0, PCPF_VEL_ROTATION = 1,           /* analytic velocity kinds */
+       PCPF_VEL_SINGLE_VORTEX = 2, PCPF_VEL_LEVEQUE3D = 3 };
+enum { PCPF_RESET_LINEAR = 0, PCPF_RESET_LOGIT = 1 };         /* psi reset transform */
+enum { PCPF_MODE_PHYS = 0, PCPF_MODE_PRECOND = 1 };           /* residual kind */
+enum { PCPF_REDUCE_MASS = 0, PCPF_REDUCE_L1 = 1 };            /* FP64 reductions */
+
+/* Mesh and FR operators (host memory, float64, row-major). */
+typedef struct pcpf_mesh {
+    int32_t ndims;           /* d: 2 (quads) or 3 (hexes) */
+    int32_t order;           /* p: 1..PCPF_MAX_ORDER (3D: 1..5); n = p + 1 */
+    int64_t nelem;           /* E >= 1 */
+    /* 1D factors of the tensor-product element (§3.1, Steps 1, 3 and 6) */
+    const double* nodes;     /* [n]   solution points xi_a on [-1, 1], ascending */
+    const double* weights;   /* [n]   quadrature weights w_a of the nodes */
+    const double* deriv;     /* [n*n] deriv[a*n + b] = l_b'(xi_a) (nodal derivative) */
+    const double* lminus;    /* [n]   l_a(-1): interpolation to the xi = -1 end */
+    const double* lplus;     /* [n]   l_a(+1): interpolation to the xi = +1 end */
+    const double* cminus;    /* [n]   divergence of the correction function of the
+                                      xi = -1 end at node a (DG: l_a(-1)/w_a) */
+    const double* cplus;     /* [n]   same for the xi = +1 end (DG: l_a(+1)/w_a) */
+    const double* vinv;      /* [n*n] vinv[j*n + a]: coefficient j of the orthonormal
+                                      Legendre expansion from nodal values (sensor, §3.2) */
+    /* affine geometry: x = x0 + J (xi + 1) */
+    const double* x0;        /* [E*d]   image of the reference corner (-1, ..., -1) */
+    const double* jac;       /* [E*d*d] J[i][j] = dx_i / dxi_j, det J > 0 */
+    const int32_t* nbr;      /* [E*2d]  element across face f, -1 = boundary (ghost state
+                                        equal to the interior state, §3.3) */
+    double period[3];        /* domain period along each physical axis (0 = not periodic):
+                                paired face points must coincide up to a translation by
+                                integer multiples of these periods */
+} pcpf_mesh;
+
+/* Method parameters (§2, §3.2, §4). */
+typedef struct pcpf_params {
+    double gamma;        /* sharpening weight and floor of |v| in max(gamma, |v|) (0.09) */
+    double eps;          /* interface diffusion eps (0.06 h / p) */
+    double eps_w;        /* width of the tanh kernel, used by the LOGIT reset */
+    double tau;          /* LDG jump penalty, dissipative sign (0.1) */
+    double nu_max;       /* maximum artificial viscosity (0.15 h / p) */
+    double s0;           /* sensor threshold (-5) */
+    double kappa;        /* sensor ramp half width (5) */
+    double dtau;         /* pseudo-time step of the preconditioning iterations */
+    double delta_n;      /* |grad psi| regularisation of the normal (1e-12) */
+    double delta_g;      /* floor of |grad psi0| in the smeared sign (1e-12) */
+    double delta_phi;    /* clamp of phi in the LOGIT reset (1e-12) */
+    double vel_amp;      /* velocity amplitude A: v = A v0(x) g(t) */
+    double vel_period;   /* T in g(t) = cos(pi t / T) (vortex and LeVeque kinds) */
+    double vel_u0[3];    /* constant velocity of PCPF_VEL_UNIFORM */
+    int32_t vel_kind;    /* PCPF_VEL_* */
+    int32_t reset_mode;  /* PCPF_RESET_* */
+    int32_t reset_every; /* reset + precondition before steps with index % N == 0 (0: never) */
+    int32_t precond_iters; /* pseudo-time RK4 iterations per reset (>= 0) */
+    int32_t precision;   /* PCPF_FP64 or PCPF_FP32 */
+    int32_t reserved[3]; /* must be 0 */
+} pcpf_params;
+
+typedef struct pcpf_ctx pcpf_ctx;
+
+/* ABI version of the loaded library (PCPF_ABI_VERSION of its build). */
+int pcpf_abi_version(void);
+
+/* Message of the last failure of ctx, or of the calling thread's last failed call
+ * when ctx is NULL (e.g. a failed pcpf_create). Never NULL; owned by the library. */
+const char* pcpf_last_error(const pcpf_ctx* ctx);
+
+/* --- host helpers (no GPU needed) -------------------------------------------------- */
+
+/* 1D operators of the order-p Gauss-Legendre nodal element with DG (Radau) correction
+ * functions (§3.1: Gauss-Legendre solution points, nodal basis from a Legendre
+ * Vandermonde matrix). Each output is caller-owned host memory of the size given in
+ * pcpf_mesh. EINVAL if order is outside 1..PCPF_MAX_ORDER or a pointer is NULL. */
+pcpf_status pcpf_line_operators(int32_t order, double* nodes, double* weights,
+                                double* deriv, double* lminus, double* lplus,
+                                double* cminus, double* cplus, double* vinv);
+
+/* Physical coordinates of every solution point, xs[(e*N_u + i)*d + k] (host, float64,
+ * caller-owned, E*N_u*d values). EINVAL on a malformed mesh. */
+pcpf_status pcpf_solution_coords(const pcpf_mesh* mesh, double* xs);
+
+/* --- context ------------------------------------------------------------------------ */
+
+/* Device workspace bytes a context needs for this mesh and form. */
+pcpf_status pcpf_workspace_bytes(const pcpf_mesh* mesh, const pcpf_params* params,
+                                 size_t* nbytes);
+
+/* Validate mesh and parameters (sizes, det J > 0, reciprocal adjacency, matching face
+ * points up to a translation), copy them to the device and create a context.
+ * d_ws: caller-owned device memory of at least pcpf_workspace_bytes bytes, 256-byte
+ * aligned, which must outlive the context. stream: a hipStream_t (NULL = default).
+ * EINVAL, EUNSUPPORTED, EDEVICE. */
+pcpf_status pcpf_create(const pcpf_mesh* mesh, const pcpf_params* params, void* d_ws,
+                        size_t ws_bytes, void* stream, pcpf_ctx** out);
+
+/* Free the host-side context (the workspace stays with the caller). NULL is a no-op. */
+void pcpf_destroy(pcpf_ctx* ctx);
+
+/* Number of solution points per element and of elements. */
+pcpf_status pcpf_sizes(const pcpf_ctx* ctx, int64_t* nelem, int32_t* nupts);
+
+/* Set the state from device arrays [E][N_u] (state type). d_psi == NULL forces a reset +
+ * preconditioning before the next step. t is the physical time, step the index of the
+ * next step (resets happen before steps with step % reset_every == 0). */
+pcpf_status pcpf_set_state(pcpf_ctx* ctx, const void* d_phi, const void* d_psi, double t,
+                           int64_t step);
+
+/* Copy the state out (either output may be NULL). Synchronous for t and step only. */
+pcpf_status pcpf_get_state(pcpf_ctx* ctx, void* d_phi, void* d_psi, double* t,
+                           int64_t* step);
+
+/* Advance nsteps classic RK4 steps of size dt (§3.1 last paragraph), with the reset +
+ * preconditioning of §2/§3.2 before each step whose index is a multiple of reset_every.
+ * Synchronises the stream once at the end to read the non-finite flag: ENONFINITE if any
+ * value became NaN/Inf or |phi| > 10 (the state is kept for inspection). */
+pcpf_status pcpf_step(pcpf_ctx* ctx, double dt, int64_t nsteps);
+
+/* Reset psi from the current phi (psi0 = phi - 1/2, or eps_w ln(phi/(1-phi)) with the
+ * LOGIT mode, always in float64), compute the smeared sign tanh(psi0/max(|grad psi0|,
+ * delta_g)) and run iters pseudo-time RK4 iterations (iters < 0: params.precond_iters).
+ * phi is not changed. */
+pcpf_status pcpf_precondition(pcpf_ctx* ctx, int32_t iters);
+
+/* One residual evaluation (the parity entry point). PCPF_MODE_PHYS: d/dt of (phi, psi)
+ * at time t from d_phi, d_psi into d_rphi, d_rpsi. PCPF_MODE_PRECOND: d/dtau of psi from
+ * d_psi using the smeared sign of the last reset (d_phi, d_rphi ignored, may be NULL).
+ * Inputs and outputs are [E][N_u] in the state type; outputs may not alias inputs.
+ * Uses the context's scratch registers: the stored state is not changed. */
+pcpf_status pcpf_residual(pcpf_ctx* ctx, const void* d_phi, const void* d_psi, double t,
+                          int32_t mode, void* d_rphi, void* d_rpsi);
+
+/* Smeared sign of the last reset, [E][N_u] in the state type. ESTATE before a reset. */
+pcpf_status pcpf_get_sign(pcpf_ctx* ctx, void* d_sgn);
+
+/* Persson-Peraire element viscosity nu_s (§3.2, Eqs. resolutionIndicator and nu_s) of the
+ * field d_psi [E][N_u] into d_nu [E] (state type). */
+pcpf_status pcpf_sensor(pcpf_ctx* ctx, const void* d_psi, void* d_nu);
+
+/* FP64 reductions with the element quadrature |J| W (§4 error measures):
+ * PCPF_REDUCE_MASS: integral of d_field (NULL: the stored phi);
+ * PCPF_REDUCE_L1:   integral of |d_field - d_ref| (d_field NULL: the stored phi).
+ * Deterministic two-pass reduction; synchronous (8 bytes device to host). */
+pcpf_status pcpf_reduce(pcpf_ctx* ctx, int32_t what, const void* d_field,
+                        const void* d_ref, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PCPF_H */

@@ -1,0 +1,880 @@
+// C-ABI of the FR-PCPF library: validation, workspace layout, the step loop, and the host
+// builders of the 1D Gauss-Legendre element.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pcpf_internal.h"
+
+using namespace pcpf;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+pcpf_status fail(std::string* dst, pcpf_status st, const std::string& msg) {
+    if (dst) *dst = msg;
+    g_err = msg;
+    return st;
+}
+
+// ------------------------------------------------------------------------------------
+// 1D Gauss-Legendre element (host, float64)
+// ------------------------------------------------------------------------------------
+// Legendre P_n and P_n' by the three-term recurrence.
+void legendre(int n, double x, double* p, double* dp) {
+    double p0 = 1.0, p1 = x;
+    if (n == 0) {
+        *p = 1.0;
+        *dp = 0.0;
+        return;
+    }
+    for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+    }
+    *p = p1;
+    *dp = n * (x * p1 - p0) / (x * x - 1.0);
+}
+
+// Gauss-Legendre nodes (ascending) and weights by Newton iteration on P_n.
+void gauss_legendre(int n, double* x, double* w) {
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        for (int it = 0; it < 100; ++it) {
+            double p, dp;
+            legendre(n, z, &p, &dp);
+            const double dz = p / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-17) break;
+        }
+        double p, dp;
+        legendre(n, z, &p, &dp);
+        const double wi = 2.0 / ((1.0 - z * z) * dp * dp);
+        x[i] = -z;
+        x[n - 1 - i] = z;
+        w[i] = wi;
+        w[n - 1 - i] = wi;
+    }
+    if (n % 2 == 1) x[n / 2] = 0.0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pcpf_abi_version(void) { return PCPF_ABI_VERSION; }
+
+pcpf_status pcpf_line_operators(int32_t order, double* nodes, double* weights, double* deriv,
+                                double* lminus, double* lplus, double* cminus, double* cplus,
+                                double* vinv) {
+    if (order < 1 || order > PCPF_MAX_ORDER)
+        return fail(nullptr, PCPF_EINVAL, "pcpf_line_operators: order out of range");
+    if (!nodes || !weights || !deriv || !lminus || !lplus || !cminus || !cplus || !vinv)
+        return fail(nullptr, PCPF_EINVAL, "pcpf_line_operators: null output");
+    const int n = order + 1;
+    gauss_legendre(n, nodes, weights);
+    // barycentric weights lambda_b = 1 / prod_{c != b} (xi_b - xi_c)
+    std::vector<double> lam(n);
+    for (int b = 0; b < n; ++b) {
+        double pr = 1.0;
+        for (int c = 0; c < n; ++c)
+            if (c != b) pr *= nodes[b] - nodes[c];
+        lam[b] = 1.0 / pr;
+    }
+    // derivative matrix of the Lagrange basis at the nodes (barycentric form)
+    for (int a = 0; a < n; ++a) {
+        double diag = 0.0;
+        for (int b = 0; b < n; ++b) {
+            if (a == b) continue;
+            const double v = (lam[b] / lam[a]) / (nodes[a] - nodes[b]);
+            deriv[a * n + b] = v;
+            diag -= v;
+        }
+        deriv[a * n + a] = diag;
+    }
+    // end values l_b(+-1) (barycentric interpolation)
+    for (int s = 0; s < 2; ++s) {
+        const double xe = s ? 1.0 : -1.0;
+        double den = 0.0;
+        for (int c = 0; c < n; ++c) den += lam[c] / (xe - nodes[c]);
+        double* out = s ? lplus : lminus;
+        for (int b = 0; b < n; ++b) out[b] = (lam[b] / (xe - nodes[b])) / den;
+    }
+    // DG correction functions: their derivatives at Gauss-Legendre nodes are l(+-1)/w
+    for (int a = 0; a < n; ++a) {
+        cminus[a] = lminus[a] / weights[a];
+        cplus[a] = lplus[a] / weights[a];
+    }
+    // modal coefficients of the orthonormal Legendre basis: Gauss-Legendre quadrature is
+    // exact for the degree-2p products, so chi_j = sum_a w_a Psi_j(xi_a) u_a
+    for (int j = 0; j < n; ++j) {
+        for (int a = 0; a < n; ++a) {
+            double p, dp;
+            legendre(j, nodes[a], &p, &dp);
+            vinv[j * n + a] = weights[a] * std::sqrt((2.0 * j + 1.0) / 2.0) * p;
+        }
+    }
+    return PCPF_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct MeshInfo {
+    int d, p, n, nu, nfa;
+    int64_t E;
+};
+
+pcpf_status check_mesh(const pcpf_mesh* m, MeshInfo* mi, std::string* err) {
+    if (!m) return fail(err, PCPF_EINVAL, "mesh is NULL");
+    if (m->ndims != 2 && m->ndims != 3) return fail(err, PCPF_EINVAL, "ndims must be 2 or 3");
+    const int pmax = m->ndims == 2 ? PCPF_MAX_ORDER : 5;
+    if (m->order < 1 || m->order > PCPF_MAX_ORDER)
+        return fail(err, PCPF_EINVAL, "order out of range 1..6");
+    if (m->order > pmax) return fail(err, PCPF_EUNSUPPORTED, "3D orders above 5 are not built");
+    if (m->nelem < 1) return fail(err, PCPF_EINVAL, "nelem must be >= 1");
+    if (m->nelem > (int64_t)1 << 31) return fail(err, PCPF_EINVAL, "nelem above 2^31");
+    if (!m->nodes || !m->weights || !m->deriv || !m->lminus || !m->lplus || !m->cminus ||
+        !m->cplus || !m->vinv || !m->x0 || !m->jac || !m->nbr)
+        return fail(err, PCPF_EINVAL, "mesh has a NULL array");
+    mi->d = m->ndims;
+    mi->p = m->order;
+    mi->n = m->order + 1;
+    mi->nu = ipow(mi->n, mi->d);
+    mi->nfa = ipow(mi->n, mi->d - 1);
+    mi->E = m->nelem;
+    return PCPF_OK;
+}
+
+void inv_det(int d, const double* J, double* Ji, double* det) {
+    if (d == 2) {
+        const double dt = J[0] * J[3] - J[1] * J[2];
+        Ji[0] = J[3] / dt;
+        Ji[1] = -J[1] / dt;
+        Ji[2] = -J[2] / dt;
+        Ji[3] = J[0] / dt;
+        *det = dt;
+    } else {
+        const double a = J[0], b = J[1], c = J[2], dd = J[3], e = J[4], f = J[5], g = J[6],
+                     h = J[7], i = J[8];
+        const double A = e * i - f * h, B = -(dd * i - f * g), C = dd * h - e * g;
+        const double dt = a * A + b * B + c * C;
+        Ji[0] = A / dt;
+        Ji[1] = -(b * i - c * h) / dt;
+        Ji[2] = (b * f - c * e) / dt;
+        Ji[3] = B / dt;
+        Ji[4] = (a * i - c * g) / dt;
+        Ji[5] = -(a * f - c * dd) / dt;
+        Ji[6] = C / dt;
+        Ji[7] = -(a * h - b * g) / dt;
+        Ji[8] = (a * e - b * dd) / dt;
+        *det = dt;
+    }
+}
+
+// Physical coordinates of point ref (reference coords) of element e.
+void map_point(int d, const double* x0, const double* J, const double* ref, double* x) {
+    for (int i = 0; i < d; ++i) {
+        double acc = x0[i];
+        for (int j = 0; j < d; ++j) acc += J[i * d + j] * (ref[j] + 1.0);
+        x[i] = acc;
+    }
+}
+
+// Reciprocal adjacency, det J > 0, and paired face points equal up to one translation.
+pcpf_status check_geometry(const pcpf_mesh* m, const MeshInfo& mi, std::string* err) {
+    const int d = mi.d, n = mi.n, nfa = mi.nfa;
+    const int64_t E = mi.E;
+    std::vector<double> ji(d * d);
+    double hmin = 1e300;
+    for (int64_t e = 0; e < E; ++e) {
+        double det;
+        inv_det(d, m->jac + e * d * d, ji.data(), &det);
+        if (!(det > 0.0)) return fail(err, PCPF_EINVAL, "element with det J <= 0");
+        hmin = std::min(hmin, std::pow(det, 1.0 / d));
+        for (int f = 0; f < 2 * d; ++f) {
+            const int32_t en = m->nbr[e * 2 * d + f];
+            if (en < -1 || en >= E) return fail(err, PCPF_EINVAL, "nbr index out of range");
+            if (en >= 0 && m->nbr[(int64_t)en * 2 * d + (f ^ 1)] != e)
+                return fail(err, PCPF_EINVAL, "adjacency is not reciprocal (face 2k+1 of e must "
+                                              "meet face 2k of nbr[e][2k+1])");
+        }
+    }
+    const double tol = 1e-8 * hmin;
+    std::vector<double> ra(d), rb(d), xa(d), xb(d);
+    for (int q = 0; q < d; ++q)
+        if (!(m->period[q] >= 0.0)) return fail(err, PCPF_EINVAL, "period must be >= 0");
+    for (int64_t e = 0; e < E; ++e) {
+        for (int k = 0; k < d; ++k) {
+            const int32_t en = m->nbr[e * 2 * d + 2 * k + 1];
+            if (en < 0) continue;
+            for (int t = 0; t < nfa; ++t) {
+                int tt = t;
+                for (int q = 0; q < d; ++q) {
+                    if (q == k) {
+                        ra[q] = 1.0;
+                        rb[q] = -1.0;
+                    } else {
+                        ra[q] = rb[q] = m->nodes[tt % n];
+                        tt /= n;
+                    }
+                }
+                map_point(d, m->x0 + e * d, m->jac + e * d * d, ra.data(), xa.data());
+                map_point(d, m->x0 + (int64_t)en * d, m->jac + (int64_t)en * d * d, rb.data(),
+                          xb.data());
+                for (int q = 0; q < d; ++q) {
+                    double dq = xb[q] - xa[q];
+                    if (m->period[q] > 0.0) dq -= std::round(dq / m->period[q]) * m->period[q];
+                    if (std::fabs(dq) > tol)
+                        return fail(err, PCPF_EINVAL,
+                                    "face points of neighbouring elements do not coincide "
+                                    "(up to the periods)");
+                }
+            }
+        }
+    }
+    return PCPF_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+    size_t un, us, acc, P, Fp, Fbm, Tm, sgn, geo, det64, w64, nbr, ops, flag, partial, red, res;
+    size_t total;
+};
+
+Layout layout(const MeshInfo& mi, int precision) {
+    const size_t r = precision == PCPF_FP32 ? 4 : 8;
+    const size_t E = (size_t)mi.E;
+    const size_t state = 2 * E * mi.nu * r;              // two variables
+    const size_t face = 2 * E * mi.d * mi.nfa * r;
+    const int geo = mi.d + 2 * mi.d * mi.d + 1;
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    L.un = take(state);
+    L.us = take(state);
+    L.acc = take(state);
+    L.P = take(state);
+    L.Fp = take(face);
+    L.Fbm = take(face);
+    L.Tm = take(face);
+    L.sgn = take(E * mi.nu * r);
+    L.geo = take(E * geo * r);
+    L.det64 = take(E * 8);
+    L.w64 = take(mi.n * 8);
+    L.nbr = take(E * 2 * mi.d * 4);
+    L.ops = take(ops_size(mi.n) * r);
+    L.flag = take(4);
+    L.partial = take(REDUCE_BLOCKS * 8);
+    L.red = take(8);
+    L.res = take(state);   // scratch residual / sensor output of the residual entry point
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------
+// context
+// ------------------------------------------------------------------------------------
+struct pcpf_ctx {
+    MeshInfo mi;
+    pcpf_params prm;
+    hipStream_t stream = nullptr;
+    char* ws = nullptr;
+    Layout L;
+    Launchers<double> L64;
+    Launchers<float> L32;
+    double t = 0.0;
+    int64_t step = 0;
+    bool has_state = false, has_psi = false, has_sign = false;
+    bool trace_ok[2] = {false, false};
+    std::string err = "no error";
+};
+
+namespace {
+
+template <typename R>
+struct Ctx {
+    pcpf_ctx* c;
+    R* plane(size_t off, int v) const {
+        return reinterpret_cast<R*>(c->ws + off) + (size_t)v * c->mi.E * c->mi.nu;
+    }
+    R* fplane(size_t off, int v) const {
+        return reinterpret_cast<R*>(c->ws + off) + (size_t)v * c->mi.E * c->mi.d * c->mi.nfa;
+    }
+    template <typename T>
+    T* at(size_t off) const {
+        return reinterpret_cast<T*>(c->ws + off);
+    }
+    const Launchers<R>& Lk() const;
+};
+template <>
+const Launchers<double>& Ctx<double>::Lk() const { return c->L64; }
+template <>
+const Launchers<float>& Ctx<float>::Lk() const { return c->L32; }
+
+pcpf_status hip_check(pcpf_ctx* c, hipError_t e, const char* what) {
+    if (e == hipSuccess) return PCPF_OK;
+    std::string msg = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(c ? &c->err : nullptr, PCPF_EDEVICE, msg);
+}
+
+#define HIPCHK(ctx, call)                                          \
+    do {                                                           \
+        pcpf_status _s = hip_check((ctx), (call), #call);          \
+        if (_s != PCPF_OK) return _s;                              \
+    } while (0)
+
+double time_factor(const pcpf_params& p, double t) {
+    if (p.vel_kind == PCPF_VEL_SINGLE_VORTEX || p.vel_kind == PCPF_VEL_LEVEQUE3D)
+        return std::cos(M_PI * t / p.vel_period);
+    return 1.0;
+}
+
+template <typename R>
+Phys<R> phys(const pcpf_params& p, double t) {
+    Phys<R> ph;
+    ph.gamma = (R)p.gamma;
+    ph.eps = (R)p.eps;
+    ph.tau = (R)p.tau;
+    ph.delta_n = (R)p.delta_n;
+    ph.delta_g = (R)p.delta_g;
+    ph.nu_max = (R)p.nu_max;
+    ph.s0 = (R)p.s0;
+    ph.kappa = (R)p.kappa;
+    ph.ampg = (R)(p.vel_amp * time_factor(p, t));
+    for (int k = 0; k < 3; ++k) ph.u0[k] = (R)p.vel_u0[k];
+    ph.vel_kind = p.vel_kind;
+    return ph;
+}
+
+template <typename R>
+GFArgs<R> gf_args(const Ctx<R>& C, const R* u0, const R* u1, double t) {
+    pcpf_ctx* c = C.c;
+    GFArgs<R> a{};
+    a.u[0] = u0;
+    a.u[1] = u1;
+    for (int v = 0; v < 2; ++v) {
+        a.P[v] = C.plane(c->L.P, v);
+        a.Fp[v] = C.fplane(c->L.Fp, v);
+        a.Fbm[v] = C.fplane(c->L.Fbm, v);
+        a.Tm[v] = C.fplane(c->L.Tm, v);
+    }
+    a.geo = C.template at<R>(c->L.geo);
+    a.nbr = C.template at<int32_t>(c->L.nbr);
+    a.ops = C.template at<R>(c->L.ops);
+    a.sgn = C.template at<R>(c->L.sgn);
+    a.out = nullptr;
+    a.E = c->mi.E;
+    a.ph = phys<R>(c->prm, t);
+    return a;
+}
+
+// select the psi plane (index 1) of every two-variable buffer for the one-variable modes
+template <typename R>
+void psi_only(GFArgs<R>& a) {
+    a.u[0] = a.u[1];
+    a.P[0] = a.P[1];
+    a.Fp[0] = a.Fp[1];
+    a.Fbm[0] = a.Fbm[1];
+    a.Tm[0] = a.Tm[1];
+}
+
+template <typename R>
+UPArgs<R> up_args(const Ctx<R>& C) {
+    pcpf_ctx* c = C.c;
+    UPArgs<R> a{};
+    for (int v = 0; v < 2; ++v) {
+        a.P[v] = C.plane(c->L.P, v);
+        a.Fp[v] = C.fplane(c->L.Fp, v);
+        a.Fbm[v] = C.fplane(c->L.Fbm, v);
+        a.un[v] = C.plane(c->L.un, v);
+        a.acc[v] = C.plane(c->L.acc, v);
+        a.us[v] = C.plane(c->L.us, v);
+        a.res[v] = nullptr;
+        a.Tm[v] = C.fplane(c->L.Tm, v);
+    }
+    a.geo = C.template at<R>(c->L.geo);
+    a.nbr = C.template at<int32_t>(c->L.nbr);
+    a.ops = C.template at<R>(c->L.ops);
+    a.flag = C.template at<int>(c->L.flag);
+    a.E = c->mi.E;
+    return a;
+}
+
+template <typename R>
+void up_psi_only(UPArgs<R>& a) {
+    a.P[0] = a.P[1];
+    a.Fp[0] = a.Fp[1];
+    a.Fbm[0] = a.Fbm[1];
+    a.un[0] = a.un[1];
+    a.acc[0] = a.acc[1];
+    a.us[0] = a.us[1];
+    a.Tm[0] = a.Tm[1];
+}
+
+template <typename R>
+pcpf_status launch_status(pcpf_ctx* c) {
+    return hip_check(c, hipGetLastError(), "kernel launch");
+}
+
+// - face traces of the stored state for the variables whose traces are stale
+template <typename R>
+pcpf_status refresh_traces(const Ctx<R>& C) {
+    pcpf_ctx* c = C.c;
+    if (c->trace_ok[0] && c->trace_ok[1]) return PCPF_OK;
+    TRArgs<R> a{};
+    int nv = 0;
+    for (int v = 0; v < 2; ++v) {
+        if (c->trace_ok[v]) continue;
+        a.u[nv] = C.plane(c->L.un, v);
+        a.Tm[nv] = C.fplane(c->L.Tm, v);
+        ++nv;
+    }
+    a.ops = C.template at<R>(c->L.ops);
+    a.E = c->mi.E;
+    C.Lk().trace(nv, a, c->stream);
+    c->trace_ok[0] = c->trace_ok[1] = true;
+    return launch_status<R>(c);
+}
+
+// classic RK4 stage constants
+constexpr double RK_B[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+constexpr double RK_C[4] = {0.0, 0.5, 0.5, 1.0};
+
+template <typename R>
+pcpf_status precondition_impl(const Ctx<R>& C, int iters) {
+    pcpf_ctx* c = C.c;
+    const int64_t n = c->mi.E * c->mi.nu;
+    R* phi = C.plane(c->L.un, 0);
+    R* psi = C.plane(c->L.un, 1);
+    launch_reset<R>(phi, psi, n, c->prm.reset_mode, c->prm.eps_w, c->prm.delta_phi, c->stream);
+    // traces of psi0
+    {
+        TRArgs<R> a{};
+        a.u[0] = psi;
+        a.Tm[0] = C.fplane(c->L.Tm, 1);
+        a.ops = C.template at<R>(c->L.ops);
+        a.E = c->mi.E;
+        C.Lk().trace(1, a, c->stream);
+    }
+    // smeared sign
+    {
+        GFArgs<R> a = gf_args<R>(C, phi, psi, c->t);
+        psi_only(a);
+        a.out = C.template at<R>(c->L.sgn);
+        C.Lk().grad_flux(GF_SIGN, 1, a, c->stream);
+    }
+    c->has_sign = true;
+    c->has_psi = true;
+    const double dtau = c->prm.dtau;
+    for (int it = 0; it < iters; ++it) {
+        for (int s = 0; s < 4; ++s) {
+            const R* uin = s == 0 ? psi : C.plane(c->L.us, 1);
+            GFArgs<R> g = gf_args<R>(C, uin, uin, c->t);
+            psi_only(g);
+            g.u[0] = uin;
+            C.Lk().grad_flux(GF_PRECOND, 1, g, c->stream);
+            UPArgs<R> u = up_args<R>(C);
+            up_psi_only(u);
+            u.first = s == 0;
+            u.last = s == 3;
+            u.bcoef = (R)RK_B[s];
+            u.ccoef = (R)(s == 3 ? dtau : RK_C[s + 1] * dtau);
+            C.Lk().update(UP_RK, 1, u, c->stream);
+        }
+    }
+    c->trace_ok[1] = iters > 0;
+    if (iters == 0) c->trace_ok[1] = true;   // traces of psi0 were written above
+    return launch_status<R>(c);
+}
+
+template <typename R>
+pcpf_status step_impl(const Ctx<R>& C, double dt, int64_t nsteps) {
+    pcpf_ctx* c = C.c;
+    HIPCHK(c, hipMemsetAsync(C.template at<int>(c->L.flag), 0, sizeof(int), c->stream));
+    for (int64_t i = 0; i < nsteps; ++i) {
+        const int N = c->prm.reset_every;
+        if (!c->has_psi || (N > 0 && c->step % N == 0)) {
+            pcpf_status st = precondition_impl<R>(C, c->prm.precond_iters);
+            if (st != PCPF_OK) return st;
+        }
+        pcpf_status st = refresh_traces<R>(C);
+        if (st != PCPF_OK) return st;
+        for (int s = 0; s < 4; ++s) {
+            const double ts = c->t + RK_C[s] * dt;
+            const R* u0 = s == 0 ? C.plane(c->L.un, 0) : C.plane(c->L.us, 0);
+            const R* u1 = s == 0 ? C.plane(c->L.un, 1) : C.plane(c->L.us, 1);
+            GFArgs<R> g = gf_args<R>(C, u0, u1, ts);
+            C.Lk().grad_flux(GF_PHYS, 2, g, c->stream);
+            UPArgs<R> u = up_args<R>(C);
+            u.first = s == 0;
+            u.last = s == 3;
+            u.bcoef = (R)RK_B[s];
+            u.ccoef = (R)(s == 3 ? dt : RK_C[s + 1] * dt);
+            C.Lk().update(UP_RK, 2, u, c->stream);
+        }
+        c->t += dt;
+        c->step += 1;
+    }
+    pcpf_status st = launch_status<R>(c);
+    if (st != PCPF_OK) return st;
+    int flag = 0;
+    HIPCHK(c, hipMemcpyAsync(&flag, C.template at<int>(c->L.flag), sizeof(int),
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (flag) return fail(&c->err, PCPF_ENONFINITE, "state became non-finite or |phi| > 10");
+    return PCPF_OK;
+}
+
+template <typename R>
+pcpf_status residual_impl(const Ctx<R>& C, const void* d_phi, const void* d_psi, double t,
+                          int mode, void* d_rphi, void* d_rpsi) {
+    pcpf_ctx* c = C.c;
+    const R* phi = static_cast<const R*>(d_phi);
+    const R* psi = static_cast<const R*>(d_psi);
+    if (mode == PCPF_MODE_PHYS) {
+        TRArgs<R> tr{};
+        tr.u[0] = phi;
+        tr.u[1] = psi;
+        tr.Tm[0] = C.fplane(c->L.Tm, 0);
+        tr.Tm[1] = C.fplane(c->L.Tm, 1);
+        tr.ops = C.template at<R>(c->L.ops);
+        tr.E = c->mi.E;
+        C.Lk().trace(2, tr, c->stream);
+        GFArgs<R> g = gf_args<R>(C, phi, psi, t);
+        C.Lk().grad_flux(GF_PHYS, 2, g, c->stream);
+        UPArgs<R> u = up_args<R>(C);
+        u.res[0] = static_cast<R*>(d_rphi);
+        u.res[1] = static_cast<R*>(d_rpsi);
+        C.Lk().update(UP_RESID, 2, u, c->stream);
+        c->trace_ok[0] = c->trace_ok[1] = false;
+    } else {
+        TRArgs<R> tr{};
+        tr.u[0] = psi;
+        tr.Tm[0] = C.fplane(c->L.Tm, 1);
+        tr.ops = C.template at<R>(c->L.ops);
+        tr.E = c->mi.E;
+        C.Lk().trace(1, tr, c->stream);
+        GFArgs<R> g = gf_args<R>(C, psi, psi, t);
+        psi_only(g);
+        g.u[0] = psi;
+        C.Lk().grad_flux(GF_PRECOND, 1, g, c->stream);
+        UPArgs<R> u = up_args<R>(C);
+        up_psi_only(u);
+        u.res[0] = static_cast<R*>(d_rpsi);
+        C.Lk().update(UP_RESID, 1, u, c->stream);
+        c->trace_ok[1] = false;
+    }
+    return launch_status<R>(c);
+}
+
+template <typename R>
+pcpf_status sensor_impl(const Ctx<R>& C, const void* d_psi, void* d_nu) {
+    pcpf_ctx* c = C.c;
+    GFArgs<R> g = gf_args<R>(C, static_cast<const R*>(d_psi), static_cast<const R*>(d_psi),
+                             c->t);
+    g.out = static_cast<R*>(d_nu);
+    C.Lk().grad_flux(GF_SENSOR, 1, g, c->stream);
+    return launch_status<R>(c);
+}
+
+template <typename R>
+pcpf_status reduce_impl(const Ctx<R>& C, int what, const void* d_field, const void* d_ref,
+                        double* out) {
+    pcpf_ctx* c = C.c;
+    RDArgs<R> a{};
+    a.field = d_field ? static_cast<const R*>(d_field) : C.plane(c->L.un, 0);
+    a.ref = static_cast<const R*>(d_ref);
+    a.det64 = C.template at<double>(c->L.det64);
+    a.w64 = C.template at<double>(c->L.w64);
+    a.partial = C.template at<double>(c->L.partial);
+    a.E = c->mi.E;
+    a.kind = what;
+    const int64_t total = c->mi.E * c->mi.nu;
+    int nb = (int)std::min<int64_t>(REDUCE_BLOCKS, (total + REDUCE_THREADS - 1) / REDUCE_THREADS);
+    if (nb < 1) nb = 1;
+    C.Lk().reduce(a, nb, c->stream);
+    double* red = C.template at<double>(c->L.red);
+    launch_reduce_final(a.partial, nb, red, c->stream);
+    pcpf_status st = launch_status<R>(c);
+    if (st != PCPF_OK) return st;
+    HIPCHK(c, hipMemcpyAsync(out, red, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PCPF_OK;
+}
+
+template <typename R>
+pcpf_status upload(pcpf_ctx* c, const pcpf_mesh* m) {
+    const MeshInfo& mi = c->mi;
+    const int d = mi.d, n = mi.n;
+    const int G = d + 2 * d * d + 1;
+    const int64_t E = mi.E;
+    std::vector<R> geo((size_t)E * G);
+    std::vector<double> det64(E);
+    std::vector<double> ji(d * d);
+    for (int64_t e = 0; e < E; ++e) {
+        double det;
+        const double* J = m->jac + e * d * d;
+        inv_det(d, J, ji.data(), &det);
+        R* g = geo.data() + e * G;
+        for (int k = 0; k < d; ++k) g[k] = (R)m->x0[e * d + k];
+        for (int k = 0; k < d * d; ++k) g[d + k] = (R)J[k];
+        for (int k = 0; k < d * d; ++k) g[d + d * d + k] = (R)ji[k];
+        g[d + 2 * d * d] = (R)det;
+        det64[e] = det;
+    }
+    // operator block: D1, DH = D1 - cp (x) lp + cm (x) lm, VINV, lm, lp, cm, cp, xi, w
+    std::vector<R> ops(ops_size(n));
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) {
+            const double d1 = m->deriv[a * n + b];
+            ops[OP_D1 + a * n + b] = (R)d1;
+            ops[op_dh(n) + a * n + b] =
+                (R)(d1 - m->cplus[a] * m->lplus[b] + m->cminus[a] * m->lminus[b]);
+            ops[op_vinv(n) + a * n + b] = (R)m->vinv[a * n + b];
+        }
+    for (int a = 0; a < n; ++a) {
+        ops[op_lm(n) + a] = (R)m->lminus[a];
+        ops[op_lp(n) + a] = (R)m->lplus[a];
+        ops[op_cm(n) + a] = (R)m->cminus[a];
+        ops[op_cp(n) + a] = (R)m->cplus[a];
+        ops[op_xi(n) + a] = (R)m->nodes[a];
+        ops[op_w(n) + a] = (R)m->weights[a];
+    }
+    Ctx<R> C{c};
+    HIPCHK(c, hipMemcpyAsync(C.template at<R>(c->L.geo), geo.data(), geo.size() * sizeof(R),
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(C.template at<double>(c->L.det64), det64.data(), E * 8,
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(C.template at<double>(c->L.w64), m->weights, n * 8,
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(C.template at<int32_t>(c->L.nbr), m->nbr, E * 2 * d * 4,
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(C.template at<R>(c->L.ops), ops.data(), ops.size() * sizeof(R),
+                             hipMemcpyHostToDevice, c->stream));
+    // Fbm is read only on boundary faces, but keep it defined
+    HIPCHK(c, hipMemsetAsync(c->ws + c->L.Fbm, 0, c->L.Tm - c->L.Fbm, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PCPF_OK;
+}
+
+pcpf_status check_ctx(pcpf_ctx* c) {
+    if (!c) return fail(nullptr, PCPF_EINVAL, "ctx is NULL");
+    return PCPF_OK;
+}
+
+#define DISPATCH(c, fn, ...) \
+    ((c)->prm.precision == PCPF_FP32 ? fn<float>(Ctx<float>{c}, __VA_ARGS__) \
+                                     : fn<double>(Ctx<double>{c}, __VA_ARGS__))
+
+pcpf_status check_params(const pcpf_params* p, std::string* err) {
+    if (!p) return fail(err, PCPF_EINVAL, "params is NULL");
+    if (p->precision != PCPF_FP64 && p->precision != PCPF_FP32)
+        return fail(err, PCPF_EUNSUPPORTED, "precision must be PCPF_FP64 or PCPF_FP32");
+    if (p->vel_kind < 0 || p->vel_kind > 3) return fail(err, PCPF_EINVAL, "unknown vel_kind");
+    if (p->reset_mode != PCPF_RESET_LINEAR && p->reset_mode != PCPF_RESET_LOGIT)
+        return fail(err, PCPF_EINVAL, "unknown reset_mode");
+    if (p->reset_every < 0 || p->precond_iters < 0)
+        return fail(err, PCPF_EINVAL, "reset_every and precond_iters must be >= 0");
+    if (!(p->gamma >= 0) || !(p->eps >= 0) || !(p->tau >= 0) || !(p->nu_max >= 0) ||
+        !(p->kappa > 0) || !(p->delta_n > 0) || !(p->delta_g > 0) || !(p->delta_phi > 0) ||
+        !(p->delta_phi < 0.5) || !std::isfinite(p->s0) || !std::isfinite(p->vel_amp) ||
+        !std::isfinite(p->dtau))
+        return fail(err, PCPF_EINVAL, "parameter out of range");
+    if ((p->vel_kind == PCPF_VEL_SINGLE_VORTEX || p->vel_kind == PCPF_VEL_LEVEQUE3D) &&
+        !(p->vel_period > 0))
+        return fail(err, PCPF_EINVAL, "vel_period must be > 0");
+    if (p->reset_mode == PCPF_RESET_LOGIT && !(p->eps_w > 0))
+        return fail(err, PCPF_EINVAL, "eps_w must be > 0 for the LOGIT reset");
+    if (p->reserved[0] || p->reserved[1] || p->reserved[2])
+        return fail(err, PCPF_EINVAL, "reserved fields must be 0");
+    return PCPF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pcpf_last_error(const pcpf_ctx* ctx) {
+    return ctx ? ctx->err.c_str() : g_err.c_str();
+}
+
+pcpf_status pcpf_solution_coords(const pcpf_mesh* m, double* xs) {
+    MeshInfo mi;
+    pcpf_status st = check_mesh(m, &mi, nullptr);
+    if (st != PCPF_OK) return st;
+    if (!xs) return fail(nullptr, PCPF_EINVAL, "xs is NULL");
+    std::vector<double> ref(mi.d);
+    for (int64_t e = 0; e < mi.E; ++e)
+        for (int i = 0; i < mi.nu; ++i) {
+            int r = i;
+            for (int k = 0; k < mi.d; ++k) {
+                ref[k] = m->nodes[r % mi.n];
+                r /= mi.n;
+            }
+            map_point(mi.d, m->x0 + e * mi.d, m->jac + e * mi.d * mi.d, ref.data(),
+                      xs + (e * mi.nu + i) * mi.d);
+        }
+    return PCPF_OK;
+}
+
+pcpf_status pcpf_workspace_bytes(const pcpf_mesh* m, const pcpf_params* p, size_t* nbytes) {
+    MeshInfo mi;
+    pcpf_status st = check_mesh(m, &mi, nullptr);
+    if (st != PCPF_OK) return st;
+    st = check_params(p, nullptr);
+    if (st != PCPF_OK) return st;
+    if (!nbytes) return fail(nullptr, PCPF_EINVAL, "nbytes is NULL");
+    *nbytes = layout(mi, p->precision).total;
+    return PCPF_OK;
+}
+
+pcpf_status pcpf_create(const pcpf_mesh* m, const pcpf_params* p, void* d_ws, size_t ws_bytes,
+                        void* stream, pcpf_ctx** out) {
+    if (!out) return fail(nullptr, PCPF_EINVAL, "out is NULL");
+    *out = nullptr;
+    MeshInfo mi;
+    pcpf_status st = check_mesh(m, &mi, nullptr);
+    if (st != PCPF_OK) return st;
+    st = check_params(p, nullptr);
+    if (st != PCPF_OK) return st;
+    st = check_geometry(m, mi, nullptr);
+    if (st != PCPF_OK) return st;
+    Layout L = layout(mi, p->precision);
+    if (!d_ws || ws_bytes < L.total)
+        return fail(nullptr, PCPF_EINVAL, "workspace missing or smaller than pcpf_workspace_bytes");
+    if (reinterpret_cast<uintptr_t>(d_ws) % 256 != 0)
+        return fail(nullptr, PCPF_EINVAL, "workspace must be 256-byte aligned");
+    pcpf_ctx* c = new pcpf_ctx();
+    c->mi = mi;
+    c->prm = *p;
+    c->stream = static_cast<hipStream_t>(stream);
+    c->ws = static_cast<char*>(d_ws);
+    c->L = L;
+    bool ok = p->precision == PCPF_FP32 ? get_launchers<float>(mi.d, mi.p, &c->L32)
+                                        : get_launchers<double>(mi.d, mi.p, &c->L64);
+    if (!ok) {
+        delete c;
+        return fail(nullptr, PCPF_EUNSUPPORTED, "no kernels built for this (d, p)");
+    }
+    st = p->precision == PCPF_FP32 ? upload<float>(c, m) : upload<double>(c, m);
+    if (st != PCPF_OK) {
+        g_err = c->err;
+        delete c;
+        return st;
+    }
+    *out = c;
+    return PCPF_OK;
+}
+
+void pcpf_destroy(pcpf_ctx* c) { delete c; }
+
+pcpf_status pcpf_sizes(const pcpf_ctx* c, int64_t* nelem, int32_t* nupts) {
+    if (!c) return fail(nullptr, PCPF_EINVAL, "ctx is NULL");
+    if (nelem) *nelem = c->mi.E;
+    if (nupts) *nupts = c->mi.nu;
+    return PCPF_OK;
+}
+
+pcpf_status pcpf_set_state(pcpf_ctx* c, const void* d_phi, const void* d_psi, double t,
+                           int64_t step) {
+    if (check_ctx(c) != PCPF_OK) return PCPF_EINVAL;
+    if (!d_phi) return fail(&c->err, PCPF_EINVAL, "d_phi is NULL");
+    if (step < 0) return fail(&c->err, PCPF_EINVAL, "step must be >= 0");
+    const size_t bytes = (size_t)c->mi.E * c->mi.nu * (c->prm.precision == PCPF_FP32 ? 4 : 8);
+    HIPCHK(c, hipMemcpyAsync(c->ws + c->L.un, d_phi, bytes, hipMemcpyDeviceToDevice, c->stream));
+    if (d_psi)
+        HIPCHK(c, hipMemcpyAsync(c->ws + c->L.un + bytes, d_psi, bytes, hipMemcpyDeviceToDevice,
+                                 c->stream));
+    c->t = t;
+    c->step = step;
+    c->has_state = true;
+    c->has_psi = d_psi != nullptr;
+    c->trace_ok[0] = c->trace_ok[1] = false;
+    return PCPF_OK;
+}
+
+pcpf_status pcpf_get_state(pcpf_ctx* c, void* d_phi, void* d_psi, double* t, int64_t* step) {
+    if (check_ctx(c) != PCPF_OK) return PCPF_EINVAL;
+    if (!c->has_state) return fail(&c->err, PCPF_ESTATE, "no state set");
+    const size_t bytes = (size_t)c->mi.E * c->mi.nu * (c->prm.precision == PCPF_FP32 ? 4 : 8);
+    if (d_phi)
+        HIPCHK(c, hipMemcpyAsync(d_phi, c->ws + c->L.un, bytes, hipMemcpyDeviceToDevice, c->stream));
+    if (d_psi) {
+        if (!c->has_psi) return fail(&c->err, PCPF_ESTATE, "psi not available before a reset");
+        HIPCHK(c, hipMemcpyAsync(d_psi, c->ws + c->L.un + bytes, bytes, hipMemcpyDeviceToDevice,
+                                 c->stream));
+    }
+    if (t) *t = c->t;
+    if (step) *step = c->step;
+    return PCPF_OK;
+}
+
+pcpf_status pcpf_step(pcpf_ctx* c, double dt, int64_t nsteps) {
+    if (check_ctx(c) != PCPF_OK) return PCPF_EINVAL;
+    if (!c->has_state) return fail(&c->err, PCPF_ESTATE, "no state set");
+    if (!std::isfinite(dt) || nsteps < 0) return fail(&c->err, PCPF_EINVAL, "bad dt or nsteps");
+    return DISPATCH(c, step_impl, dt, nsteps);
+}
+
+pcpf_status pcpf_precondition(pcpf_ctx* c, int32_t iters) {
+    if (check_ctx(c) != PCPF_OK) return PCPF_EINVAL;
+    if (!c->has_state) return fail(&c->err, PCPF_ESTATE, "no state set");
+    const int k = iters < 0 ? c->prm.precond_iters : iters;
+    return DISPATCH(c, precondition_impl, k);
+}
+
+pcpf_status pcpf_residual(pcpf_ctx* c, const void* d_phi, const void* d_psi, double t,
+                          int32_t mode, void* d_rphi, void* d_rpsi) {
+    if (check_ctx(c) != PCPF_OK) return PCPF_EINVAL;
+    if (mode != PCPF_MODE_PHYS && mode != PCPF_MODE_PRECOND)
+        return fail(&c->err, PCPF_EINVAL, "unknown residual mode");
+    if (!d_psi || !d_rpsi || (mode == PCPF_MODE_PHYS && (!d_phi || !d_rphi)))
+        return fail(&c->err, PCPF_EINVAL, "residual: NULL input or output");
+    if (mode == PCPF_MODE_PRECOND && !c->has_sign)
+        return fail(&c->err, PCPF_ESTATE, "precond residual needs the sign of a reset");
+    if (d_rpsi == d_psi || d_rpsi == d_phi || (d_rphi && (d_rphi == d_phi || d_rphi == d_psi)))
+        return fail(&c->err, PCPF_EINVAL, "residual outputs may not alias inputs");
+    return DISPATCH(c, residual_impl, d_phi, d_psi, t, mode, d_rphi, d_rpsi);
+}
+
+pcpf_status pcpf_get_sign(pcpf_ctx* c, void* d_sgn) {
+    if (check_ctx(c) != PCPF_OK) return PCPF_EINVAL;
+    if (!c->has_sign) return fail(&c->err, PCPF_ESTATE, "no reset has run");
+    if (!d_sgn) return fail(&c->err, PCPF_EINVAL, "d_sgn is NULL");
+    const size_t bytes = (size_t)c->mi.E * c->mi.nu * (c->prm.precision == PCPF_FP32 ? 4 : 8);
+    HIPCHK(c, hipMemcpyAsync(d_sgn, c->ws + c->L.sgn, bytes, hipMemcpyDeviceToDevice, c->stream));
+    return PCPF_OK;
+}
+
+pcpf_status pcpf_sensor(pcpf_ctx* c, const void* d_psi, void* d_nu) {
+    if (check_ctx(c) != PCPF_OK) return PCPF_EINVAL;
+    if (!d_psi || !d_nu) return fail(&c->err, PCPF_EINVAL, "sensor: NULL pointer");
+    return DISPATCH(c, sensor_impl, d_psi, d_nu);
+}
+
+pcpf_status pcpf_reduce(pcpf_ctx* c, int32_t what, const void* d_field, const void* d_ref,
+                        double* out) {
+    if (check_ctx(c) != PCPF_OK) return PCPF_EINVAL;
+    if (!out) return fail(&c->err, PCPF_EINVAL, "out is NULL");
+    if (what != PCPF_REDUCE_MASS && what != PCPF_REDUCE_L1)
+        return fail(&c->err, PCPF_EINVAL, "unknown reduction");
+    if (what == PCPF_REDUCE_L1 && !d_ref) return fail(&c->err, PCPF_EINVAL, "L1 needs d_ref");
+    if (!d_field && !c->has_state) return fail(&c->err, PCPF_ESTATE, "no state set");
+    return DISPATCH(c, reduce_impl, what, d_field, d_ref, out);
+}
+
+}  // extern "C"

@@ -1,0 +1,133 @@
+// Internal declarations shared by the HIP kernels and the C-ABI implementation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "pcpf.h"
+
+namespace pcpf {
+
+constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+
+// Block shape of a (d, p) element: one thread per solution point, EPB elements per block.
+template <int D, int P>
+struct Shape {
+    static constexpr int N = P + 1;
+    static constexpr int NU = ipow(N, D);
+    static constexpr int NFA = ipow(N, D - 1);
+    static constexpr int NF = 2 * D * NFA;
+    static constexpr int EPB = (256 / NU) > 0 ? (256 / NU) : 1;
+    static constexpr int NT = ((EPB * NU + 63) / 64) * 64;
+    static constexpr int GEO = D + 2 * D * D + 1;   // x0[D], J[D][D], Jinv[D][D], detJ
+};
+
+// Operator block (compute type), n = p + 1:
+//   D1[n*n] (nodal derivative), DH[n*n] (derivative minus boundary correction of the
+//   discontinuous normal flux), VINV[n*n], lm[n], lp[n], cm[n], cp[n], xi[n], w[n]
+constexpr int ops_size(int n) { return 3 * n * n + 6 * n; }
+constexpr int OP_D1 = 0;
+constexpr int op_dh(int n) { return n * n; }
+constexpr int op_vinv(int n) { return 2 * n * n; }
+constexpr int op_lm(int n) { return 3 * n * n; }
+constexpr int op_lp(int n) { return 3 * n * n + n; }
+constexpr int op_cm(int n) { return 3 * n * n + 2 * n; }
+constexpr int op_cp(int n) { return 3 * n * n + 3 * n; }
+constexpr int op_xi(int n) { return 3 * n * n + 4 * n; }
+constexpr int op_w(int n) { return 3 * n * n + 5 * n; }
+
+// kernel-side physics parameters (compute type)
+template <typename R>
+struct Phys {
+    R gamma, eps, tau, delta_n, delta_g, nu_max, s0, kappa;
+    R ampg;        // A * g(t) at the stage time
+    R u0[3];
+    int vel_kind;
+};
+
+// grad_flux kernel modes
+enum { GF_PHYS = 0, GF_PRECOND = 1, GF_SIGN = 2, GF_SENSOR = 3 };
+
+template <typename R>
+struct GFArgs {
+    const R* u[2];       // stage input per variable ([E][NU])
+    R* P[2];             // partial divergence per variable
+    R* Fp[2];            // common flux on + faces   [E][D][NFA]
+    R* Fbm[2];           // common flux on boundary - faces [E][D][NFA]
+    const R* Tm[2];      // traces on - faces        [E][D][NFA]
+    const R* geo;        // [E][GEO]
+    const int32_t* nbr;  // [E][2D]
+    const R* ops;
+    const R* sgn;        // smeared sign (precond)
+    R* out;              // sign (GF_SIGN) or nu (GF_SENSOR)
+    int64_t E;
+    Phys<R> ph;
+};
+
+// update kernel kinds
+enum { UP_RK = 0, UP_RESID = 1 };
+
+template <typename R>
+struct UPArgs {
+    const R* P[2];
+    const R* Fp[2];
+    const R* Fbm[2];
+    R* un[2];            // u_n (read; written on the last stage)
+    R* acc[2];           // RK accumulator
+    R* us[2];            // next stage input (written on stages 0-2)
+    R* res[2];           // residual output (UP_RESID)
+    R* Tm[2];            // - face traces of the next stage input
+    const R* geo;
+    const int32_t* nbr;
+    const R* ops;
+    int* flag;           // set to 1 on a non-finite value or |phi| > 10
+    int64_t E;
+    R bcoef;             // weight of R in the accumulator
+    R ccoef;             // step of the next stage input (a_{s+1} dt), or dt on the last stage
+    int first, last;
+};
+
+template <typename R>
+struct TRArgs {
+    const R* u[2];
+    R* Tm[2];
+    const R* ops;
+    int64_t E;
+};
+
+template <typename R>
+struct RDArgs {
+    const R* field;
+    const R* ref;        // may be null
+    const double* det64; // |J| per element in float64
+    const double* w64;   // 1D quadrature weights in float64
+    double* partial;
+    int64_t E;
+    int kind;            // 0 mass, 1 L1
+};
+
+// Launch table of one (precision, d, p) instantiation.
+template <typename R>
+struct Launchers {
+    int epb, nt, ngeo;
+    void (*grad_flux)(int mode, int nvar, const GFArgs<R>&, hipStream_t);
+    void (*update)(int kind, int nvar, const UPArgs<R>&, hipStream_t);
+    void (*trace)(int nvar, const TRArgs<R>&, hipStream_t);
+    void (*reduce)(const RDArgs<R>&, int nblocks, hipStream_t);
+};
+
+template <typename R>
+bool get_launchers(int d, int p, Launchers<R>* out);
+
+// elementwise helpers (not order dependent)
+template <typename R>
+void launch_reset(const R* phi, R* psi, int64_t n, int mode, double eps_w, double delta_phi,
+                  hipStream_t s);
+void launch_reduce_final(const double* partial, int nblocks, double* out, hipStream_t s);
+
+constexpr int REDUCE_BLOCKS = 1024;
+constexpr int REDUCE_THREADS = 256;
+
+}  // namespace pcpf

@@ -1,0 +1,205 @@
+"""Python binding of the FR-PCPF HIP library (argument marshalling only).
+
+Every step of the method runs in the library's kernels; this module converts numpy /
+torch arguments to the C ABI of include/pcpf.h. torch provides the device memory (the
+workspace and the state tensors) and the HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import PcpfMesh, PcpfParams, check
+
+FP64, FP32 = _lib.PCPF_FP64, _lib.PCPF_FP32
+MODE_PHYS, MODE_PRECOND = _lib.PCPF_MODE_PHYS, _lib.PCPF_MODE_PRECOND
+REDUCE_MASS, REDUCE_L1 = _lib.PCPF_REDUCE_MASS, _lib.PCPF_REDUCE_L1
+
+_PRECISIONS = {"fp64": FP64, "fp32": FP32, FP64: FP64, FP32: FP32}
+_DTYPES = {FP64: torch.float64, FP32: torch.float32}
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def line_operators(order: int) -> dict:
+    """1D Gauss-Legendre element operators built by the library (host)."""
+    lib = _lib.load()
+    n = order + 1
+    out = {k: np.zeros(n) for k in ("nodes", "weights", "lminus", "lplus", "cminus", "cplus")}
+    out["deriv"] = np.zeros(n * n)
+    out["vinv"] = np.zeros(n * n)
+    check(lib.pcpf_line_operators(order, _dptr(out["nodes"]), _dptr(out["weights"]),
+                                  _dptr(out["deriv"]), _dptr(out["lminus"]), _dptr(out["lplus"]),
+                                  _dptr(out["cminus"]), _dptr(out["cplus"]), _dptr(out["vinv"])))
+    return out
+
+
+class MeshArgs:
+    """A pcpf_mesh whose host arrays stay alive as long as this object."""
+
+    def __init__(self, ndims: int, order: int, x0, jac, nbr, period=(0.0, 0.0, 0.0),
+                 ops: dict | None = None):
+        self.ops = ops if ops is not None else line_operators(order)
+        self.x0 = np.ascontiguousarray(x0, dtype=np.float64)
+        self.jac = np.ascontiguousarray(jac, dtype=np.float64)
+        self.nbr = np.ascontiguousarray(nbr, dtype=np.int32)
+        E = self.x0.shape[0]
+        if self.x0.shape != (E, ndims) or self.jac.shape != (E, ndims, ndims) \
+                or self.nbr.shape != (E, 2 * ndims):
+            raise ValueError("mesh array shapes do not match ndims")
+        o = self.ops
+        self.c = PcpfMesh(ndims, order, E, _dptr(o["nodes"]), _dptr(o["weights"]),
+                          _dptr(o["deriv"]), _dptr(o["lminus"]), _dptr(o["lplus"]),
+                          _dptr(o["cminus"]), _dptr(o["cplus"]), _dptr(o["vinv"]),
+                          _dptr(self.x0), _dptr(self.jac),
+                          self.nbr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                          (ctypes.c_double * 3)(*[float(x) for x in (list(period) + [0.0] * 3)[:3]]))
+        self.ndims, self.order, self.nelem = ndims, order, E
+        self.nupts = (order + 1) ** ndims
+
+    def solution_coords(self) -> np.ndarray:
+        lib = _lib.load()
+        xs = np.zeros((self.nelem, self.nupts, self.ndims))
+        check(lib.pcpf_solution_coords(ctypes.byref(self.c), _dptr(xs)))
+        return xs
+
+
+def make_params(prm, precision) -> PcpfParams:
+    """pcpf_params from any object with the workloads.Params attribute names."""
+    c = PcpfParams()
+    for name in ("gamma", "eps", "eps_w", "tau", "nu_max", "s0", "kappa", "dtau", "delta_n",
+                 "delta_g", "delta_phi", "vel_amp", "vel_period"):
+        setattr(c, name, float(getattr(prm, name)))
+    u0 = list(getattr(prm, "vel_u0")) + [0.0] * 3
+    c.vel_u0 = (ctypes.c_double * 3)(*[float(x) for x in u0[:3]])
+    c.vel_kind = int(prm.vel_kind)
+    c.reset_mode = int(prm.reset_mode)
+    c.reset_every = int(prm.reset_every)
+    c.precond_iters = int(prm.precond_iters)
+    c.precision = _PRECISIONS[precision]
+    return c
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Solver:
+    """One FR-PCPF context on a CUDA/HIP device."""
+
+    def __init__(self, ndims, order, x0, jac, nbr, params, precision="fp64", device="cuda",
+                 period=(0.0, 0.0, 0.0)):
+        self.lib = _lib.load()
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.mesh = MeshArgs(ndims, order, x0, jac, nbr, period)
+        self.params = params
+        self.precision = _PRECISIONS[precision]
+        self.dtype = _DTYPES[self.precision]
+        self.cparams = make_params(params, self.precision)
+        nb = ctypes.c_size_t(0)
+        check(self.lib.pcpf_workspace_bytes(ctypes.byref(self.mesh.c), ctypes.byref(self.cparams),
+                                            ctypes.byref(nb)))
+        self.ws_bytes = nb.value
+        with torch.cuda.device(self.device):
+            self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+            base = self.ws.data_ptr()
+            self._ws_ptr = (base + 255) // 256 * 256
+            self.stream = torch.cuda.current_stream(self.device)
+        ctx = ctypes.c_void_p()
+        check(self.lib.pcpf_create(ctypes.byref(self.mesh.c), ctypes.byref(self.cparams),
+                                   ctypes.c_void_p(self._ws_ptr), ctypes.c_size_t(self.ws_bytes),
+                                   ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx)))
+        self.ctx = ctx
+        self.nelem = self.mesh.nelem
+        self.nupts = self.mesh.nupts
+
+    @classmethod
+    def from_box(cls, mesh, order, params, precision="fp64", device="cuda"):
+        period = [float(mesh.period[k]) if mesh.periodic[k] else 0.0 for k in range(mesh.ndims)]
+        return cls(mesh.ndims, order, mesh.x0, mesh.jac, mesh.nbr, params, precision, device,
+                   period)
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx is not None and ctx.value:
+            self.lib.pcpf_destroy(ctx)
+            self.ctx = None
+
+    # -- helpers -----------------------------------------------------------------------
+    def _field(self, a) -> torch.Tensor:
+        t = torch.as_tensor(a)
+        if t.shape != (self.nelem, self.nupts):
+            raise ValueError(f"field must have shape {(self.nelem, self.nupts)}")
+        return t.to(device=self.device, dtype=self.dtype).contiguous()
+
+    def empty(self, shape=None):
+        shape = shape or (self.nelem, self.nupts)
+        return torch.empty(shape, dtype=self.dtype, device=self.device)
+
+    def _chk(self, status):
+        check(status, self.ctx)
+
+    # -- the C ABI ------------------------------------------------------------------------
+    def solution_coords(self) -> np.ndarray:
+        return self.mesh.solution_coords()
+
+    def set_state(self, phi, psi=None, t=0.0, step=0):
+        self._phi_in = self._field(phi)
+        self._psi_in = self._field(psi) if psi is not None else None
+        self._chk(self.lib.pcpf_set_state(self.ctx, _ptr(self._phi_in), _ptr(self._psi_in),
+                                          float(t), int(step)))
+
+    def get_state(self, want_psi=True):
+        phi = self.empty()
+        psi = self.empty() if want_psi else None
+        t = ctypes.c_double()
+        n = ctypes.c_int64()
+        self._chk(self.lib.pcpf_get_state(self.ctx, _ptr(phi), _ptr(psi), ctypes.byref(t),
+                                          ctypes.byref(n)))
+        return phi, psi, t.value, n.value
+
+    def step(self, dt, nsteps=1):
+        self._chk(self.lib.pcpf_step(self.ctx, float(dt), int(nsteps)))
+
+    def precondition(self, iters=-1):
+        self._chk(self.lib.pcpf_precondition(self.ctx, int(iters)))
+
+    def residual(self, phi, psi, t=0.0, mode=MODE_PHYS):
+        phi_t = self._field(phi) if phi is not None else None
+        psi_t = self._field(psi)
+        rpsi = self.empty()
+        rphi = self.empty() if mode == MODE_PHYS else None
+        self._chk(self.lib.pcpf_residual(self.ctx, _ptr(phi_t), _ptr(psi_t), float(t), int(mode),
+                                         _ptr(rphi), _ptr(rpsi)))
+        return rphi, rpsi
+
+    def sign(self):
+        out = self.empty()
+        self._chk(self.lib.pcpf_get_sign(self.ctx, _ptr(out)))
+        return out
+
+    def sensor(self, psi):
+        psi_t = self._field(psi)
+        nu = self.empty((self.nelem,))
+        self._chk(self.lib.pcpf_sensor(self.ctx, _ptr(psi_t), _ptr(nu)))
+        return nu
+
+    def reduce(self, what=REDUCE_MASS, field=None, ref=None) -> float:
+        f = self._field(field) if field is not None else None
+        r = self._field(ref) if ref is not None else None
+        out = ctypes.c_double()
+        self._chk(self.lib.pcpf_reduce(self.ctx, int(what), _ptr(f), _ptr(r), ctypes.byref(out)))
+        return out.value
+
+    def mass(self, field=None) -> float:
+        return self.reduce(REDUCE_MASS, field)
+
+    def l1(self, ref, field=None) -> float:
+        return self.reduce(REDUCE_L1, field, ref)
