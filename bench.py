@@ -1,0 +1,243 @@
+#!/usr/bin/env python3
+"""Throughput of the FR-PCPF RK4 step on one MI355X.
+
+Workload: 2D unit square, 128x128 affine quads, p = 4 (25 Gauss-Legendre points per
+element, 409 600 DOF), time-reversing single-vortex velocity (T = 8), tanh circle r = 0.15
+at (0.5, 0.75), CFL 0.05, reset + 10 pseudo-time iterations of the preconditioner before
+every step whose index is a multiple of 1000 (the timed region starts at step 0, so it
+contains one). A step is one classic RK4 step of the whole path (4 x [grad_flux + update]
+plus the scheduled reset/preconditioning). Inputs are resident in device memory before
+the timed region starts.
+
+Prints ONE JSON line: value = DOF-stage updates per second of the FP64 form (E*N_u*4*K /
+wall time of K steps), with the FP32 form, the per-kernel roofline (HIP events around
+every launch of a second, identical timed region), and the CPU oracle on a bounded sample
+of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "DOF-stage updates/s FP64 vs FP32/BF16 at equal interface L1 error; adjoint s/step"
+UNIT = "DOF-stage updates/s"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_vortex2d_128x128_p4.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_bytes(d, p, word, kind):
+    """Algorithmic bytes per element of one launch (inputs read + outputs written once)."""
+    n = p + 1
+    nu, nfa = n ** d, n ** (d - 1)
+    V = 2
+    geo = d + 2 * d * d + 1
+    if kind == "grad_flux":
+        words = V * nu + V * d * nfa + geo + V * nu + V * d * nfa
+    else:  # update, averaged over the four stages (acc is not read on stage 1, not written on 4)
+        words = V * nu + 2 * V * d * nfa + 1 + V * nu + 0.75 * V * nu + 0.75 * V * nu + V * nu \
+            + V * d * nfa
+    return words * word
+
+
+def step_alg_bytes_per_dof(d, p, word):
+    """B_alg per DOF-stage: RK4 registers (5 V N_u) + two face exchanges (2 V N_f)."""
+    n = p + 1
+    nu, nf = n ** d, 2 * d * n ** (d - 1)
+    return (5 * 2 * nu + 2 * 2 * nf) * word / nu
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("pcpf_kernels.hip", "pcpf_internal.h"):
+        with open(os.path.join(ROOT, "paper_2006_10967_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def make_solver(cfg, mesh, precision):
+    from paper_2006_10967_amd import Solver
+    return Solver.from_box(mesh, cfg.order, cfg.params, precision=precision, device="cuda:0")
+
+
+def run_form(cfg, mesh, precision, steps, warmup, phi0_np):
+    import torch
+    s = make_solver(cfg, mesh, precision)
+    dt = cfg.dt(mesh)
+    phi0 = torch.as_tensor(phi0_np).to("cuda:0", s.dtype)
+    # warm-up (includes a reset + preconditioning at step 0)
+    s.set_state(phi0, None, 0.0, 0)
+    s.step(dt, warmup)
+    # timed region: K steps from step 0 (one reset + preconditioning inside)
+    s.set_state(phi0, None, 0.0, 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(dt, steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    phi_end = s.get_state(want_psi=False)[0].clone()
+    # the same region again with HIP events around every launch (per-kernel durations)
+    s.set_state(phi0, None, 0.0, 0)
+    s.kernel_times(reset=True)
+    s.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(dt, steps)
+    torch.cuda.synchronize()
+    wall_ev = time.perf_counter() - t0
+    s.set_timing(False)
+    kt = s.kernel_times(reset=True)
+    # preconditioning alone (reset + K pseudo iterations)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.precondition()
+    torch.cuda.synchronize()
+    pc_ms = (time.perf_counter() - t0) * 1e3
+    return s, wall, wall_ev, kt, pc_ms, phi_end
+
+
+def cpu_baseline(cfg, mesh, phi0_np, nsteps):
+    """The FP64 CPU oracle (test infrastructure) on a bounded sample of the same workload:
+    one reset + preconditioning and nsteps RK4 steps of the full mesh."""
+    import torch
+    from oracle import Oracle
+    cores = min(16, len(os.sched_getaffinity(0)))
+    torch.set_num_threads(cores)
+    o = Oracle(cfg.ndims, cfg.order, mesh, cfg.params)
+    phi = torch.as_tensor(phi0_np, dtype=torch.float64)
+    t0 = time.perf_counter()
+    psi, _ = o.precondition(phi)
+    t_pc = time.perf_counter() - t0
+    dt = cfg.dt(mesh)
+    t0 = time.perf_counter()
+    t = 0.0
+    for _ in range(nsteps):
+        phi, psi = o.step(phi, psi, t, dt)
+        t += dt
+    t_steps = time.perf_counter() - t0
+    rate = cfg.dof * 4 * nsteps / t_steps
+    return {"value": rate, "unit": UNIT, "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"full {cfg.n}x{cfg.n} p={cfg.order} mesh: {nsteps} RK4 steps "
+                      f"({t_steps:.1f} s) after one reset + {cfg.params.precond_iters} "
+                      f"pseudo iterations ({t_pc:.1f} s, not in value)",
+            "s_per_step": t_steps / nsteps}
+
+
+def load_traffic(kernel, hsh):
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            data = json.load(fh)
+    except OSError:
+        return None
+    if data.get("kernel_source_hash") != hsh:
+        return None
+    return data.get("per_launch_bytes", {}).get(kernel)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--config", default="C2")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=60)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path "
+              f"(--gpus {args.gpus} requested)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2006_10967_amd import MeshArgs
+
+    cfg = W.config(args.config)
+    mesh = cfg.mesh()
+    period = [float(mesh.period[k]) if mesh.periodic[k] else 0.0 for k in range(cfg.ndims)]
+    coords = MeshArgs(cfg.ndims, cfg.order, mesh.x0, mesh.jac, mesh.nbr, period).solution_coords()
+    phi0 = W.ic_phi(coords, cfg.centre, cfg.radius, cfg.params.eps_w)
+    K, Wm = args.steps, args.warmup
+    log(f"[bench] {cfg.name}: E={cfg.nelem} N_u={cfg.nupts} DOF={cfg.dof} steps={K} warmup={Wm}")
+
+    s64, wall64, wall64_ev, kt64, pc64, phi64 = run_form(cfg, mesh, "fp64", K, Wm, phi0)
+    value = cfg.dof * 4 * K / wall64
+    log(f"[bench] fp64: {wall64 * 1e3 / K:.4f} ms/step, {value:.4e} DOF-stage/s")
+
+    # roofline of the dominant kernel (HIP-event durations of the second timed region)
+    word = 8
+    kern = max(("grad_flux", "update"), key=lambda k: kt64[k][0])
+    ms, nl = kt64[kern]
+    avg_s = ms / nl * 1e-3
+    bytes_launch = kernel_bytes(cfg.ndims, cfg.order, word, kern) * cfg.nelem
+    achieved = bytes_launch / avg_s / 1e9
+    hsh = kernel_source_hash()
+    traffic = load_traffic(kern, hsh)
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kern,
+                "alg_bytes_per_launch": bytes_launch,
+                "avg_launch_us": avg_s * 1e6}
+    kernels = {k: {"avg_us": (v[0] / v[1] * 1e3) if v[1] else None, "launches": v[1],
+                   "alg_bytes_per_launch": kernel_bytes(cfg.ndims, cfg.order, word, k) * cfg.nelem
+                   if k in ("grad_flux", "update") else None}
+               for k, v in kt64.items()}
+    for k in ("grad_flux", "update"):
+        if kernels[k]["avg_us"]:
+            kernels[k]["alg_GBs"] = kernels[k]["alg_bytes_per_launch"] / (kernels[k]["avg_us"] * 1e3)
+    step_bytes = step_alg_bytes_per_dof(cfg.ndims, cfg.order, word) * cfg.dof * 4
+    out = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": K, "warmup": Wm,
+        "ms_per_step": wall64 * 1e3 / K, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": cfg.name, "mesh": f"{cfg.n}x{cfg.n} quads", "order": cfg.order,
+                   "dof": cfg.dof, "velocity": "single vortex T=8", "dt": cfg.dt(mesh),
+                   "reset_every": cfg.params.reset_every,
+                   "precond_iters": cfg.params.precond_iters},
+        "roofline": roofline,
+        "kernels_fp64": kernels,
+        "step_alg_GBs_fp64": step_bytes / (wall64 / K * 1e9),
+        "ms_per_step_with_events": wall64_ev * 1e3 / K,
+        "precondition_ms_fp64": pc64,
+    }
+
+    if not args.no_fp32:
+        s32, wall32, _, kt32, pc32, phi32 = run_form(cfg, mesh, "fp32", K, Wm, phi0)
+        v32 = cfg.dof * 4 * K / wall32
+        l1 = s64.l1(phi64, phi32.double())
+        mass64 = s64.mass(phi64)
+        mass0 = s64.mass(torch.as_tensor(phi0))
+        mass32 = s64.mass(phi32.double())
+        out["forms"] = {"fp32": {
+            "value": v32, "ms_per_step": wall32 * 1e3 / K, "speedup_vs_fp64": v32 / value,
+            "interface_l1_vs_fp64": l1, "mass_drift_fp32": (mass32 - mass0) / mass0,
+            "mass_drift_fp64": (mass64 - mass0) / mass0, "precondition_ms": pc32,
+            "kernels": {k: {"avg_us": (v[0] / v[1] * 1e3) if v[1] else None}
+                        for k, v in kt32.items()}}}
+        log(f"[bench] fp32: {wall32 * 1e3 / K:.4f} ms/step, {v32:.4e} DOF-stage/s, "
+            f"int|phi32-phi64| = {l1:.3e}")
+
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(cfg, mesh, phi0, args.cpu_steps)
+        log(f"[bench] oracle: {out['cpu_baseline']['value']:.4e} DOF-stage/s on "
+            f"{out['cpu_baseline']['cores']} cores")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

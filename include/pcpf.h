@@ -195,6 +195,25 @@ pcpf_status pcpf_sensor(pcpf_ctx* ctx, const void* d_psi, void* d_nu);
 pcpf_status pcpf_reduce(pcpf_ctx* ctx, int32_t what, const void* d_field,
                         const void* d_ref, double* out);
 
+/* --- measurement -------------------------------------------------------------------- */
+
+/* Kernel classes of the per-launch timing. */
+enum { PCPF_KT_GRAD_FLUX = 0,     /* physical grad_flux launches (Steps 1-5)           */
+       PCPF_KT_UPDATE = 1,        /* physical update launches (Step 6 + RK4 combine)   */
+       PCPF_KT_PC_GRAD_FLUX = 2,  /* preconditioning grad_flux launches               */
+       PCPF_KT_PC_UPDATE = 3,     /* preconditioning update launches                  */
+       PCPF_KT_COUNT = 4 };
+
+/* on != 0: pcpf_step and pcpf_precondition record a HIP event pair around every
+ * grad_flux / update launch on the context's stream and accumulate the elapsed times
+ * when they synchronise. Off by default (the event records add a small gap between
+ * launches). */
+pcpf_status pcpf_set_timing(pcpf_ctx* ctx, int32_t on);
+
+/* Accumulated kernel time in milliseconds and launch count per class, host arrays of
+ * PCPF_KT_COUNT entries (either may be NULL); reset != 0 clears the accumulators. */
+pcpf_status pcpf_kernel_times(pcpf_ctx* ctx, double* ms, int64_t* launches, int32_t reset);
+
 #ifdef __cplusplus
 }
 #endif

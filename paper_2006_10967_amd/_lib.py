@@ -85,6 +85,8 @@ def load() -> ctypes.CDLL:
         "pcpf_get_sign": (st, [vp, vp]),
         "pcpf_sensor": (st, [vp, vp, vp]),
         "pcpf_reduce": (st, [vp, i32, vp, vp, ctypes.POINTER(dbl)]),
+        "pcpf_set_timing": (st, [vp, i32]),
+        "pcpf_kernel_times": (st, [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64), i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

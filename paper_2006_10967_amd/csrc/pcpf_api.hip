@@ -301,6 +301,16 @@ struct pcpf_ctx {
     bool has_state = false, has_psi = false, has_sign = false;
     bool trace_ok[2] = {false, false};
     std::string err = "no error";
+    // per-launch event timing (pcpf_set_timing)
+    bool timing = false;
+    std::vector<hipEvent_t> events;
+    std::vector<int> ev_kind;
+    size_t ev_used = 0;
+    double kt_ms[PCPF_KT_COUNT] = {0, 0, 0, 0};
+    int64_t kt_n[PCPF_KT_COUNT] = {0, 0, 0, 0};
+    ~pcpf_ctx() {
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    }
 };
 
 namespace {
@@ -430,6 +440,45 @@ pcpf_status launch_status(pcpf_ctx* c) {
     return hip_check(c, hipGetLastError(), "kernel launch");
 }
 
+// Run launch() between two recorded events when timing is on.
+template <typename F>
+pcpf_status timed(pcpf_ctx* c, int kind, F&& launch) {
+    if (!c->timing) {
+        launch();
+        return PCPF_OK;
+    }
+    while (c->events.size() < c->ev_used + 2) {
+        hipEvent_t e;
+        HIPCHK(c, hipEventCreate(&e));
+        c->events.push_back(e);
+    }
+    HIPCHK(c, hipEventRecord(c->events[c->ev_used], c->stream));
+    launch();
+    HIPCHK(c, hipEventRecord(c->events[c->ev_used + 1], c->stream));
+    c->ev_kind.push_back(kind);
+    c->ev_used += 2;
+    return PCPF_OK;
+}
+
+// Accumulate the recorded event pairs (the stream must have been synchronised).
+pcpf_status collect_times(pcpf_ctx* c) {
+    for (size_t i = 0; i < c->ev_kind.size(); ++i) {
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->events[2 * i], c->events[2 * i + 1]));
+        c->kt_ms[c->ev_kind[i]] += ms;
+        c->kt_n[c->ev_kind[i]] += 1;
+    }
+    c->ev_kind.clear();
+    c->ev_used = 0;
+    return PCPF_OK;
+}
+
+#define TIMED(c, kind, stmt)                                               \
+    do {                                                                   \
+        pcpf_status _t = timed((c), (kind), [&]() { stmt; });              \
+        if (_t != PCPF_OK) return _t;                                      \
+    } while (0)
+
 // - face traces of the stored state for the variables whose traces are stale
 template <typename R>
 pcpf_status refresh_traces(const Ctx<R>& C) {
@@ -486,14 +535,14 @@ pcpf_status precondition_impl(const Ctx<R>& C, int iters) {
             GFArgs<R> g = gf_args<R>(C, uin, uin, c->t);
             psi_only(g);
             g.u[0] = uin;
-            C.Lk().grad_flux(GF_PRECOND, 1, g, c->stream);
+            TIMED(c, PCPF_KT_PC_GRAD_FLUX, C.Lk().grad_flux(GF_PRECOND, 1, g, c->stream));
             UPArgs<R> u = up_args<R>(C);
             up_psi_only(u);
             u.first = s == 0;
             u.last = s == 3;
             u.bcoef = (R)RK_B[s];
             u.ccoef = (R)(s == 3 ? dtau : RK_C[s + 1] * dtau);
-            C.Lk().update(UP_RK, 1, u, c->stream);
+            TIMED(c, PCPF_KT_PC_UPDATE, C.Lk().update(UP_RK, 1, u, c->stream));
         }
     }
     c->trace_ok[1] = iters > 0;
@@ -518,13 +567,13 @@ pcpf_status step_impl(const Ctx<R>& C, double dt, int64_t nsteps) {
             const R* u0 = s == 0 ? C.plane(c->L.un, 0) : C.plane(c->L.us, 0);
             const R* u1 = s == 0 ? C.plane(c->L.un, 1) : C.plane(c->L.us, 1);
             GFArgs<R> g = gf_args<R>(C, u0, u1, ts);
-            C.Lk().grad_flux(GF_PHYS, 2, g, c->stream);
+            TIMED(c, PCPF_KT_GRAD_FLUX, C.Lk().grad_flux(GF_PHYS, 2, g, c->stream));
             UPArgs<R> u = up_args<R>(C);
             u.first = s == 0;
             u.last = s == 3;
             u.bcoef = (R)RK_B[s];
             u.ccoef = (R)(s == 3 ? dt : RK_C[s + 1] * dt);
-            C.Lk().update(UP_RK, 2, u, c->stream);
+            TIMED(c, PCPF_KT_UPDATE, C.Lk().update(UP_RK, 2, u, c->stream));
         }
         c->t += dt;
         c->step += 1;
@@ -535,6 +584,8 @@ pcpf_status step_impl(const Ctx<R>& C, double dt, int64_t nsteps) {
     HIPCHK(c, hipMemcpyAsync(&flag, C.template at<int>(c->L.flag), sizeof(int),
                              hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    st = collect_times(c);
+    if (st != PCPF_OK) return st;
     if (flag) return fail(&c->err, PCPF_ENONFINITE, "state became non-finite or |phi| > 10");
     return PCPF_OK;
 }
@@ -834,7 +885,10 @@ pcpf_status pcpf_precondition(pcpf_ctx* c, int32_t iters) {
     if (check_ctx(c) != PCPF_OK) return PCPF_EINVAL;
     if (!c->has_state) return fail(&c->err, PCPF_ESTATE, "no state set");
     const int k = iters < 0 ? c->prm.precond_iters : iters;
-    return DISPATCH(c, precondition_impl, k);
+    pcpf_status st = DISPATCH(c, precondition_impl, k);
+    if (st != PCPF_OK || !c->timing) return st;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return collect_times(c);
 }
 
 pcpf_status pcpf_residual(pcpf_ctx* c, const void* d_phi, const void* d_psi, double t,
@@ -875,6 +929,30 @@ pcpf_status pcpf_reduce(pcpf_ctx* c, int32_t what, const void* d_field, const vo
     if (what == PCPF_REDUCE_L1 && !d_ref) return fail(&c->err, PCPF_EINVAL, "L1 needs d_ref");
     if (!d_field && !c->has_state) return fail(&c->err, PCPF_ESTATE, "no state set");
     return DISPATCH(c, reduce_impl, what, d_field, d_ref, out);
+}
+
+pcpf_status pcpf_set_timing(pcpf_ctx* c, int32_t on) {
+    if (check_ctx(c) != PCPF_OK) return PCPF_EINVAL;
+    if (c->ev_used) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        pcpf_status st = collect_times(c);
+        if (st != PCPF_OK) return st;
+    }
+    c->timing = on != 0;
+    return PCPF_OK;
+}
+
+pcpf_status pcpf_kernel_times(pcpf_ctx* c, double* ms, int64_t* launches, int32_t reset) {
+    if (check_ctx(c) != PCPF_OK) return PCPF_EINVAL;
+    for (int k = 0; k < PCPF_KT_COUNT; ++k) {
+        if (ms) ms[k] = c->kt_ms[k];
+        if (launches) launches[k] = c->kt_n[k];
+        if (reset) {
+            c->kt_ms[k] = 0.0;
+            c->kt_n[k] = 0;
+        }
+    }
+    return PCPF_OK;
 }
 
 }  // extern "C"

@@ -198,6 +198,17 @@ class Solver:
         self._chk(self.lib.pcpf_reduce(self.ctx, int(what), _ptr(f), _ptr(r), ctypes.byref(out)))
         return out.value
 
+    def set_timing(self, on=True):
+        self._chk(self.lib.pcpf_set_timing(self.ctx, 1 if on else 0))
+
+    def kernel_times(self, reset=False):
+        """{class: (total ms, launches)} of the per-launch event timing."""
+        ms = (ctypes.c_double * 4)()
+        n = (ctypes.c_int64 * 4)()
+        self._chk(self.lib.pcpf_kernel_times(self.ctx, ms, n, 1 if reset else 0))
+        names = ("grad_flux", "update", "pc_grad_flux", "pc_update")
+        return {k: (ms[i], n[i]) for i, k in enumerate(names)}
+
     def mass(self, field=None) -> float:
         return self.reduce(REDUCE_MASS, field)
 
