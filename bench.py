@@ -155,6 +155,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=60)
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path "
@@ -174,6 +176,15 @@ def main():
     phi0 = W.ic_phi(coords, cfg.centre, cfg.radius, cfg.params.eps_w)
     K, Wm = args.steps, args.warmup
     log(f"[bench] {cfg.name}: E={cfg.nelem} N_u={cfg.nupts} DOF={cfg.dof} steps={K} warmup={Wm}")
+
+    if args.copy_mb > 0:
+        # a plain copy of known size: reads and writes copy_mb MiB once each
+        src = torch.ones(args.copy_mb << 18, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     s64, wall64, wall64_ev, kt64, pc64, phi64 = run_form(cfg, mesh, "fp64", K, Wm, phi0)
     value = cfg.dof * 4 * K / wall64

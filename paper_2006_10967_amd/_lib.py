@@ -6,7 +6,7 @@ import os
 import re
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpcpf.so")
+LIB_PATH = os.environ.get("PCPF_LIBRARY") or os.path.join(HERE, "libpcpf.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "pcpf.h")
 
 PCPF_OK, PCPF_EINVAL, PCPF_EDEVICE, PCPF_EUNSUPPORTED, PCPF_ESTATE, PCPF_ENONFINITE = range(6)

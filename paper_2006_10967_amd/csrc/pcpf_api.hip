@@ -245,7 +245,7 @@ pcpf_status check_geometry(const pcpf_mesh* m, const MeshInfo& mi, std::string* 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t un, us, acc, P, Fp, Fbm, Tm, sgn, geo, det64, w64, nbr, ops, flag, partial, red, res;
+    size_t un, us, acc, P, Fp, Fm, Tp, sgn, geo, det64, w64, nbr, ops, flag, partial, red, res;
     size_t total;
 };
 
@@ -267,8 +267,8 @@ Layout layout(const MeshInfo& mi, int precision) {
     L.acc = take(state);
     L.P = take(state);
     L.Fp = take(face);
-    L.Fbm = take(face);
-    L.Tm = take(face);
+    L.Fm = take(face);
+    L.Tp = take(face);
     L.sgn = take(E * mi.nu * r);
     L.geo = take(E * geo * r);
     L.det64 = take(E * 8);
@@ -300,6 +300,7 @@ struct pcpf_ctx {
     int64_t step = 0;
     bool has_state = false, has_psi = false, has_sign = false;
     bool trace_ok[2] = {false, false};
+    bool axis = false;     // every element axis-aligned (diagonal J)
     std::string err = "no error";
     // per-launch event timing (pcpf_set_timing)
     bool timing = false;
@@ -379,8 +380,8 @@ GFArgs<R> gf_args(const Ctx<R>& C, const R* u0, const R* u1, double t) {
     for (int v = 0; v < 2; ++v) {
         a.P[v] = C.plane(c->L.P, v);
         a.Fp[v] = C.fplane(c->L.Fp, v);
-        a.Fbm[v] = C.fplane(c->L.Fbm, v);
-        a.Tm[v] = C.fplane(c->L.Tm, v);
+        a.Fm[v] = C.fplane(c->L.Fm, v);
+        a.Tp[v] = C.fplane(c->L.Tp, v);
     }
     a.geo = C.template at<R>(c->L.geo);
     a.nbr = C.template at<int32_t>(c->L.nbr);
@@ -389,6 +390,7 @@ GFArgs<R> gf_args(const Ctx<R>& C, const R* u0, const R* u1, double t) {
     a.out = nullptr;
     a.E = c->mi.E;
     a.ph = phys<R>(c->prm, t);
+    a.axis = c->axis ? 1 : 0;
     return a;
 }
 
@@ -398,8 +400,8 @@ void psi_only(GFArgs<R>& a) {
     a.u[0] = a.u[1];
     a.P[0] = a.P[1];
     a.Fp[0] = a.Fp[1];
-    a.Fbm[0] = a.Fbm[1];
-    a.Tm[0] = a.Tm[1];
+    a.Fm[0] = a.Fm[1];
+    a.Tp[0] = a.Tp[1];
 }
 
 template <typename R>
@@ -409,12 +411,12 @@ UPArgs<R> up_args(const Ctx<R>& C) {
     for (int v = 0; v < 2; ++v) {
         a.P[v] = C.plane(c->L.P, v);
         a.Fp[v] = C.fplane(c->L.Fp, v);
-        a.Fbm[v] = C.fplane(c->L.Fbm, v);
+        a.Fm[v] = C.fplane(c->L.Fm, v);
         a.un[v] = C.plane(c->L.un, v);
         a.acc[v] = C.plane(c->L.acc, v);
         a.us[v] = C.plane(c->L.us, v);
         a.res[v] = nullptr;
-        a.Tm[v] = C.fplane(c->L.Tm, v);
+        a.Tp[v] = C.fplane(c->L.Tp, v);
     }
     a.geo = C.template at<R>(c->L.geo);
     a.nbr = C.template at<int32_t>(c->L.nbr);
@@ -428,11 +430,11 @@ template <typename R>
 void up_psi_only(UPArgs<R>& a) {
     a.P[0] = a.P[1];
     a.Fp[0] = a.Fp[1];
-    a.Fbm[0] = a.Fbm[1];
+    a.Fm[0] = a.Fm[1];
     a.un[0] = a.un[1];
     a.acc[0] = a.acc[1];
     a.us[0] = a.us[1];
-    a.Tm[0] = a.Tm[1];
+    a.Tp[0] = a.Tp[1];
 }
 
 template <typename R>
@@ -440,11 +442,12 @@ pcpf_status launch_status(pcpf_ctx* c) {
     return hip_check(c, hipGetLastError(), "kernel launch");
 }
 
-// Run launch() between two recorded events when timing is on.
+// Run launch(ev0, ev1): with timing on, the dispatch records the two events at kernel start
+// and end (hipExtLaunchKernelGGL), so their difference is the kernel's execution time.
 template <typename F>
 pcpf_status timed(pcpf_ctx* c, int kind, F&& launch) {
     if (!c->timing) {
-        launch();
+        launch(nullptr, nullptr);
         return PCPF_OK;
     }
     while (c->events.size() < c->ev_used + 2) {
@@ -452,9 +455,7 @@ pcpf_status timed(pcpf_ctx* c, int kind, F&& launch) {
         HIPCHK(c, hipEventCreate(&e));
         c->events.push_back(e);
     }
-    HIPCHK(c, hipEventRecord(c->events[c->ev_used], c->stream));
-    launch();
-    HIPCHK(c, hipEventRecord(c->events[c->ev_used + 1], c->stream));
+    launch(c->events[c->ev_used], c->events[c->ev_used + 1]);
     c->ev_kind.push_back(kind);
     c->ev_used += 2;
     return PCPF_OK;
@@ -475,7 +476,7 @@ pcpf_status collect_times(pcpf_ctx* c) {
 
 #define TIMED(c, kind, stmt)                                               \
     do {                                                                   \
-        pcpf_status _t = timed((c), (kind), [&]() { stmt; });              \
+        pcpf_status _t = timed((c), (kind), [&](hipEvent_t ev0_, hipEvent_t ev1_) { stmt; }); \
         if (_t != PCPF_OK) return _t;                                      \
     } while (0)
 
@@ -489,10 +490,11 @@ pcpf_status refresh_traces(const Ctx<R>& C) {
     for (int v = 0; v < 2; ++v) {
         if (c->trace_ok[v]) continue;
         a.u[nv] = C.plane(c->L.un, v);
-        a.Tm[nv] = C.fplane(c->L.Tm, v);
+        a.Tp[nv] = C.fplane(c->L.Tp, v);
         ++nv;
     }
     a.ops = C.template at<R>(c->L.ops);
+    a.nbr = C.template at<int32_t>(c->L.nbr);
     a.E = c->mi.E;
     C.Lk().trace(nv, a, c->stream);
     c->trace_ok[0] = c->trace_ok[1] = true;
@@ -514,7 +516,8 @@ pcpf_status precondition_impl(const Ctx<R>& C, int iters) {
     {
         TRArgs<R> a{};
         a.u[0] = psi;
-        a.Tm[0] = C.fplane(c->L.Tm, 1);
+        a.Tp[0] = C.fplane(c->L.Tp, 1);
+        a.nbr = C.template at<int32_t>(c->L.nbr);
         a.ops = C.template at<R>(c->L.ops);
         a.E = c->mi.E;
         C.Lk().trace(1, a, c->stream);
@@ -524,7 +527,7 @@ pcpf_status precondition_impl(const Ctx<R>& C, int iters) {
         GFArgs<R> a = gf_args<R>(C, phi, psi, c->t);
         psi_only(a);
         a.out = C.template at<R>(c->L.sgn);
-        C.Lk().grad_flux(GF_SIGN, 1, a, c->stream);
+        C.Lk().grad_flux(GF_SIGN, 1, a, c->stream, nullptr, nullptr);
     }
     c->has_sign = true;
     c->has_psi = true;
@@ -535,14 +538,14 @@ pcpf_status precondition_impl(const Ctx<R>& C, int iters) {
             GFArgs<R> g = gf_args<R>(C, uin, uin, c->t);
             psi_only(g);
             g.u[0] = uin;
-            TIMED(c, PCPF_KT_PC_GRAD_FLUX, C.Lk().grad_flux(GF_PRECOND, 1, g, c->stream));
+            TIMED(c, PCPF_KT_PC_GRAD_FLUX, C.Lk().grad_flux(GF_PRECOND, 1, g, c->stream, ev0_, ev1_));
             UPArgs<R> u = up_args<R>(C);
             up_psi_only(u);
             u.first = s == 0;
             u.last = s == 3;
             u.bcoef = (R)RK_B[s];
             u.ccoef = (R)(s == 3 ? dtau : RK_C[s + 1] * dtau);
-            TIMED(c, PCPF_KT_PC_UPDATE, C.Lk().update(UP_RK, 1, u, c->stream));
+            TIMED(c, PCPF_KT_PC_UPDATE, C.Lk().update(UP_RK, 1, u, c->stream, ev0_, ev1_));
         }
     }
     c->trace_ok[1] = iters > 0;
@@ -567,13 +570,13 @@ pcpf_status step_impl(const Ctx<R>& C, double dt, int64_t nsteps) {
             const R* u0 = s == 0 ? C.plane(c->L.un, 0) : C.plane(c->L.us, 0);
             const R* u1 = s == 0 ? C.plane(c->L.un, 1) : C.plane(c->L.us, 1);
             GFArgs<R> g = gf_args<R>(C, u0, u1, ts);
-            TIMED(c, PCPF_KT_GRAD_FLUX, C.Lk().grad_flux(GF_PHYS, 2, g, c->stream));
+            TIMED(c, PCPF_KT_GRAD_FLUX, C.Lk().grad_flux(GF_PHYS, 2, g, c->stream, ev0_, ev1_));
             UPArgs<R> u = up_args<R>(C);
             u.first = s == 0;
             u.last = s == 3;
             u.bcoef = (R)RK_B[s];
             u.ccoef = (R)(s == 3 ? dt : RK_C[s + 1] * dt);
-            TIMED(c, PCPF_KT_UPDATE, C.Lk().update(UP_RK, 2, u, c->stream));
+            TIMED(c, PCPF_KT_UPDATE, C.Lk().update(UP_RK, 2, u, c->stream, ev0_, ev1_));
         }
         c->t += dt;
         c->step += 1;
@@ -600,33 +603,35 @@ pcpf_status residual_impl(const Ctx<R>& C, const void* d_phi, const void* d_psi,
         TRArgs<R> tr{};
         tr.u[0] = phi;
         tr.u[1] = psi;
-        tr.Tm[0] = C.fplane(c->L.Tm, 0);
-        tr.Tm[1] = C.fplane(c->L.Tm, 1);
+        tr.Tp[0] = C.fplane(c->L.Tp, 0);
+        tr.Tp[1] = C.fplane(c->L.Tp, 1);
+        tr.nbr = C.template at<int32_t>(c->L.nbr);
         tr.ops = C.template at<R>(c->L.ops);
         tr.E = c->mi.E;
         C.Lk().trace(2, tr, c->stream);
         GFArgs<R> g = gf_args<R>(C, phi, psi, t);
-        C.Lk().grad_flux(GF_PHYS, 2, g, c->stream);
+        C.Lk().grad_flux(GF_PHYS, 2, g, c->stream, nullptr, nullptr);
         UPArgs<R> u = up_args<R>(C);
         u.res[0] = static_cast<R*>(d_rphi);
         u.res[1] = static_cast<R*>(d_rpsi);
-        C.Lk().update(UP_RESID, 2, u, c->stream);
+        C.Lk().update(UP_RESID, 2, u, c->stream, nullptr, nullptr);
         c->trace_ok[0] = c->trace_ok[1] = false;
     } else {
         TRArgs<R> tr{};
         tr.u[0] = psi;
-        tr.Tm[0] = C.fplane(c->L.Tm, 1);
+        tr.Tp[0] = C.fplane(c->L.Tp, 1);
+        tr.nbr = C.template at<int32_t>(c->L.nbr);
         tr.ops = C.template at<R>(c->L.ops);
         tr.E = c->mi.E;
         C.Lk().trace(1, tr, c->stream);
         GFArgs<R> g = gf_args<R>(C, psi, psi, t);
         psi_only(g);
         g.u[0] = psi;
-        C.Lk().grad_flux(GF_PRECOND, 1, g, c->stream);
+        C.Lk().grad_flux(GF_PRECOND, 1, g, c->stream, nullptr, nullptr);
         UPArgs<R> u = up_args<R>(C);
         up_psi_only(u);
         u.res[0] = static_cast<R*>(d_rpsi);
-        C.Lk().update(UP_RESID, 1, u, c->stream);
+        C.Lk().update(UP_RESID, 1, u, c->stream, nullptr, nullptr);
         c->trace_ok[1] = false;
     }
     return launch_status<R>(c);
@@ -638,7 +643,7 @@ pcpf_status sensor_impl(const Ctx<R>& C, const void* d_psi, void* d_nu) {
     GFArgs<R> g = gf_args<R>(C, static_cast<const R*>(d_psi), static_cast<const R*>(d_psi),
                              c->t);
     g.out = static_cast<R*>(d_nu);
-    C.Lk().grad_flux(GF_SENSOR, 1, g, c->stream);
+    C.Lk().grad_flux(GF_SENSOR, 1, g, c->stream, nullptr, nullptr);
     return launch_status<R>(c);
 }
 
@@ -687,7 +692,8 @@ pcpf_status upload(pcpf_ctx* c, const pcpf_mesh* m) {
         g[d + 2 * d * d] = (R)det;
         det64[e] = det;
     }
-    // operator block: D1, DH = D1 - cp (x) lp + cm (x) lm, VINV, lm, lp, cm, cp, xi, w
+    // operator block: D1, DH = D1 - cp (x) lp + cm (x) lm, VINV, DT = D1 - cp (x) lp, lm, lp,
+    // cm, cp, xi, w
     std::vector<R> ops(ops_size(n));
     for (int a = 0; a < n; ++a)
         for (int b = 0; b < n; ++b) {
@@ -696,6 +702,7 @@ pcpf_status upload(pcpf_ctx* c, const pcpf_mesh* m) {
             ops[op_dh(n) + a * n + b] =
                 (R)(d1 - m->cplus[a] * m->lplus[b] + m->cminus[a] * m->lminus[b]);
             ops[op_vinv(n) + a * n + b] = (R)m->vinv[a * n + b];
+            ops[op_dt(n) + a * n + b] = (R)(d1 - m->cplus[a] * m->lplus[b]);
         }
     for (int a = 0; a < n; ++a) {
         ops[op_lm(n) + a] = (R)m->lminus[a];
@@ -716,8 +723,8 @@ pcpf_status upload(pcpf_ctx* c, const pcpf_mesh* m) {
                              hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(C.template at<R>(c->L.ops), ops.data(), ops.size() * sizeof(R),
                              hipMemcpyHostToDevice, c->stream));
-    // Fbm is read only on boundary faces, but keep it defined
-    HIPCHK(c, hipMemsetAsync(c->ws + c->L.Fbm, 0, c->L.Tm - c->L.Fbm, c->stream));
+    // face buffers start defined (boundary + face slots of Tp are never written)
+    HIPCHK(c, hipMemsetAsync(c->ws + c->L.Fp, 0, c->L.sgn - c->L.Fp, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return PCPF_OK;
 }
@@ -815,6 +822,11 @@ pcpf_status pcpf_create(const pcpf_mesh* m, const pcpf_params* p, void* d_ws, si
     c->stream = static_cast<hipStream_t>(stream);
     c->ws = static_cast<char*>(d_ws);
     c->L = L;
+    c->axis = true;
+    for (int64_t e = 0; e < mi.E && c->axis; ++e)
+        for (int i = 0; i < mi.d; ++i)
+            for (int j = 0; j < mi.d; ++j)
+                if (i != j && m->jac[(e * mi.d + i) * mi.d + j] != 0.0) c->axis = false;
     bool ok = p->precision == PCPF_FP32 ? get_launchers<float>(mi.d, mi.p, &c->L32)
                                         : get_launchers<double>(mi.d, mi.p, &c->L64);
     if (!ok) {

@@ -12,6 +12,17 @@ namespace pcpf {
 
 constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 
+// Lane utilisation (per mille) of nt-thread blocks holding whole elements of nu points.
+constexpr int lane_util(int nu, int nt) { return nt >= nu ? (nt / nu) * nu * 1000 / nt : 0; }
+// Smallest block (64, 128 or 256 threads) that keeps >= 90% of the lanes busy, else the
+// best of the three: small blocks give fine-grained scheduling and cheap barriers.
+constexpr int pick_nt(int nu) {
+    return lane_util(nu, 64) >= 900    ? 64
+           : lane_util(nu, 128) >= 900 ? 128
+           : lane_util(nu, 256) >= 900 ? 256
+           : (lane_util(nu, 128) >= lane_util(nu, 256) ? 128 : 256);
+}
+
 // Block shape of a (d, p) element: one thread per solution point, EPB elements per block.
 template <int D, int P>
 struct Shape {
@@ -19,24 +30,30 @@ struct Shape {
     static constexpr int NU = ipow(N, D);
     static constexpr int NFA = ipow(N, D - 1);
     static constexpr int NF = 2 * D * NFA;
-    static constexpr int EPB = (256 / NU) > 0 ? (256 / NU) : 1;
-    static constexpr int NT = ((EPB * NU + 63) / 64) * 64;
+    static constexpr int NT = pick_nt(NU);
+    static constexpr int EPB = NT / NU;
     static constexpr int GEO = D + 2 * D * D + 1;   // x0[D], J[D][D], Jinv[D][D], detJ
 };
 
 // Operator block (compute type), n = p + 1:
-//   D1[n*n] (nodal derivative), DH[n*n] (derivative minus boundary correction of the
-//   discontinuous normal flux), VINV[n*n], lm[n], lp[n], cm[n], cp[n], xi[n], w[n]
-constexpr int ops_size(int n) { return 3 * n * n + 6 * n; }
+//   D1[n*n]  nodal derivative;
+//   DH[n*n]  D1 - cp (x) lp + cm (x) lm: derivative minus the lifted discontinuous normal
+//            flux of both ends (volume part of the corrected divergence);
+//   DT[n*n]  D1 - cp (x) lp: derivative minus the lifted own trace of the + end (with the
+//            neighbour's trace lifted separately this is the corrected gradient of a line
+//            whose + face has a neighbour);
+//   VINV[n*n], lm[n], lp[n], cm[n], cp[n], xi[n], w[n]
+constexpr int ops_size(int n) { return 4 * n * n + 6 * n; }
 constexpr int OP_D1 = 0;
 constexpr int op_dh(int n) { return n * n; }
 constexpr int op_vinv(int n) { return 2 * n * n; }
-constexpr int op_lm(int n) { return 3 * n * n; }
-constexpr int op_lp(int n) { return 3 * n * n + n; }
-constexpr int op_cm(int n) { return 3 * n * n + 2 * n; }
-constexpr int op_cp(int n) { return 3 * n * n + 3 * n; }
-constexpr int op_xi(int n) { return 3 * n * n + 4 * n; }
-constexpr int op_w(int n) { return 3 * n * n + 5 * n; }
+constexpr int op_dt(int n) { return 3 * n * n; }
+constexpr int op_lm(int n) { return 4 * n * n; }
+constexpr int op_lp(int n) { return 4 * n * n + n; }
+constexpr int op_cm(int n) { return 4 * n * n + 2 * n; }
+constexpr int op_cp(int n) { return 4 * n * n + 3 * n; }
+constexpr int op_xi(int n) { return 4 * n * n + 4 * n; }
+constexpr int op_w(int n) { return 4 * n * n + 5 * n; }
 
 // kernel-side physics parameters (compute type)
 template <typename R>
@@ -54,9 +71,9 @@ template <typename R>
 struct GFArgs {
     const R* u[2];       // stage input per variable ([E][NU])
     R* P[2];             // partial divergence per variable
-    R* Fp[2];            // common flux on + faces   [E][D][NFA]
-    R* Fbm[2];           // common flux on boundary - faces [E][D][NFA]
-    const R* Tm[2];      // traces on - faces        [E][D][NFA]
+    R* Fp[2];            // common flux on the own + faces             [E][D][NFA]
+    R* Fm[2];            // common flux on - faces (pushed by the owner) [E][D][NFA]
+    const R* Tp[2];      // neighbour traces on the own + faces (pushed) [E][D][NFA]
     const R* geo;        // [E][GEO]
     const int32_t* nbr;  // [E][2D]
     const R* ops;
@@ -64,6 +81,8 @@ struct GFArgs {
     R* out;              // sign (GF_SIGN) or nu (GF_SENSOR)
     int64_t E;
     Phys<R> ph;
+    int axis;            // every element axis-aligned (diagonal J): diagonal-Jacobian
+                         // arithmetic and velocity from per-element 1D sin/cos tables
 };
 
 // update kernel kinds
@@ -73,12 +92,12 @@ template <typename R>
 struct UPArgs {
     const R* P[2];
     const R* Fp[2];
-    const R* Fbm[2];
+    const R* Fm[2];
     R* un[2];            // u_n (read; written on the last stage)
     R* acc[2];           // RK accumulator
     R* us[2];            // next stage input (written on stages 0-2)
     R* res[2];           // residual output (UP_RESID)
-    R* Tm[2];            // - face traces of the next stage input
+    R* Tp[2];            // - face traces of the next stage input, pushed to the owners
     const R* geo;
     const int32_t* nbr;
     const R* ops;
@@ -92,7 +111,8 @@ struct UPArgs {
 template <typename R>
 struct TRArgs {
     const R* u[2];
-    R* Tm[2];
+    R* Tp[2];
+    const int32_t* nbr;
     const R* ops;
     int64_t E;
 };
@@ -112,8 +132,11 @@ struct RDArgs {
 template <typename R>
 struct Launchers {
     int epb, nt, ngeo;
-    void (*grad_flux)(int mode, int nvar, const GFArgs<R>&, hipStream_t);
-    void (*update)(int kind, int nvar, const UPArgs<R>&, hipStream_t);
+    // ev0/ev1 (may be null): events the dispatch itself records at kernel start and end
+    void (*grad_flux)(int mode, int nvar, const GFArgs<R>&, hipStream_t, hipEvent_t ev0,
+                      hipEvent_t ev1);
+    void (*update)(int kind, int nvar, const UPArgs<R>&, hipStream_t, hipEvent_t ev0,
+                   hipEvent_t ev1);
     void (*trace)(int nvar, const TRArgs<R>&, hipStream_t);
     void (*reduce)(const RDArgs<R>&, int nblocks, hipStream_t);
 };

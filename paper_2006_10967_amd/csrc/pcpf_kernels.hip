@@ -11,10 +11,15 @@
 // LDG orientation (§3.1 Step 2 with beta = +-1/2): the element on the - side of a face
 // owns it. Its common solution is the neighbour's trace (so only + faces carry a jump in
 // the corrected gradient), and it computes the common normal flux (Step 5) from its own
-// viscous flux. Hence only two fields cross element boundaries per stage: the traces on
-// - faces (read by the owner) and the common flux on + faces (read back by the neighbour
-// with the opposite sign). Boundary faces (no neighbour) use the ghost state B(u) = u,
-// B(q) = q of §3.3 and are computed by the element itself.
+// viscous flux. Hence only two fields cross element boundaries per stage, and both are
+// pushed by their producer into the consumer's own slots, so that every load of both
+// kernels is indexed by the loading element: the traces of - faces (written by update
+// into the owner's + face slots Tp) and the common flux (written by grad_flux into its own
+// + face slots Fp and, negated, into the neighbour's - face slots Fm). Boundary faces (no
+// neighbour) use the ghost state B(u) = u, B(q) = q of §3.3 and are computed by the
+// element itself.
+#include <hip/hip_ext.h>
+
 #include <cmath>
 
 #include "pcpf_internal.h"
@@ -32,6 +37,7 @@ struct Math<double> {
     __device__ static double log10_(double x) { return ::log10(x); }
     __device__ static double sinpi_(double x) { return ::sinpi(x); }
     __device__ static double fabs_(double x) { return ::fabs(x); }
+    __device__ static double rsqrt_(double x) { return ::rsqrt(x); }
 };
 template <>
 struct Math<float> {
@@ -41,6 +47,7 @@ struct Math<float> {
     __device__ static float log10_(float x) { return ::log10f(x); }
     __device__ static float sinpi_(float x) { return ::sinpif(x); }
     __device__ static float fabs_(float x) { return ::fabsf(x); }
+    __device__ static float rsqrt_(float x) { return ::rsqrtf(x); }
 };
 
 template <int N>
@@ -112,6 +119,21 @@ __device__ __forceinline__ void velocity(const Phys<R>& ph, const R (&x)[D], R (
     }
 }
 
+// v(x, t) for the fields without trigonometric factors (uniform, rotation).
+template <typename R, int D>
+__device__ __forceinline__ void velocity_lin(const Phys<R>& ph, const R (&x)[D], R (&v)[D]) {
+    const R A = ph.ampg;
+    if (ph.vel_kind == PCPF_VEL_ROTATION) {
+        v[0] = A * (R(0.5) - x[1]);
+        v[1] = A * (x[0] - R(0.5));
+#pragma unroll
+        for (int k = 2; k < D; ++k) v[k] = R(0);
+    } else {
+#pragma unroll
+        for (int k = 0; k < D; ++k) v[k] = A * ph.u0[k];
+    }
+}
+
 template <typename R>
 __device__ __forceinline__ R visc_ramp(R e_all, R e_top, R s0, R kappa, R nu_max) {
     // §3.2: s_e = log10(<u-u^,u-u^>/<u,u>), smooth ramp of half width kappa around s0
@@ -122,6 +144,37 @@ __device__ __forceinline__ R visc_ramp(R e_all, R e_top, R s0, R kappa, R nu_max
     return R(0.5) * nu_max * (R(1) + Math<R>::sinpi_((s - s0) / (R(2) * kappa)));
 }
 
+// Velocity from the per-element (sin, cos)(pi x_k) tables of an axis-aligned element:
+// vt[(k * NTB + pos_k) * 2 + {0, 1}], pos_k the node index along k, or N / N + 1 for the
+// xi_k = -1 / +1 end of the element.
+template <typename R, int D, int NTB>
+__device__ __forceinline__ void velocity_tab(const Phys<R>& ph, const R* vt, const int (&pos)[D],
+                                             R (&v)[D]) {
+    const R A = ph.ampg;
+    R s[3], c[3];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        s[k] = vt[(k * NTB + pos[k]) * 2];
+        c[k] = vt[(k * NTB + pos[k]) * 2 + 1];
+    }
+    if (ph.vel_kind == PCPF_VEL_SINGLE_VORTEX) {
+        v[0] = A * (-(s[0] * s[0]) * (R(2) * s[1] * c[1]));
+        v[1] = A * ((R(2) * s[0] * c[0]) * (s[1] * s[1]));
+#pragma unroll
+        for (int k = 2; k < D; ++k) v[k] = R(0);
+    } else {
+        if (D == 3) {
+            const R s2x = R(2) * s[0] * c[0], s2y = R(2) * s[1] * c[1], s2z = R(2) * s[2] * c[2];
+            v[0] = A * (R(2) * (s[0] * s[0]) * s2y * s2z);
+            v[1] = A * (-s2x * (s[1] * s[1]) * s2z);
+            v[D - 1] = A * (-s2x * s2y * (s[2] * s[2]));
+        } else {
+#pragma unroll
+            for (int k = 0; k < D; ++k) v[k] = R(0);
+        }
+    }
+}
+
 // ------------------------------------------------------------------------------------
 // grad_flux: Steps 1-5 for the elements of one block.
 //   GF_PHYS     u = [phi, psi]: corrected gradients, fluxes at solution points, partial
@@ -130,9 +183,25 @@ __device__ __forceinline__ R visc_ramp(R e_all, R e_top, R s0, R kappa, R nu_max
 //               P = sum_k DH_k g~_k - |J| S, common fluxes on owned faces.
 //   GF_SIGN     psi0 only: smeared sign tanh(psi0 / max(|grad psi0|, delta_g)).
 //   GF_SENSOR   psi only: the element viscosity nu_e.
+// AXIS: every element is axis-aligned (diagonal J): the metric terms reduce to one
+// product per component, face normals are +-e_k, and trigonometric velocity fields come
+// from per-element tables of sin/cos(pi x_k) at the n node positions and both ends.
+// Phases: A loads (state, operators, geometry, neighbour traces, face normals, velocity
+// tables) | B corrected gradient q and fluxes f~ at solution points -> LDS | C common
+// fluxes on owned face points -> global, and P = sum_k DH_k f~_k -> global.
 // ------------------------------------------------------------------------------------
-template <typename R, int D, int P, int MODE>
-__global__ __launch_bounds__((Shape<D, P>::NT)) void k_grad_flux(GFArgs<R> a) {
+// Occupancy target (waves per SIMD) of the physical grad_flux kernel; 0 leaves the
+// register budget to the compiler.
+#ifndef PCPF_GF_WAVES
+#define PCPF_GF_WAVES 0
+#endif
+
+template <typename R, int D, int P, int MODE, bool AXIS>
+__global__ __launch_bounds__((Shape<D, P>::NT))
+#if PCPF_GF_WAVES > 0
+__attribute__((amdgpu_waves_per_eu(PCPF_GF_WAVES)))
+#endif
+void k_grad_flux(GFArgs<R> a) {
     using S = Shape<D, P>;
     constexpr int N = S::N, NU = S::NU, NFA = S::NFA, EPB = S::EPB, NT = S::NT, G = S::GEO;
     constexpr int V = (MODE == GF_PHYS) ? 2 : 1;
@@ -140,30 +209,28 @@ __global__ __launch_bounds__((Shape<D, P>::NT)) void k_grad_flux(GFArgs<R> a) {
     constexpr bool FLUX = (MODE == GF_PHYS || MODE == GF_PRECOND);
     constexpr bool SENS = (MODE == GF_PRECOND || MODE == GF_SENSOR);
     constexpr bool GRAD = (MODE != GF_SENSOR);
-    constexpr int NFE = 2 * D * NFA;     // face points per element
+    constexpr bool TAB = (MODE == GF_PHYS) && AXIS;      // velocity tables possible
+    constexpr int NPF = D * NFA;                         // points on the + faces of one element
+    constexpr int NTB = N + 2;                           // table positions per axis
+    constexpr int XST = EPB * NU;                        // stride of one field in s_x / s_f
+    constexpr int NX = (V * D > 2 ? V * D : 2) * XST;
+    constexpr int FI = (2 * EPB * NPF + NT - 1) / NT;    // face items per thread
     using M = Math<R>;
 
     __shared__ R s_ops[NOPS];
     __shared__ R s_geo[EPB * G];
     __shared__ R s_u[V][EPB * NU];
-    __shared__ R s_q[GRAD ? V : 1][D][GRAD ? EPB * NU : 1];
-    __shared__ R s_f[FLUX ? V : 1][D][FLUX ? EPB * NU : 1];
-    __shared__ R s_own[V][GRAD ? EPB * NFE : 1];
-    __shared__ R s_nbr[V][GRAD ? EPB * NFE : 1];
-    __shared__ R s_tmp[SENS ? 2 : 1][SENS ? EPB * NU : 1];
+    __shared__ R s_x[NX];                                // q (or sensor scratch)
+    __shared__ R s_f[FLUX ? V * D * XST : 1];            // f~ at solution points
+    __shared__ R s_nb[GRAD ? V : 1][GRAD ? EPB * NPF : 1];  // + face neighbour traces
+    __shared__ R s_vt[TAB ? EPB * D * NTB * 2 : 1];
     __shared__ R s_nu[EPB];
+    __shared__ R s_fn[FLUX ? EPB * D * (D + 1) : 1];     // + face unit normal and scale
+    __shared__ int s_nbr[EPB * 2 * D];
 
     const int tid = threadIdx.x;
     const int64_t e0 = (int64_t)blockIdx.x * EPB;
     const int nel = (int)((a.E - e0) < EPB ? (a.E - e0) : EPB);
-
-    for (int i = tid; i < NOPS; i += NT) s_ops[i] = a.ops[i];
-    for (int i = tid; i < nel * G; i += NT) s_geo[i] = a.geo[e0 * G + i];
-#pragma unroll
-    for (int v = 0; v < V; ++v)
-        for (int i = tid; i < nel * NU; i += NT) s_u[v][i] = a.u[v][e0 * NU + i];
-    __syncthreads();
-
     const bool pt = tid < nel * NU;
     const int le = tid / NU;
     const int ip = tid - le * NU;
@@ -176,14 +243,138 @@ __global__ __launch_bounds__((Shape<D, P>::NT)) void k_grad_flux(GFArgs<R> a) {
             r /= N;
         }
     }
+    const bool trig = a.ph.vel_kind == PCPF_VEL_SINGLE_VORTEX || a.ph.vel_kind == PCPF_VEL_LEVEQUE3D;
 
-    // --- sensor (§3.2): modal coefficients by one 1D transform per direction ----------
+    // ---- A: loads. Every global load of the phase is issued into registers before the
+    // first wait, then the values go to LDS. All loads are indexed by this block's own
+    // elements: the neighbours pushed their traces into this element's + face slots.
+    constexpr int I_OPS = (NOPS + NT - 1) / NT;
+    constexpr int I_GEO = (EPB * G + NT - 1) / NT;
+    constexpr int I_NBR = (EPB * 2 * D + NT - 1) / NT;
+    constexpr int I_U = (EPB * NU + NT - 1) / NT;
+    constexpr int I_NB = (EPB * NPF + NT - 1) / NT;
+    constexpr int I_TB = TAB ? (EPB * D * NTB + NT - 1) / NT : 1;
+    R r_ops[I_OPS], r_geo[I_GEO], r_u[V][I_U];
+    int32_t r_nbr[I_NBR];
+#pragma unroll
+    for (int j = 0; j < I_OPS; ++j) {
+        const int i = tid + j * NT;
+        r_ops[j] = (i < NOPS) ? a.ops[i] : R(0);
+    }
+#pragma unroll
+    for (int j = 0; j < I_GEO; ++j) {
+        const int i = tid + j * NT;
+        r_geo[j] = (i < nel * G) ? a.geo[e0 * G + i] : R(0);
+    }
+#pragma unroll
+    for (int j = 0; j < I_NBR; ++j) {
+        const int i = tid + j * NT;
+        r_nbr[j] = (i < nel * 2 * D) ? a.nbr[e0 * 2 * D + i] : -1;
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+        for (int j = 0; j < I_U; ++j) {
+            const int i = tid + j * NT;
+            r_u[v][j] = (i < nel * NU) ? a.u[v][e0 * NU + i] : R(0);
+        }
+    // + face normal inputs (row k of J^-1 and |J|) of this thread's (element, face)
+    R r_ji[FLUX ? D : 1], r_det = R(1);
+    const bool fn_thread = FLUX && tid < nel * D;
+    if constexpr (FLUX) {
+        if (fn_thread) {
+            const int el = tid / D, k = tid - el * D;
+            const R* gg = a.geo + (e0 + el) * G;
+#pragma unroll
+            for (int i = 0; i < D; ++i) r_ji[i] = gg[D + D * D + k * D + i];
+            r_det = gg[D + 2 * D * D];
+        }
+    }
+    // velocity-table inputs: x0_k, J_kk and the reference position of each table entry
+    R r_tx[I_TB];
+    if constexpr (TAB) {
+#pragma unroll
+        for (int j = 0; j < I_TB; ++j) {
+            const int it = tid + j * NT;
+            r_tx[j] = R(0);
+            if (trig && it < nel * D * NTB) {
+                const int el = it / (D * NTB), r = it - el * (D * NTB), k = r / NTB, jj = r - k * NTB;
+                const R* gg = a.geo + (e0 + el) * G;
+                const R xi = jj < N ? a.ops[op_xi(N) + jj] : (jj == N ? R(-1) : R(1));
+                r_tx[j] = gg[k] + gg[D + k * D + k] * (xi + R(1));
+            }
+        }
+    }
+    // neighbour traces on the + faces, pushed here by the neighbours (boundary + face
+    // slots are zeroed when the context is created and never written)
+    R r_nb[GRAD ? I_NB : 1][V];
+    if constexpr (GRAD) {
+#pragma unroll
+        for (int j = 0; j < I_NB; ++j) {
+            const int it = tid + j * NT;
+#pragma unroll
+            for (int v = 0; v < V; ++v) r_nb[j][v] = (it < nel * NPF) ? a.Tp[v][e0 * NPF + it] : R(0);
+        }
+    }
+    // registers -> LDS
+#pragma unroll
+    for (int j = 0; j < I_OPS; ++j)
+        if (tid + j * NT < NOPS) s_ops[tid + j * NT] = r_ops[j];
+#pragma unroll
+    for (int j = 0; j < I_GEO; ++j)
+        if (tid + j * NT < nel * G) s_geo[tid + j * NT] = r_geo[j];
+#pragma unroll
+    for (int j = 0; j < I_NBR; ++j)
+        if (tid + j * NT < nel * 2 * D) s_nbr[tid + j * NT] = r_nbr[j];
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+        for (int j = 0; j < I_U; ++j)
+            if (tid + j * NT < nel * NU) s_u[v][tid + j * NT] = r_u[v][j];
+    if constexpr (GRAD) {
+#pragma unroll
+        for (int j = 0; j < I_NB; ++j)
+            if (tid + j * NT < nel * NPF)
+#pragma unroll
+                for (int v = 0; v < V; ++v) s_nb[v][tid + j * NT] = r_nb[j][v];
+    }
+    // outward unit normal n = J^-T e_k / |J^-T e_k| and scale |J| |J^-T e_k| of face +k
+    if constexpr (FLUX) {
+        if (fn_thread) {
+            R mag2 = R(0);
+#pragma unroll
+            for (int i = 0; i < D; ++i) mag2 += r_ji[i] * r_ji[i];
+            const R mag = M::sqrt_(mag2);
+            R* fn = &s_fn[tid * (D + 1)];
+#pragma unroll
+            for (int i = 0; i < D; ++i) fn[i] = r_ji[i] / mag;
+            fn[D] = r_det * mag;
+        }
+    }
+    if constexpr (TAB) {
+        // one sincospi per line position of each axis
+        if (trig) {
+#pragma unroll
+            for (int j = 0; j < I_TB; ++j) {
+                const int it = tid + j * NT;
+                if (it < nel * D * NTB) {
+                    R sn, cs;
+                    M::sincospi_(r_tx[j], &sn, &cs);
+                    s_vt[2 * it] = sn;
+                    s_vt[2 * it + 1] = cs;
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- sensor (§3.2): modal coefficients by one 1D transform per direction -----------
     if constexpr (SENS) {
         const R* VI = &s_ops[op_vinv(N)];
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            const R* src = (k == 0) ? s_u[0] : s_tmp[(k - 1) & 1];
-            R* dst = s_tmp[k & 1];
+            const R* src = (k == 0) ? s_u[0] : s_x + ((k - 1) & 1) * XST;
+            R* dst = s_x + (k & 1) * XST;
             if (pt) {
                 R acc = R(0);
                 const int b0 = le * NU + ip - mi[k] * st<N>(k);
@@ -193,7 +384,7 @@ __global__ __launch_bounds__((Shape<D, P>::NT)) void k_grad_flux(GFArgs<R> a) {
             }
             __syncthreads();
         }
-        const R* chi = s_tmp[(D - 1) & 1];
+        const R* chi = s_x + ((D - 1) & 1) * XST;
         if (tid < nel) {
             R ea = R(0), et = R(0);
             for (int i = 0; i < NU; ++i) {
@@ -216,37 +407,12 @@ __global__ __launch_bounds__((Shape<D, P>::NT)) void k_grad_flux(GFArgs<R> a) {
     }
 
     if constexpr (GRAD) {
-        // --- Step 1 + 2: traces on owned faces and the neighbour's traces ------------------
-        for (int it = tid; it < nel * NFE; it += NT) {
-            const int el = it / NFE;
-            const int r = it - el * NFE;
-            const int f = r / NFA;
-            const int t = r - f * NFA;
-            const int k = f >> 1, s = f & 1;
-            const int32_t en = a.nbr[(e0 + el) * 2 * D + f];
-            if (s == 0 && en >= 0) continue;
-            const int base = el * NU + face_base<D, N>(k, t);
-            const R* l = &s_ops[s ? op_lp(N) : op_lm(N)];
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-                R own = R(0);
-#pragma unroll
-                for (int q = 0; q < N; ++q) own += l[q] * s_u[v][base + q * st<N>(k)];
-                const R nb = (en >= 0) ? a.Tm[v][((int64_t)en * D + k) * NFA + t] : own;
-                s_own[v][it] = own;
-                s_nbr[v][it] = nb;
-            }
-        }
-        __syncthreads();
-
-        // --- Step 3 (+ Step 4): corrected gradient and fluxes at solution points -----------
-        R det = R(1);
+        // ---- B: corrected gradient (Steps 1-3) and fluxes at solution points (Step 4) ---
         R Sdet = R(0);
         if (pt) {
             const R* gg = &s_geo[le * G];
-            det = gg[D + 2 * D * D];
-            const R* Ji = gg + D + D * D;        // Jinv[k][i] = Ji[k*D + i]
-            const R* D1 = &s_ops[OP_D1];
+            const R det = gg[D + 2 * D * D];
+            const R* Ji = gg + D + D * D;            // Jinv[k][i] = Ji[k*D + i]
             const R* cp = &s_ops[op_cp(N)];
             R q[V][D];
 #pragma unroll
@@ -254,21 +420,30 @@ __global__ __launch_bounds__((Shape<D, P>::NT)) void k_grad_flux(GFArgs<R> a) {
                 R qt[D];
 #pragma unroll
                 for (int k = 0; k < D; ++k) {
+                    // + face with a neighbour: the LDG jump (nb - own trace) is lifted; the
+                    // own-trace part is folded into DT = D1 - cp (x) lp
+                    const bool hk = s_nbr[le * 2 * D + 2 * k + 1] >= 0;
+                    const R* Dk = &s_ops[hk ? op_dt(N) : OP_D1] + mi[k] * N;
                     const int b0 = le * NU + ip - mi[k] * st<N>(k);
                     R acc = R(0);
 #pragma unroll
-                    for (int b = 0; b < N; ++b) acc += D1[mi[k] * N + b] * s_u[v][b0 + b * st<N>(k)];
-                    const int jx = le * NFE + (2 * k + 1) * NFA + tang_index<D, N>(k, mi);
-                    acc += cp[mi[k]] * (s_nbr[v][jx] - s_own[v][jx]);
+                    for (int b = 0; b < N; ++b) acc += Dk[b] * s_u[v][b0 + b * st<N>(k)];
+                    // boundary + faces: s_nb holds 0 (those slots are never written)
+                    acc += cp[mi[k]] * s_nb[v][le * NPF + k * NFA + tang_index<D, N>(k, mi)];
                     qt[k] = acc;
                 }
 #pragma unroll
                 for (int i = 0; i < D; ++i) {
-                    R acc = R(0);
+                    R acc;
+                    if constexpr (AXIS) {
+                        acc = Ji[i * D + i] * qt[i];
+                    } else {
+                        acc = R(0);
 #pragma unroll
-                    for (int k = 0; k < D; ++k) acc += Ji[k * D + i] * qt[k];
+                        for (int k = 0; k < D; ++k) acc += Ji[k * D + i] * qt[k];
+                    }
                     q[v][i] = acc;
-                    s_q[v][i][tid] = acc;
+                    s_x[(v * D + i) * XST + tid] = acc;
                 }
             }
             if constexpr (MODE == GF_SIGN) {
@@ -281,15 +456,27 @@ __global__ __launch_bounds__((Shape<D, P>::NT)) void k_grad_flux(GFArgs<R> a) {
             }
             if constexpr (MODE == GF_PHYS) {
                 const R* xi = &s_ops[op_xi(N)];
-                R x[D], vel[D];
+                R vel[D];
+                if constexpr (TAB) {
+                    if (trig) {
+                        velocity_tab<R, D, NTB>(a.ph, &s_vt[le * D * NTB * 2], mi, vel);
+                    } else {
+                        R x[D];
 #pragma unroll
-                for (int i = 0; i < D; ++i) {
-                    R acc = gg[i];
+                        for (int i = 0; i < D; ++i) x[i] = gg[i] + gg[D + i * D + i] * (xi[mi[i]] + R(1));
+                        velocity_lin<R, D>(a.ph, x, vel);
+                    }
+                } else {
+                    R x[D];
 #pragma unroll
-                    for (int j = 0; j < D; ++j) acc += gg[D + i * D + j] * (xi[mi[j]] + R(1));
-                    x[i] = acc;
+                    for (int i = 0; i < D; ++i) {
+                        R acc = gg[i];
+#pragma unroll
+                        for (int j = 0; j < D; ++j) acc += gg[D + i * D + j] * (xi[mi[j]] + R(1));
+                        x[i] = acc;
+                    }
+                    velocity<R, D>(a.ph, x, vel);
                 }
-                velocity<R, D>(a.ph, x, vel);
                 R v2 = R(0), g2 = R(0);
 #pragma unroll
                 for (int i = 0; i < D; ++i) {
@@ -298,7 +485,7 @@ __global__ __launch_bounds__((Shape<D, P>::NT)) void k_grad_flux(GFArgs<R> a) {
                 }
                 R mm = M::sqrt_(v2);
                 if (!(mm > a.ph.gamma)) mm = a.ph.gamma;
-                const R rn = R(1) / M::sqrt_(g2 + a.ph.delta_n * a.ph.delta_n);
+                const R rn = M::rsqrt_(g2 + a.ph.delta_n * a.ph.delta_n);
                 const R phi = s_u[0][tid], psi = s_u[1][tid];
                 const R sharp = a.ph.gamma * phi * (R(1) - phi) * rn;
                 R f0[D], f1[D];
@@ -310,14 +497,21 @@ __global__ __launch_bounds__((Shape<D, P>::NT)) void k_grad_flux(GFArgs<R> a) {
                 }
 #pragma unroll
                 for (int k = 0; k < D; ++k) {
-                    R a0 = R(0), a1 = R(0);
+                    R a0, a1;
+                    if constexpr (AXIS) {
+                        a0 = Ji[k * D + k] * f0[k];
+                        a1 = Ji[k * D + k] * f1[k];
+                    } else {
+                        a0 = R(0);
+                        a1 = R(0);
 #pragma unroll
-                    for (int i = 0; i < D; ++i) {
-                        a0 += Ji[k * D + i] * f0[i];
-                        a1 += Ji[k * D + i] * f1[i];
+                        for (int i = 0; i < D; ++i) {
+                            a0 += Ji[k * D + i] * f0[i];
+                            a1 += Ji[k * D + i] * f1[i];
+                        }
                     }
-                    s_f[0][k][tid] = det * a0;
-                    s_f[V - 1][k][tid] = det * a1;
+                    s_f[(0 * D + k) * XST + tid] = det * a0;
+                    s_f[((V - 1) * D + k) * XST + tid] = det * a1;
                 }
             }
             if constexpr (MODE == GF_PRECOND) {
@@ -328,17 +522,148 @@ __global__ __launch_bounds__((Shape<D, P>::NT)) void k_grad_flux(GFArgs<R> a) {
                 Sdet = det * a.sgn[(e0 + le) * NU + ip] * (R(1) - M::sqrt_(g2));
 #pragma unroll
                 for (int k = 0; k < D; ++k) {
-                    R acc = R(0);
+                    R acc;
+                    if constexpr (AXIS) {
+                        acc = Ji[k * D + k] * q[0][k];
+                    } else {
+                        acc = R(0);
 #pragma unroll
-                    for (int i = 0; i < D; ++i) acc += Ji[k * D + i] * q[0][i];
-                    s_f[0][k][tid] = -det * nu * acc;
+                        for (int i = 0; i < D; ++i) acc += Ji[k * D + i] * q[0][i];
+                    }
+                    s_f[k * XST + tid] = -det * nu * acc;
                 }
             }
         }
         if constexpr (MODE == GF_SIGN) return;
         __syncthreads();
 
-        // --- Step 6 (volume part): P = sum_k DH_k f~_k (- |J| S) ------------------------
+        // ---- C: common normal fluxes on owned face points (Step 5) ----------------------
+        // items [0, nel*NPF): + faces (owned); [nel*NPF, 2*nel*NPF): - faces, computed here
+        // only on boundaries (ghost state = interior state)
+#pragma unroll
+        for (int j = 0; j < FI; ++j) {
+            const int it = tid + j * NT;
+            if (it >= 2 * nel * NPF) continue;
+            const bool plus = it < nel * NPF;
+            const int itf = plus ? it : it - nel * NPF;
+            const int el = itf / NPF, r = itf - el * NPF, k = r / NFA, t = r - k * NFA;
+            const int s = plus ? 1 : 0;
+            const int32_t en = s_nbr[el * 2 * D + 2 * k + s];
+            if (!plus && en >= 0) continue;
+            const int64_t e = e0 + el;
+            const int base = el * NU + face_base<D, N>(k, t);
+            const R* l = &s_ops[s ? op_lp(N) : op_lm(N)];
+            const R* gg = &s_geo[el * G];
+            const R* fn = &s_fn[(el * D + k) * (D + 1)];
+            const R sc = fn[D];
+            R nrm[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) nrm[i] = s ? fn[i] : -fn[i];
+            R uL[V], uR[V], qn[V], g2 = R(0);
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                R acc = R(0);
+#pragma unroll
+                for (int q = 0; q < N; ++q) acc += l[q] * s_u[v][base + q * st<N>(k)];
+                uL[v] = acc;
+                uR[v] = (en >= 0) ? s_nb[v][el * NPF + k * NFA + t] : acc;
+                // the psi gradient at the face point enters |grad psi| of the normal
+                const bool full = (MODE == GF_PHYS && v == V - 1) || !AXIS;
+                R acc_n = R(0);
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    if (!full && i != k) continue;
+                    R qa = R(0);
+#pragma unroll
+                    for (int q = 0; q < N; ++q) qa += l[q] * s_x[(v * D + i) * XST + base + q * st<N>(k)];
+                    acc_n += qa * nrm[i];
+                    if (MODE == GF_PHYS && v == V - 1) g2 += qa * qa;
+                }
+                qn[v] = acc_n;
+            }
+            const int64_t fo = (e * D + k) * NFA + t;
+            if constexpr (MODE == GF_PHYS) {
+                const R* xi = &s_ops[op_xi(N)];
+                R vel[D];
+                int pos[D];
+                {
+                    int tt = t;
+#pragma unroll
+                    for (int m = 0; m < D; ++m) {
+                        if (m == k) {
+                            pos[m] = N + s;
+                        } else {
+                            pos[m] = tt % N;
+                            tt /= N;
+                        }
+                    }
+                }
+                if constexpr (TAB) {
+                    if (trig) {
+                        velocity_tab<R, D, NTB>(a.ph, &s_vt[el * D * NTB * 2], pos, vel);
+                    } else {
+                        R x[D];
+#pragma unroll
+                        for (int m = 0; m < D; ++m) {
+                            const R xr = (m == k) ? (s ? R(2) : R(0)) : xi[pos[m]] + R(1);
+                            x[m] = gg[m] + gg[D + m * D + m] * xr;
+                        }
+                        velocity_lin<R, D>(a.ph, x, vel);
+                    }
+                } else {
+                    R x[D];
+#pragma unroll
+                    for (int i = 0; i < D; ++i) {
+                        R acc = gg[i];
+#pragma unroll
+                        for (int m = 0; m < D; ++m) {
+                            const R xr = (m == k) ? (s ? R(2) : R(0)) : xi[pos[m]] + R(1);
+                            acc += gg[D + i * D + m] * xr;
+                        }
+                        x[i] = acc;
+                    }
+                    velocity<R, D>(a.ph, x, vel);
+                }
+                R v2 = R(0), vn = R(0);
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    v2 += vel[i] * vel[i];
+                    if (!AXIS || i == k) vn += vel[i] * nrm[i];
+                }
+                R mm = M::sqrt_(v2);
+                if (!(mm > a.ph.gamma)) mm = a.ph.gamma;
+                const R rn = M::rsqrt_(g2 + a.ph.delta_n * a.ph.delta_n);
+                const R pL = uL[0], pR = uR[0], sL = uL[1], sR = uR[1];
+                const R fvn = mm * (a.ph.eps * qn[0] - a.ph.gamma * pL * (R(1) - pL) * qn[1] * rn);
+                const R F0 = R(0.5) * (pL + pR) * vn - fvn + a.ph.tau * (pL - pR);
+                const R F1 = R(0.5) * (sL + sR) * vn + a.ph.tau * (sL - sR);
+                const R G0 = sc * F0, G1 = sc * F1;
+                if (s) {
+                    a.Fp[0][fo] = G0;
+                    a.Fp[1][fo] = G1;
+                    if (en >= 0) {
+                        // the neighbour's - face: same flux, its outward normal is -n
+                        const int64_t fn_ = ((int64_t)en * D + k) * NFA + t;
+                        a.Fm[0][fn_] = -G0;
+                        a.Fm[1][fn_] = -G1;
+                    }
+                } else {
+                    a.Fm[0][fo] = G0;
+                    a.Fm[1][fo] = G1;
+                }
+            } else {
+                const R F = -s_nu[el] * qn[0] + a.ph.tau * (uL[0] - uR[0]);
+                const R G0 = sc * F;
+                if (s) {
+                    a.Fp[0][fo] = G0;
+                    if (en >= 0) a.Fm[0][((int64_t)en * D + k) * NFA + t] = -G0;
+                } else {
+                    a.Fm[0][fo] = G0;
+                }
+            }
+        }
+
+        // ---- E: volume part of Step 6, P = sum_k DH_k f~_k (- |J| S) ---------------------
         if (pt) {
             const R* DH = &s_ops[op_dh(N)];
 #pragma unroll
@@ -348,99 +673,10 @@ __global__ __launch_bounds__((Shape<D, P>::NT)) void k_grad_flux(GFArgs<R> a) {
                 for (int k = 0; k < D; ++k) {
                     const int b0 = le * NU + ip - mi[k] * st<N>(k);
 #pragma unroll
-                    for (int b = 0; b < N; ++b) acc += DH[mi[k] * N + b] * s_f[v][k][b0 + b * st<N>(k)];
+                    for (int b = 0; b < N; ++b) acc += DH[mi[k] * N + b] * s_f[(v * D + k) * XST + b0 + b * st<N>(k)];
                 }
                 if constexpr (MODE == GF_PRECOND) acc -= Sdet;
                 a.P[v][(e0 + le) * NU + ip] = acc;
-            }
-        }
-
-        // --- Step 5: common normal fluxes on owned faces -----------------------------------
-        for (int it = tid; it < nel * NFE; it += NT) {
-            const int el = it / NFE;
-            const int r = it - el * NFE;
-            const int f = r / NFA;
-            const int t = r - f * NFA;
-            const int k = f >> 1, s = f & 1;
-            const int64_t e = e0 + el;
-            const int32_t en = a.nbr[e * 2 * D + f];
-            if (s == 0 && en >= 0) continue;
-            const int base = el * NU + face_base<D, N>(k, t);
-            const R* l = &s_ops[s ? op_lp(N) : op_lm(N)];
-            const R* gg = &s_geo[el * G];
-            const R* Ji = gg + D + D * D;
-            const R det_e = gg[D + 2 * D * D];
-            R mag2 = R(0);
-#pragma unroll
-            for (int i = 0; i < D; ++i) mag2 += Ji[k * D + i] * Ji[k * D + i];
-            const R mag = M::sqrt_(mag2);
-            const R sgn_n = s ? R(1) : R(-1);
-            R nrm[D];
-#pragma unroll
-            for (int i = 0; i < D; ++i) nrm[i] = sgn_n * Ji[k * D + i] / mag;
-            const R sc = det_e * mag;
-            R qn[V];      // own corrected gradient at the face point, dotted with n
-            R qf1[D];     // psi gradient at the face point (normal of the sharpening term)
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-                R acc_n = R(0);
-#pragma unroll
-                for (int i = 0; i < D; ++i) {
-                    R acc = R(0);
-#pragma unroll
-                    for (int q = 0; q < N; ++q) acc += l[q] * s_q[v][i][base + q * st<N>(k)];
-                    acc_n += acc * nrm[i];
-                    if (v == V - 1) qf1[i] = acc;
-                }
-                qn[v] = acc_n;
-            }
-            const int64_t fo = (e * D + k) * NFA + t;
-            if constexpr (MODE == GF_PHYS) {
-                const R* xi = &s_ops[op_xi(N)];
-                R xr[D];
-                {
-                    int tt = t;
-#pragma unroll
-                    for (int m = 0; m < D; ++m) {
-                        if (m == k) {
-                            xr[m] = s ? R(2) : R(0);
-                        } else {
-                            xr[m] = xi[tt % N] + R(1);
-                            tt /= N;
-                        }
-                    }
-                }
-                R x[D], vel[D];
-#pragma unroll
-                for (int i = 0; i < D; ++i) {
-                    R acc = gg[i];
-#pragma unroll
-                    for (int j = 0; j < D; ++j) acc += gg[D + i * D + j] * xr[j];
-                    x[i] = acc;
-                }
-                velocity<R, D>(a.ph, x, vel);
-                R v2 = R(0), vn = R(0), g2 = R(0), gn = R(0);
-#pragma unroll
-                for (int i = 0; i < D; ++i) {
-                    v2 += vel[i] * vel[i];
-                    vn += vel[i] * nrm[i];
-                    g2 += qf1[i] * qf1[i];
-                }
-                gn = qn[1];
-                R mm = M::sqrt_(v2);
-                if (!(mm > a.ph.gamma)) mm = a.ph.gamma;
-                const R pL = s_own[0][it], pR = s_nbr[0][it];
-                const R sL = s_own[1][it], sR = s_nbr[1][it];
-                const R rn = R(1) / M::sqrt_(g2 + a.ph.delta_n * a.ph.delta_n);
-                const R fvn = mm * (a.ph.eps * qn[0] - a.ph.gamma * pL * (R(1) - pL) * gn * rn);
-                const R F0 = R(0.5) * (pL + pR) * vn - fvn + a.ph.tau * (pL - pR);
-                const R F1 = R(0.5) * (sL + sR) * vn + a.ph.tau * (sL - sR);
-                (s ? a.Fp[0] : a.Fbm[0])[fo] = sc * F0;
-                (s ? a.Fp[1] : a.Fbm[1])[fo] = sc * F1;
-            } else {
-                const R sL = s_own[0][it], sR = s_nbr[0][it];
-                const R F = -s_nu[el] * qn[0] + a.ph.tau * (sL - sR);
-                (s ? a.Fp[0] : a.Fbm[0])[fo] = sc * F;
             }
         }
     }
@@ -456,19 +692,56 @@ template <typename R, int D, int P, int V, int KIND>
 __global__ __launch_bounds__((Shape<D, P>::NT)) void k_update(UPArgs<R> a) {
     using S = Shape<D, P>;
     constexpr int N = S::N, NU = S::NU, NFA = S::NFA, EPB = S::EPB, NT = S::NT, G = S::GEO;
-    constexpr int NOPS = ops_size(N);
     constexpr int NFE = 2 * D * NFA;
-    __shared__ R s_ops[NOPS];
+    __shared__ R s_c[3 * N];                 // cm, cp, lm
     __shared__ R s_F[V][EPB * NFE];
     __shared__ R s_u[V][KIND == UP_RK ? EPB * NU : 1];
-    __shared__ R s_det[EPB];
 
     const int tid = threadIdx.x;
     const int64_t e0 = (int64_t)blockIdx.x * EPB;
     const int nel = (int)((a.E - e0) < EPB ? (a.E - e0) : EPB);
-    for (int i = tid; i < NOPS; i += NT) s_ops[i] = a.ops[i];
-    if (tid < nel) s_det[tid] = a.geo[(e0 + tid) * G + D + 2 * D * D];
-    for (int it = tid; it < nel * NFE; it += NT) {
+    const bool pt = tid < nel * NU;
+    const int le = tid / NU;
+    const int ip = tid - le * NU;
+    const int64_t idx = (e0 + le) * NU + ip;
+    // every global load is issued before the first wait; all are indexed by this block's
+    // own elements (the owners pushed the - face fluxes here). The adjacency is only needed
+    // for the addresses of the trace pushes at the end.
+    constexpr int I_F = (EPB * NFE + NT - 1) / NT;
+    constexpr int NMF = D * NFA;
+    constexpr int I_T = (EPB * NMF + NT - 1) / NT;
+    int32_t r_own[KIND == UP_RK ? I_T : 1];
+    if constexpr (KIND == UP_RK) {
+#pragma unroll
+        for (int j = 0; j < I_T; ++j) {
+            const int it = tid + j * NT;
+            const int el = it / NMF, k = (it - el * NMF) / NFA;
+            r_own[j] = (it < nel * NMF) ? a.nbr[(e0 + el) * 2 * D + 2 * k] : -1;
+        }
+    }
+    R rP[V], rU[V], rA[V];
+    R det = R(1);
+    if (pt) {
+        det = a.geo[(e0 + le) * G + D + 2 * D * D];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            rP[v] = a.P[v][idx];
+            if constexpr (KIND == UP_RK) {
+                rU[v] = a.un[v][idx];
+                rA[v] = a.first ? R(0) : a.acc[v][idx];
+            }
+        }
+    }
+    R r_c[3] = {R(0), R(0), R(0)};
+    if (tid < N) {
+        r_c[0] = a.ops[op_cm(N) + tid];
+        r_c[1] = a.ops[op_cp(N) + tid];
+        r_c[2] = a.ops[op_lm(N) + tid];
+    }
+    R r_F[I_F][V];
+#pragma unroll
+    for (int j = 0; j < I_F; ++j) {
+        const int it = tid + j * NT;
         const int el = it / NFE;
         const int r = it - el * NFE;
         const int f = r / NFA;
@@ -477,23 +750,24 @@ __global__ __launch_bounds__((Shape<D, P>::NT)) void k_update(UPArgs<R> a) {
         const int64_t e = e0 + el;
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            R F;
-            if (s) {
-                F = a.Fp[v][(e * D + k) * NFA + t];
-            } else {
-                const int32_t en = a.nbr[e * 2 * D + f];
-                F = (en >= 0) ? -a.Fp[v][((int64_t)en * D + k) * NFA + t]
-                              : a.Fbm[v][(e * D + k) * NFA + t];
-            }
-            s_F[v][it] = F;
+            R F = R(0);
+            if (it < nel * NFE) F = (s ? a.Fp[v] : a.Fm[v])[(e * D + k) * NFA + t];
+            r_F[j][v] = F;
         }
     }
+    if (tid < N) {
+        s_c[tid] = r_c[0];
+        s_c[N + tid] = r_c[1];
+        s_c[2 * N + tid] = r_c[2];
+    }
+#pragma unroll
+    for (int j = 0; j < I_F; ++j)
+        if (tid + j * NT < nel * NFE)
+#pragma unroll
+            for (int v = 0; v < V; ++v) s_F[v][tid + j * NT] = r_F[j][v];
     __syncthreads();
 
-    const bool pt = tid < nel * NU;
     if (pt) {
-        const int le = tid / NU;
-        const int ip = tid - le * NU;
         int mi[D];
         {
             int r = ip;
@@ -503,32 +777,27 @@ __global__ __launch_bounds__((Shape<D, P>::NT)) void k_update(UPArgs<R> a) {
                 r /= N;
             }
         }
-        const R* cm = &s_ops[op_cm(N)];
-        const R* cp = &s_ops[op_cp(N)];
-        const int64_t idx = (e0 + le) * NU + ip;
-        const R rdet = R(1) / s_det[le];
+        const R rdet = R(1) / det;
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            R acc = a.P[v][idx];
+            R acc = rP[v];
 #pragma unroll
             for (int k = 0; k < D; ++k) {
                 const int tk = tang_index<D, N>(k, mi);
-                acc += cp[mi[k]] * s_F[v][le * NFE + (2 * k + 1) * NFA + tk]
-                     + cm[mi[k]] * s_F[v][le * NFE + (2 * k) * NFA + tk];
+                acc += s_c[N + mi[k]] * s_F[v][le * NFE + (2 * k + 1) * NFA + tk]
+                     + s_c[mi[k]] * s_F[v][le * NFE + (2 * k) * NFA + tk];
             }
             const R res = -acc * rdet;
             if constexpr (KIND == UP_RESID) {
                 a.res[v][idx] = res;
             } else {
-                const R un = a.un[v][idx];
                 R nx;
                 if (!a.last) {
-                    const R ac = (a.first ? R(0) : a.acc[v][idx]) + a.bcoef * res;
-                    a.acc[v][idx] = ac;
-                    nx = un + a.ccoef * res;
+                    a.acc[v][idx] = rA[v] + a.bcoef * res;
+                    nx = rU[v] + a.ccoef * res;
                     a.us[v][idx] = nx;
                 } else {
-                    nx = un + a.ccoef * (a.acc[v][idx] + a.bcoef * res);
+                    nx = rU[v] + a.ccoef * (rA[v] + a.bcoef * res);
                     a.un[v][idx] = nx;
                 }
                 s_u[v][tid] = nx;
@@ -539,9 +808,12 @@ __global__ __launch_bounds__((Shape<D, P>::NT)) void k_update(UPArgs<R> a) {
     }
     if constexpr (KIND == UP_RK) {
         __syncthreads();
-        const R* lm = &s_ops[op_lm(N)];
-        constexpr int NMF = D * NFA;
-        for (int it = tid; it < nel * NMF; it += NT) {
+        // - face traces of the next stage input, pushed into the owners' + face slots
+        const R* lm = &s_c[2 * N];
+#pragma unroll
+        for (int j = 0; j < I_T; ++j) {
+            const int it = tid + j * NT;
+            if (it >= nel * NMF || r_own[j] < 0) continue;
             const int el = it / NMF;
             const int r = it - el * NMF;
             const int k = r / NFA;
@@ -552,29 +824,53 @@ __global__ __launch_bounds__((Shape<D, P>::NT)) void k_update(UPArgs<R> a) {
                 R acc = R(0);
 #pragma unroll
                 for (int q = 0; q < N; ++q) acc += lm[q] * s_u[v][base + q * st<N>(k)];
-                a.Tm[v][((e0 + el) * D + k) * NFA + t] = acc;
+                a.Tp[v][((int64_t)r_own[j] * D + k) * NFA + t] = acc;
             }
         }
     }
 }
 
-// traces on - faces of a given state (after set_state / reset)
+// - face traces of a given state pushed into the owners' + face slots (after set_state /
+// reset)
 template <typename R, int D, int P, int V>
 __global__ __launch_bounds__((Shape<D, P>::NT)) void k_trace(TRArgs<R> a) {
     using S = Shape<D, P>;
     constexpr int N = S::N, NU = S::NU, NFA = S::NFA, EPB = S::EPB, NT = S::NT;
+    constexpr int NMF = D * NFA;
+    constexpr int I_T = (EPB * NMF + NT - 1) / NT;
+    constexpr int I_U = (EPB * NU + NT - 1) / NT;
     __shared__ R s_lm[N];
     __shared__ R s_u[V][EPB * NU];
     const int tid = threadIdx.x;
     const int64_t e0 = (int64_t)blockIdx.x * EPB;
     const int nel = (int)((a.E - e0) < EPB ? (a.E - e0) : EPB);
-    if (tid < N) s_lm[tid] = a.ops[op_lm(N) + tid];
+    int32_t r_own[I_T];
+#pragma unroll
+    for (int j = 0; j < I_T; ++j) {
+        const int it = tid + j * NT;
+        const int el = it / NMF, k = (it - el * NMF) / NFA;
+        r_own[j] = (it < nel * NMF) ? a.nbr[(e0 + el) * 2 * D + 2 * k] : -1;
+    }
+    R r_u[V][I_U];
 #pragma unroll
     for (int v = 0; v < V; ++v)
-        for (int i = tid; i < nel * NU; i += NT) s_u[v][i] = a.u[v][e0 * NU + i];
+#pragma unroll
+        for (int j = 0; j < I_U; ++j) {
+            const int i = tid + j * NT;
+            r_u[v][j] = (i < nel * NU) ? a.u[v][e0 * NU + i] : R(0);
+        }
+    R r_l = (tid < N) ? a.ops[op_lm(N) + tid] : R(0);
+    if (tid < N) s_lm[tid] = r_l;
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+        for (int j = 0; j < I_U; ++j)
+            if (tid + j * NT < nel * NU) s_u[v][tid + j * NT] = r_u[v][j];
     __syncthreads();
-    constexpr int NMF = D * NFA;
-    for (int it = tid; it < nel * NMF; it += NT) {
+#pragma unroll
+    for (int j = 0; j < I_T; ++j) {
+        const int it = tid + j * NT;
+        if (it >= nel * NMF || r_own[j] < 0) continue;
         const int el = it / NMF;
         const int r = it - el * NMF;
         const int k = r / NFA;
@@ -585,7 +881,7 @@ __global__ __launch_bounds__((Shape<D, P>::NT)) void k_trace(TRArgs<R> a) {
             R acc = R(0);
 #pragma unroll
             for (int q = 0; q < N; ++q) acc += s_lm[q] * s_u[v][base + q * st<N>(k)];
-            a.Tm[v][((e0 + el) * D + k) * NFA + t] = acc;
+            a.Tp[v][((int64_t)r_own[j] * D + k) * NFA + t] = acc;
         }
     }
 }
@@ -658,24 +954,36 @@ struct Impl {
     using S = Shape<D, P>;
     static unsigned grid(int64_t E) { return (unsigned)((E + S::EPB - 1) / S::EPB); }
 
-    static void grad_flux(int mode, int nvar, const GFArgs<R>& a, hipStream_t st) {
+    static void grad_flux(int mode, int nvar, const GFArgs<R>& a, hipStream_t st, hipEvent_t e0,
+                          hipEvent_t e1) {
         (void)nvar;
         const dim3 g(grid(a.E)), b(S::NT);
         switch (mode) {
-            case GF_PHYS: hipLaunchKernelGGL((k_grad_flux<R, D, P, GF_PHYS>), g, b, 0, st, a); break;
-            case GF_PRECOND: hipLaunchKernelGGL((k_grad_flux<R, D, P, GF_PRECOND>), g, b, 0, st, a); break;
-            case GF_SIGN: hipLaunchKernelGGL((k_grad_flux<R, D, P, GF_SIGN>), g, b, 0, st, a); break;
-            default: hipLaunchKernelGGL((k_grad_flux<R, D, P, GF_SENSOR>), g, b, 0, st, a); break;
+            case GF_PHYS:
+                if (a.axis)
+                    hipExtLaunchKernelGGL((k_grad_flux<R, D, P, GF_PHYS, true>), g, b, 0, st, e0, e1, 0, a);
+                else
+                    hipExtLaunchKernelGGL((k_grad_flux<R, D, P, GF_PHYS, false>), g, b, 0, st, e0, e1, 0, a);
+                break;
+            case GF_PRECOND:
+                if (a.axis)
+                    hipExtLaunchKernelGGL((k_grad_flux<R, D, P, GF_PRECOND, true>), g, b, 0, st, e0, e1, 0, a);
+                else
+                    hipExtLaunchKernelGGL((k_grad_flux<R, D, P, GF_PRECOND, false>), g, b, 0, st, e0, e1, 0, a);
+                break;
+            case GF_SIGN: hipExtLaunchKernelGGL((k_grad_flux<R, D, P, GF_SIGN, false>), g, b, 0, st, e0, e1, 0, a); break;
+            default: hipExtLaunchKernelGGL((k_grad_flux<R, D, P, GF_SENSOR, false>), g, b, 0, st, e0, e1, 0, a); break;
         }
     }
-    static void update(int kind, int nvar, const UPArgs<R>& a, hipStream_t st) {
+    static void update(int kind, int nvar, const UPArgs<R>& a, hipStream_t st, hipEvent_t e0,
+                       hipEvent_t e1) {
         const dim3 g(grid(a.E)), b(S::NT);
         if (nvar == 2) {
-            if (kind == UP_RK) hipLaunchKernelGGL((k_update<R, D, P, 2, UP_RK>), g, b, 0, st, a);
-            else hipLaunchKernelGGL((k_update<R, D, P, 2, UP_RESID>), g, b, 0, st, a);
+            if (kind == UP_RK) hipExtLaunchKernelGGL((k_update<R, D, P, 2, UP_RK>), g, b, 0, st, e0, e1, 0, a);
+            else hipExtLaunchKernelGGL((k_update<R, D, P, 2, UP_RESID>), g, b, 0, st, e0, e1, 0, a);
         } else {
-            if (kind == UP_RK) hipLaunchKernelGGL((k_update<R, D, P, 1, UP_RK>), g, b, 0, st, a);
-            else hipLaunchKernelGGL((k_update<R, D, P, 1, UP_RESID>), g, b, 0, st, a);
+            if (kind == UP_RK) hipExtLaunchKernelGGL((k_update<R, D, P, 1, UP_RK>), g, b, 0, st, e0, e1, 0, a);
+            else hipExtLaunchKernelGGL((k_update<R, D, P, 1, UP_RESID>), g, b, 0, st, e0, e1, 0, a);
         }
     }
     static void trace(int nvar, const TRArgs<R>& a, hipStream_t st) {
