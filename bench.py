@@ -135,6 +135,45 @@ def cpu_baseline(cfg, mesh, phi0_np, nsteps):
             "s_per_step": t_steps / nsteps}
 
 
+def adjoint_leg(precision, steps, every):
+    """The adjoint workload (64x64 p=3 single vortex, L2 mismatch of phi(T) against a
+    seeded target circle): checkpointed forward run + reverse sweep; seconds per step."""
+    import torch
+    import workloads as W
+    from paper_2006_10967_amd import MeshArgs, Solver
+    cfg = W.config("C4")
+    mesh = cfg.mesh()
+    s = Solver.from_box(mesh, cfg.order, cfg.params, precision=precision, device="cuda:0")
+    period = [float(mesh.period[k]) if mesh.periodic[k] else 0.0 for k in range(cfg.ndims)]
+    x = MeshArgs(cfg.ndims, cfg.order, mesh.x0, mesh.jac, mesh.nbr, period).solution_coords()
+    phi0 = torch.as_tensor(W.ic_phi(x, cfg.centre, cfg.radius, cfg.params.eps_w)).to(
+        "cuda:0", s.dtype)
+    tgt = torch.as_tensor(W.ic_phi(x, W.adjoint_target_centre(cfg), cfg.radius,
+                                   cfg.params.eps_w)).to("cuda:0", s.dtype)
+    det = torch.as_tensor(mesh.jac).reshape(cfg.nelem, cfg.ndims, cfg.ndims).det()
+    w1 = torch.as_tensor(s.mesh.ops["weights"])
+    wq = (det[:, None] * torch.kron(w1, w1)[None, :]).to("cuda:0", s.dtype)
+    dt = cfg.dt(mesh)
+    s.set_state(phi0, None, 0.0, 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.forward_ckpt(dt, steps, every)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    phiT = s.get_state(want_psi=False)[0]
+    seed = wq * (phiT - tgt)
+    loss = 0.5 * float(torch.sum(wq.double() * (phiT.double() - tgt.double()) ** 2))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gphi0, _, ga = s.adjoint(seed)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    return {"s_per_step": (t_fwd + t_adj) / steps, "adjoint_s_per_step": t_adj / steps,
+            "forward_ckpt_s_per_step": t_fwd / steps, "steps": steps, "ckpt_every": every,
+            "dof": cfg.dof, "loss": loss, "dL_dA": ga,
+            "max_abs_dL_dphi0": float(gphi0.abs().max())}
+
+
 def load_traffic(kernel, hsh):
     try:
         with open(TRAFFIC_FILE) as fh:
@@ -155,6 +194,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=60)
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adj-steps", type=int, default=512)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -241,6 +282,16 @@ def main():
                         for k, v in kt32.items()}}}
         log(f"[bench] fp32: {wall32 * 1e3 / K:.4f} ms/step, {v32:.4e} DOF-stage/s, "
             f"int|phi32-phi64| = {l1:.3e}")
+
+    if not args.no_adjoint:
+        adj = {}
+        for prec in ("fp64", "fp32"):
+            adj[prec] = adjoint_leg(prec, args.adj_steps, 32)
+            log(f"[bench] adjoint {prec}: {adj[prec]['s_per_step'] * 1e3:.3f} ms/step "
+                f"(forward+reverse), dL/dA = {adj[prec]['dL_dA']:.6e}")
+        adj["fp32"]["dL_dA_rel_vs_fp64"] = abs(adj["fp32"]["dL_dA"] - adj["fp64"]["dL_dA"]) \
+            / abs(adj["fp64"]["dL_dA"])
+        out["adjoint"] = {"workload": "adjoint2d_64x64_p3", **adj}
 
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")

@@ -214,6 +214,53 @@ pcpf_status pcpf_set_timing(pcpf_ctx* ctx, int32_t on);
  * PCPF_KT_COUNT entries (either may be NULL); reset != 0 clears the accumulators. */
 pcpf_status pcpf_kernel_times(pcpf_ctx* ctx, double* ms, int64_t* launches, int32_t reset);
 
+/* --- adjoint (reverse mode) ----------------------------------------------------------
+ *
+ * Gradients of a loss L(phi(T), psi(T)) of the discrete solution after nsteps RK4 steps
+ * with respect to the initial state and to the velocity amplitude A (v = A v0(x) g(t)):
+ * the exact vector-Jacobian products of the discrete scheme above (the FR operators of
+ * §3.1 applied transposed, the fluxes of §2 and the preconditioner of §3.2 differentiated
+ * by hand), including every reset + preconditioning inside the run. The forward run is
+ * checkpointed every `every` steps and each segment is recomputed once in the reverse
+ * sweep (every stage input of the segment is held in the scratch buffer).
+ */
+
+/* Set the velocity amplitude A of subsequent calls (the adjoint's parameter). */
+pcpf_status pcpf_set_velocity_amplitude(pcpf_ctx* ctx, double amp);
+
+/* Bytes of the checkpoint buffer of a run of nsteps steps checkpointed every `every`
+ * steps: ceil(nsteps / every) copies of (phi, psi). EINVAL unless nsteps >= 1 and
+ * every >= 1. */
+pcpf_status pcpf_ckpt_bytes(const pcpf_ctx* ctx, int64_t nsteps, int64_t every,
+                            size_t* nbytes);
+
+/* Advance the stored state by nsteps steps exactly as pcpf_step does, keeping (phi, psi)
+ * before every step whose index (counted from this call) is a multiple of `every` in
+ * d_ckpt (caller-owned device memory of pcpf_ckpt_bytes bytes). Records the run (start
+ * time and step, dt, nsteps, every, A, whether psi was set) for pcpf_adjoint. When resets
+ * are scheduled, every <= reset_every is required (at most one reset per segment), and a
+ * run that starts without psi must start on the reset schedule. Synchronous. ESTATE
+ * without a state, EINVAL, ENONFINITE (the run is then not recorded). */
+pcpf_status pcpf_forward_ckpt(pcpf_ctx* ctx, double dt, int64_t nsteps, int64_t every,
+                              void* d_ckpt, size_t ckpt_bytes);
+
+/* Device scratch bytes pcpf_adjoint needs for checkpoints every `every` steps
+ * (4 stage inputs of every step of one segment, the stage inputs of one preconditioning,
+ * and the adjoint registers). */
+pcpf_status pcpf_adjoint_bytes(const pcpf_ctx* ctx, int64_t every, size_t* nbytes);
+
+/* Reverse sweep of the last pcpf_forward_ckpt run (d_ckpt unchanged since), with the
+ * amplitude A recorded by that run.
+ * d_gphi, d_gpsi: dL/dphi(T), dL/dpsi(T) ([E][N_u], state type; d_gpsi may be NULL = 0).
+ * Outputs: d_gphi0 = dL/dphi(0), d_gpsi0 = dL/dpsi(0) (may be NULL; zero when the run
+ * started with a reset, which discards psi(0)), *g_amp = dL/dA (may be NULL, float64,
+ * deterministic). d_scratch: caller-owned, 256-byte aligned, >= pcpf_adjoint_bytes.
+ * The stored state is used as a recompute register: after the call no state is set
+ * (ESTATE until pcpf_set_state). Synchronous. ESTATE without a recorded run, EINVAL. */
+pcpf_status pcpf_adjoint(pcpf_ctx* ctx, const void* d_ckpt, void* d_scratch,
+                         size_t scratch_bytes, const void* d_gphi, const void* d_gpsi,
+                         void* d_gphi0, void* d_gpsi0, double* g_amp);
+
 #ifdef __cplusplus
 }
 #endif

@@ -87,6 +87,11 @@ def load() -> ctypes.CDLL:
         "pcpf_reduce": (st, [vp, i32, vp, vp, ctypes.POINTER(dbl)]),
         "pcpf_set_timing": (st, [vp, i32]),
         "pcpf_kernel_times": (st, [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64), i32]),
+        "pcpf_set_velocity_amplitude": (st, [vp, dbl]),
+        "pcpf_ckpt_bytes": (st, [vp, i64, i64, ctypes.POINTER(ctypes.c_size_t)]),
+        "pcpf_forward_ckpt": (st, [vp, dbl, i64, i64, vp, ctypes.c_size_t]),
+        "pcpf_adjoint_bytes": (st, [vp, i64, ctypes.POINTER(ctypes.c_size_t)]),
+        "pcpf_adjoint": (st, [vp, vp, vp, ctypes.c_size_t, vp, vp, vp, vp, ctypes.POINTER(dbl)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -7,6 +7,7 @@
 #include <string>
 #include <vector>
 
+#include "pcpf_adjoint.h"
 #include "pcpf_internal.h"
 
 using namespace pcpf;
@@ -301,6 +302,17 @@ struct pcpf_ctx {
     bool has_state = false, has_psi = false, has_sign = false;
     bool trace_ok[2] = {false, false};
     bool axis = false;     // every element axis-aligned (diagonal J)
+    // checkpointed forward run recorded by pcpf_forward_ckpt (read by pcpf_adjoint)
+    bool ck_valid = false, ck_has_psi0 = false;
+    int64_t ck_step0 = 0, ck_nsteps = 0, ck_every = 1;
+    double ck_amp = 0.0;
+    double ck_t0 = 0.0, ck_dt = 0.0;
+    // storage hooks of the checkpointed recompute (null outside it)
+    void* pc_store_psi0_v = nullptr;
+    std::vector<void*> pc_store_stage_v;
+    bool pc_reset_hit = false;
+    AdjLaunchers<double> A64;
+    AdjLaunchers<float> A32;
     std::string err = "no error";
     // per-launch event timing (pcpf_set_timing)
     bool timing = false;
@@ -505,13 +517,20 @@ pcpf_status refresh_traces(const Ctx<R>& C) {
 constexpr double RK_B[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
 constexpr double RK_C[4] = {0.0, 0.5, 0.5, 1.0};
 
+// Reset + iters pseudo-time RK4 iterations of psi. With store_psi0 / store_stage set (the
+// checkpointed recompute of the adjoint), psi0 and the input of every pseudo stage are kept:
+// store_stage[4*k + s] receives the psi input of stage s of iteration k.
 template <typename R>
-pcpf_status precondition_impl(const Ctx<R>& C, int iters) {
+pcpf_status precondition_impl(const Ctx<R>& C, int iters, R* store_psi0 = nullptr,
+                              R* const* store_stage = nullptr) {
     pcpf_ctx* c = C.c;
     const int64_t n = c->mi.E * c->mi.nu;
+    const size_t bytes = (size_t)n * sizeof(R);
     R* phi = C.plane(c->L.un, 0);
     R* psi = C.plane(c->L.un, 1);
     launch_reset<R>(phi, psi, n, c->prm.reset_mode, c->prm.eps_w, c->prm.delta_phi, c->stream);
+    if (store_psi0)
+        HIPCHK(c, hipMemcpyAsync(store_psi0, psi, bytes, hipMemcpyDeviceToDevice, c->stream));
     // traces of psi0
     {
         TRArgs<R> a{};
@@ -533,14 +552,19 @@ pcpf_status precondition_impl(const Ctx<R>& C, int iters) {
     c->has_psi = true;
     const double dtau = c->prm.dtau;
     for (int it = 0; it < iters; ++it) {
+        if (store_stage)
+            HIPCHK(c, hipMemcpyAsync(store_stage[4 * it], psi, bytes, hipMemcpyDeviceToDevice,
+                                     c->stream));
         for (int s = 0; s < 4; ++s) {
-            const R* uin = s == 0 ? psi : C.plane(c->L.us, 1);
+            R* stage_buf = store_stage ? store_stage[4 * it + (s < 3 ? s + 1 : 0)] : nullptr;
+            const R* uin = s == 0 ? psi : (store_stage ? store_stage[4 * it + s] : C.plane(c->L.us, 1));
             GFArgs<R> g = gf_args<R>(C, uin, uin, c->t);
             psi_only(g);
             g.u[0] = uin;
             TIMED(c, PCPF_KT_PC_GRAD_FLUX, C.Lk().grad_flux(GF_PRECOND, 1, g, c->stream, ev0_, ev1_));
             UPArgs<R> u = up_args<R>(C);
             up_psi_only(u);
+            if (store_stage && s < 3) u.us[0] = stage_buf;
             u.first = s == 0;
             u.last = s == 3;
             u.bcoef = (R)RK_B[s];
@@ -548,9 +572,52 @@ pcpf_status precondition_impl(const Ctx<R>& C, int iters) {
             TIMED(c, PCPF_KT_PC_UPDATE, C.Lk().update(UP_RK, 1, u, c->stream, ev0_, ev1_));
         }
     }
-    c->trace_ok[1] = iters > 0;
-    if (iters == 0) c->trace_ok[1] = true;   // traces of psi0 were written above
+    c->trace_ok[1] = true;   // written by the last update (or by the trace of psi0)
     return launch_status<R>(c);
+}
+
+// One classic RK4 step of the stored state. With y_store set (the checkpointed recompute),
+// the input of stage s is kept in y_store[2*s + v].
+template <typename R>
+pcpf_status step_one(const Ctx<R>& C, double dt, R* const* y_store) {
+    pcpf_ctx* c = C.c;
+    const int N = c->prm.reset_every;
+    if (!c->has_psi || (N > 0 && c->step % N == 0)) {
+        pcpf_status st = precondition_impl<R>(
+            C, c->prm.precond_iters, static_cast<R*>(c->pc_store_psi0_v),
+            c->pc_store_stage_v.empty() ? nullptr
+                                        : reinterpret_cast<R* const*>(c->pc_store_stage_v.data()));
+        if (st != PCPF_OK) return st;
+        c->pc_reset_hit = true;
+    }
+    pcpf_status st = refresh_traces<R>(C);
+    if (st != PCPF_OK) return st;
+    if (y_store) {
+        const size_t bytes = (size_t)c->mi.E * c->mi.nu * sizeof(R);
+        for (int v = 0; v < 2; ++v)
+            HIPCHK(c, hipMemcpyAsync(y_store[v], C.plane(c->L.un, v), bytes,
+                                     hipMemcpyDeviceToDevice, c->stream));
+    }
+    for (int s = 0; s < 4; ++s) {
+        const double ts = c->t + RK_C[s] * dt;
+        const R* u0 = s == 0 ? C.plane(c->L.un, 0) : (y_store ? y_store[2 * s] : C.plane(c->L.us, 0));
+        const R* u1 = s == 0 ? C.plane(c->L.un, 1) : (y_store ? y_store[2 * s + 1] : C.plane(c->L.us, 1));
+        GFArgs<R> g = gf_args<R>(C, u0, u1, ts);
+        TIMED(c, PCPF_KT_GRAD_FLUX, C.Lk().grad_flux(GF_PHYS, 2, g, c->stream, ev0_, ev1_));
+        UPArgs<R> u = up_args<R>(C);
+        if (y_store && s < 3) {
+            u.us[0] = y_store[2 * (s + 1)];
+            u.us[1] = y_store[2 * (s + 1) + 1];
+        }
+        u.first = s == 0;
+        u.last = s == 3;
+        u.bcoef = (R)RK_B[s];
+        u.ccoef = (R)(s == 3 ? dt : RK_C[s + 1] * dt);
+        TIMED(c, PCPF_KT_UPDATE, C.Lk().update(UP_RK, 2, u, c->stream, ev0_, ev1_));
+    }
+    c->t += dt;
+    c->step += 1;
+    return PCPF_OK;
 }
 
 template <typename R>
@@ -558,28 +625,8 @@ pcpf_status step_impl(const Ctx<R>& C, double dt, int64_t nsteps) {
     pcpf_ctx* c = C.c;
     HIPCHK(c, hipMemsetAsync(C.template at<int>(c->L.flag), 0, sizeof(int), c->stream));
     for (int64_t i = 0; i < nsteps; ++i) {
-        const int N = c->prm.reset_every;
-        if (!c->has_psi || (N > 0 && c->step % N == 0)) {
-            pcpf_status st = precondition_impl<R>(C, c->prm.precond_iters);
-            if (st != PCPF_OK) return st;
-        }
-        pcpf_status st = refresh_traces<R>(C);
+        pcpf_status st = step_one<R>(C, dt, nullptr);
         if (st != PCPF_OK) return st;
-        for (int s = 0; s < 4; ++s) {
-            const double ts = c->t + RK_C[s] * dt;
-            const R* u0 = s == 0 ? C.plane(c->L.un, 0) : C.plane(c->L.us, 0);
-            const R* u1 = s == 0 ? C.plane(c->L.un, 1) : C.plane(c->L.us, 1);
-            GFArgs<R> g = gf_args<R>(C, u0, u1, ts);
-            TIMED(c, PCPF_KT_GRAD_FLUX, C.Lk().grad_flux(GF_PHYS, 2, g, c->stream, ev0_, ev1_));
-            UPArgs<R> u = up_args<R>(C);
-            u.first = s == 0;
-            u.last = s == 3;
-            u.bcoef = (R)RK_B[s];
-            u.ccoef = (R)(s == 3 ? dt : RK_C[s + 1] * dt);
-            TIMED(c, PCPF_KT_UPDATE, C.Lk().update(UP_RK, 2, u, c->stream, ev0_, ev1_));
-        }
-        c->t += dt;
-        c->step += 1;
     }
     pcpf_status st = launch_status<R>(c);
     if (st != PCPF_OK) return st;
@@ -729,6 +776,302 @@ pcpf_status upload(pcpf_ctx* c, const pcpf_mesh* m) {
     return PCPF_OK;
 }
 
+// ------------------------------------------------------------------------------------
+// adjoint: checkpointed reverse sweep
+// ------------------------------------------------------------------------------------
+struct AdjLayout {
+    size_t seg, pre0, pre, yb, ya, rb, ub, tb, gp, sb, pb, pa, prb, apart, total;
+};
+
+AdjLayout adj_layout(const pcpf_ctx* c, int64_t every) {
+    const size_t r = c->prm.precision == PCPF_FP32 ? 4 : 8;
+    const size_t S = (size_t)c->mi.E * c->mi.nu;
+    const size_t F = (size_t)c->mi.E * c->mi.d * c->mi.nfa;
+    const int epb = c->prm.precision == PCPF_FP32 ? c->L32.epb : c->L64.epb;
+    const size_t nblocks = (size_t)((c->mi.E + epb - 1) / epb);
+    AdjLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    L.seg = take((size_t)every * 4 * 2 * S * r);
+    L.pre0 = take(S * r);
+    L.pre = take((size_t)(c->prm.precond_iters > 0 ? c->prm.precond_iters : 1) * 4 * S * r);
+    L.yb = take(2 * S * r);
+    L.ya = take(2 * S * r);
+    L.rb = take(2 * S * r);
+    L.ub = take(2 * S * r);
+    L.tb = take(2 * F * r);
+    L.gp = take(2 * F * r);
+    L.sb = take(S * r);
+    L.pb = take(S * r);
+    L.pa = take(S * r);
+    L.prb = take(S * r);
+    L.apart = take(nblocks * 8);
+    L.total = off;
+    return L;
+}
+
+template <typename R>
+const AdjLaunchers<R>& adj_launchers(const pcpf_ctx* c);
+template <>
+const AdjLaunchers<double>& adj_launchers<double>(const pcpf_ctx* c) { return c->A64; }
+template <>
+const AdjLaunchers<float>& adj_launchers<float>(const pcpf_ctx* c) { return c->A32; }
+
+// One stage of the reverse sweep: Y^ = (dR/dY)^T R^ for the stage input Y (nvar planes);
+// then ya += Y^ and rnext = c_prev yb + c_cur Y^ (either may be null).
+template <typename R>
+pcpf_status adj_stage(const Ctx<R>& C, int mode, R* const* Y, R* const* rb, double t, R* const* ub,
+                      R* const* tb, R* const* gp, R* sb, R* const* ya, R* const* rnext,
+                      R* const* yb, double c_prev, double c_cur, double* apart) {
+    pcpf_ctx* c = C.c;
+    const int nvar = mode == AD_PHYS ? 2 : 1;
+    const AdjLaunchers<R>& AL = adj_launchers<R>(c);
+    TRArgs<R> tr{};
+    for (int v = 0; v < nvar; ++v) {
+        tr.u[v] = Y[v];
+        tr.Tp[v] = C.fplane(c->L.Tp, v);
+    }
+    tr.nbr = C.template at<int32_t>(c->L.nbr);
+    tr.ops = C.template at<R>(c->L.ops);
+    tr.E = c->mi.E;
+    C.Lk().trace(nvar, tr, c->stream);
+    if (mode != AD_SIGN) {
+        AJPush<R> p{};
+        for (int v = 0; v < nvar; ++v) {
+            p.rbar[v] = rb[v];
+            p.gp[v] = gp[v];
+        }
+        p.geo = C.template at<R>(c->L.geo);
+        p.nbr = tr.nbr;
+        p.ops = tr.ops;
+        p.E = c->mi.E;
+        AL.push(nvar, p, c->stream);
+    }
+    AJMain<R> m{};
+    for (int v = 0; v < nvar; ++v) {
+        m.u[v] = Y[v];
+        m.Tp[v] = tr.Tp[v];
+        m.rbar[v] = rb ? rb[v] : nullptr;
+        m.gp[v] = gp[v];
+        m.ub[v] = ub[v];
+        m.tb[v] = tb[v];
+    }
+    m.sb = sb;
+    m.sgn = C.template at<R>(c->L.sgn);
+    m.geo = C.template at<R>(c->L.geo);
+    m.nbr = tr.nbr;
+    m.ops = tr.ops;
+    m.apart = apart;
+    m.E = c->mi.E;
+    m.ph = phys<R>(c->prm, t);
+    m.amp = (R)c->prm.vel_amp;
+    m.gt = (R)time_factor(c->prm, t);
+    AL.main(mode, m, c->stream);
+    AJFinish<R> f{};
+    for (int v = 0; v < nvar; ++v) {
+        f.ub[v] = ub[v];
+        f.tb[v] = tb[v];
+        f.ya[v] = ya ? ya[v] : nullptr;
+        f.rnext[v] = rnext ? rnext[v] : nullptr;
+        f.yb[v] = yb ? yb[v] : nullptr;
+    }
+    f.nbr = tr.nbr;
+    f.ops = tr.ops;
+    f.E = c->mi.E;
+    f.c_prev = (R)c_prev;
+    f.c_cur = (R)c_cur;
+    AL.finish(nvar, f, c->stream);
+    return launch_status<R>(c);
+}
+
+template <typename R>
+pcpf_status forward_ckpt_impl(const Ctx<R>& C, double dt, int64_t nsteps, int64_t every,
+                              void* d_ckpt) {
+    pcpf_ctx* c = C.c;
+    const size_t S = (size_t)c->mi.E * c->mi.nu;
+    c->ck_valid = false;
+    c->ck_step0 = c->step;
+    c->ck_t0 = c->t;
+    c->ck_dt = dt;
+    c->ck_nsteps = nsteps;
+    c->ck_every = every;
+    c->ck_amp = c->prm.vel_amp;
+    c->ck_has_psi0 = c->has_psi;
+    HIPCHK(c, hipMemsetAsync(C.template at<int>(c->L.flag), 0, sizeof(int), c->stream));
+    R* ck = static_cast<R*>(d_ckpt);
+    for (int64_t i = 0; i < nsteps; ++i) {
+        if (i % every == 0) {
+            // state before step i (before a reset of that step)
+            HIPCHK(c, hipMemcpyAsync(ck + (size_t)(i / every) * 2 * S, C.plane(c->L.un, 0),
+                                     2 * S * sizeof(R), hipMemcpyDeviceToDevice, c->stream));
+        }
+        pcpf_status st = step_one<R>(C, dt, nullptr);
+        if (st != PCPF_OK) return st;
+    }
+    pcpf_status st = launch_status<R>(c);
+    if (st != PCPF_OK) return st;
+    int flag = 0;
+    HIPCHK(c, hipMemcpyAsync(&flag, C.template at<int>(c->L.flag), sizeof(int),
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    st = collect_times(c);
+    if (st != PCPF_OK) return st;
+    if (flag) return fail(&c->err, PCPF_ENONFINITE, "state became non-finite or |phi| > 10");
+    c->ck_valid = true;
+    return PCPF_OK;
+}
+
+template <typename R>
+pcpf_status adjoint_impl(const Ctx<R>& C, const void* d_ckpt, void* d_scratch,
+                         const void* d_gphi, const void* d_gpsi, void* d_gphi0, void* d_gpsi0,
+                         double* g_amp) {
+    pcpf_ctx* c = C.c;
+    const AdjLayout A = adj_layout(c, c->ck_every);
+    const size_t S = (size_t)c->mi.E * c->mi.nu;
+    const size_t Sb = S * sizeof(R);
+    const size_t F = (size_t)c->mi.E * c->mi.d * c->mi.nfa;
+    char* w = static_cast<char*>(d_scratch);
+    auto at = [&](size_t off) { return reinterpret_cast<R*>(w + off); };
+    R* yb[2] = {at(A.yb), at(A.yb) + S};
+    R* ya[2] = {at(A.ya), at(A.ya) + S};
+    R* rb[2] = {at(A.rb), at(A.rb) + S};
+    R* ub[2] = {at(A.ub), at(A.ub) + S};
+    R* tb[2] = {at(A.tb), at(A.tb) + F};
+    R* gp[2] = {at(A.gp), at(A.gp) + F};
+    R* sb = at(A.sb);
+    R* pb = at(A.pb);
+    R* pa = at(A.pa);
+    R* prb = at(A.prb);
+    R* pre0 = at(A.pre0);
+    double* apart = reinterpret_cast<double*>(w + A.apart);
+    const int K = c->prm.precond_iters;
+    const double dt = c->ck_dt, dtau = c->prm.dtau;
+    const double amp_now = c->prm.vel_amp;
+    c->prm.vel_amp = c->ck_amp;   // recompute and differentiate the recorded run
+    struct RestoreAmp {
+        pcpf_ctx* c;
+        double a;
+        ~RestoreAmp() { c->prm.vel_amp = a; }
+    } restore_amp{c, amp_now};
+    const int64_t every = c->ck_every, nsteps = c->ck_nsteps;
+    const int64_t nseg = (nsteps + every - 1) / every;
+    const R* ck = static_cast<const R*>(d_ckpt);
+    // exchange slots that are never written (boundary faces) must read as zero
+    HIPCHK(c, hipMemsetAsync(w + A.tb, 0, A.sb - A.tb, c->stream));
+    HIPCHK(c, hipMemsetAsync(w + A.apart, 0, A.total - A.apart, c->stream));
+    HIPCHK(c, hipMemcpyAsync(yb[0], d_gphi, Sb, hipMemcpyDeviceToDevice, c->stream));
+    if (d_gpsi) HIPCHK(c, hipMemcpyAsync(yb[1], d_gpsi, Sb, hipMemcpyDeviceToDevice, c->stream));
+    else HIPCHK(c, hipMemsetAsync(yb[1], 0, Sb, c->stream));
+    std::vector<R*> pre_stage((size_t)(K > 0 ? K : 1) * 4);
+    for (size_t i = 0; i < pre_stage.size(); ++i) pre_stage[i] = at(A.pre) + i * S;
+    for (int64_t j = nseg - 1; j >= 0; --j) {
+        const int64_t seg_start = j * every;
+        const int64_t nloc = std::min(every, nsteps - seg_start);
+        // recompute the segment from its checkpoint, keeping every stage input
+        HIPCHK(c, hipMemcpyAsync(C.plane(c->L.un, 0), ck + (size_t)j * 2 * S, 2 * Sb,
+                                 hipMemcpyDeviceToDevice, c->stream));
+        c->has_psi = (j == 0) ? c->ck_has_psi0 : true;
+        c->step = c->ck_step0 + seg_start;
+        c->t = c->ck_t0 + (double)seg_start * dt;
+        c->trace_ok[0] = c->trace_ok[1] = false;
+        c->pc_store_psi0_v = pre0;
+        c->pc_store_stage_v.assign(pre_stage.begin(), pre_stage.end());
+        int64_t reset_local = -1;
+        for (int64_t i = 0; i < nloc; ++i) {
+            R* ys[8];
+            for (int s = 0; s < 4; ++s)
+                for (int v = 0; v < 2; ++v) ys[2 * s + v] = at(A.seg) + ((size_t)i * 4 + s) * 2 * S + v * S;
+            c->pc_reset_hit = false;
+            pcpf_status st = step_one<R>(C, dt, ys);
+            if (st != PCPF_OK) return st;
+            if (c->pc_reset_hit) {
+                if (reset_local >= 0)
+                    return fail(&c->err, PCPF_EINVAL, "two resets in one checkpoint segment");
+                reset_local = i;
+            }
+        }
+        c->pc_store_psi0_v = nullptr;
+        c->pc_store_stage_v.clear();
+        // reverse sweep over the segment
+        for (int64_t i = nloc - 1; i >= 0; --i) {
+            const double tn = c->ck_t0 + (double)(seg_start + i) * dt;
+            HIPCHK(c, hipMemcpyAsync(ya[0], yb[0], 2 * Sb, hipMemcpyDeviceToDevice, c->stream));
+            for (int v = 0; v < 2; ++v) launch_axpby<R>(rb[v], yb[v], nullptr, (R)(dt * RK_B[3]), R(0), (int64_t)S, c->stream);
+            for (int s = 3; s >= 0; --s) {
+                R* Y[2] = {at(A.seg) + ((size_t)i * 4 + s) * 2 * S, at(A.seg) + ((size_t)i * 4 + s) * 2 * S + S};
+                pcpf_status st = adj_stage<R>(C, AD_PHYS, Y, rb, tn + RK_C[s] * dt, ub, tb, gp, nullptr,
+                                              ya, s > 0 ? rb : nullptr, yb,
+                                              s > 0 ? dt * RK_B[s - 1] : 0.0, s > 0 ? dt * RK_C[s] : 0.0,
+                                              apart);
+                if (st != PCPF_OK) return st;
+            }
+            std::swap(yb[0], ya[0]);
+            std::swap(yb[1], ya[1]);
+            if (i == reset_local) {
+                // psi after the preconditioning came from phi_n; the previous psi was discarded
+                HIPCHK(c, hipMemcpyAsync(pb, yb[1], Sb, hipMemcpyDeviceToDevice, c->stream));
+                HIPCHK(c, hipMemsetAsync(yb[1], 0, Sb, c->stream));
+                HIPCHK(c, hipMemsetAsync(sb, 0, Sb, c->stream));
+                R* pbv[1] = {pb};
+                for (int k = K - 1; k >= 0; --k) {
+                    HIPCHK(c, hipMemcpyAsync(pa, pb, Sb, hipMemcpyDeviceToDevice, c->stream));
+                    launch_axpby<R>(prb, pb, nullptr, (R)(dtau * RK_B[3]), R(0), (int64_t)S, c->stream);
+                    R* pav[1] = {pa};
+                    R* prv[1] = {prb};
+                    R* ubv[1] = {ub[0]};
+                    R* tbv[1] = {tb[0]};
+                    R* gpv[1] = {gp[0]};
+                    pbv[0] = pb;
+                    for (int s = 3; s >= 0; --s) {
+                        R* Y[1] = {pre_stage[(size_t)k * 4 + s]};
+                        pcpf_status st = adj_stage<R>(C, AD_PRECOND, Y, prv, c->t, ubv, tbv, gpv, sb, pav,
+                                                      s > 0 ? prv : nullptr, pbv,
+                                                      s > 0 ? dtau * RK_B[s - 1] : 0.0,
+                                                      s > 0 ? dtau * RK_C[s] : 0.0, apart);
+                        if (st != PCPF_OK) return st;
+                    }
+                    std::swap(pb, pa);
+                }
+                // sign VJP: psi0^ += d sgn / d psi0 ^T sb
+                {
+                    R* Y[1] = {pre0};
+                    R* ubv[1] = {ub[0]};
+                    R* tbv[1] = {tb[0]};
+                    R* gpv[1] = {gp[0]};
+                    R* accv[1] = {pb};
+                    pcpf_status st = adj_stage<R>(C, AD_SIGN, Y, nullptr, c->t, ubv, tbv, gpv, sb, accv,
+                                                  nullptr, nullptr, 0.0, 0.0, apart);
+                    if (st != PCPF_OK) return st;
+                }
+                // reset VJP into phi_n^ (phi_n is the stage-0 input of step n)
+                const R* phin = at(A.seg) + (size_t)i * 4 * 2 * S;
+                launch_reset_adj<R>(yb[0], pb, phin, (int64_t)S, c->prm.reset_mode, c->prm.eps_w,
+                                    c->prm.delta_phi, c->stream);
+                pcpf_status st = launch_status<R>(c);
+                if (st != PCPF_OK) return st;
+            }
+        }
+    }
+    HIPCHK(c, hipMemcpyAsync(d_gphi0, yb[0], Sb, hipMemcpyDeviceToDevice, c->stream));
+    if (d_gpsi0) HIPCHK(c, hipMemcpyAsync(d_gpsi0, yb[1], Sb, hipMemcpyDeviceToDevice, c->stream));
+    const int epb = C.Lk().epb;
+    const int nb = (int)((c->mi.E + epb - 1) / epb);
+    double* red = C.template at<double>(c->L.red);
+    launch_reduce_final(apart, nb, red, c->stream);
+    pcpf_status st = launch_status<R>(c);
+    if (st != PCPF_OK) return st;
+    double ga = 0.0;
+    HIPCHK(c, hipMemcpyAsync(&ga, red, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (g_amp) *g_amp = ga;
+    c->has_state = false;   // the stored state was used as the recompute register
+    return PCPF_OK;
+}
+
 pcpf_status check_ctx(pcpf_ctx* c) {
     if (!c) return fail(nullptr, PCPF_EINVAL, "ctx is NULL");
     return PCPF_OK;
@@ -827,8 +1170,9 @@ pcpf_status pcpf_create(const pcpf_mesh* m, const pcpf_params* p, void* d_ws, si
         for (int i = 0; i < mi.d; ++i)
             for (int j = 0; j < mi.d; ++j)
                 if (i != j && m->jac[(e * mi.d + i) * mi.d + j] != 0.0) c->axis = false;
-    bool ok = p->precision == PCPF_FP32 ? get_launchers<float>(mi.d, mi.p, &c->L32)
-                                        : get_launchers<double>(mi.d, mi.p, &c->L64);
+    bool ok = p->precision == PCPF_FP32
+                  ? (get_launchers<float>(mi.d, mi.p, &c->L32) && get_adj_launchers<float>(mi.d, mi.p, &c->A32))
+                  : (get_launchers<double>(mi.d, mi.p, &c->L64) && get_adj_launchers<double>(mi.d, mi.p, &c->A64));
     if (!ok) {
         delete c;
         return fail(nullptr, PCPF_EUNSUPPORTED, "no kernels built for this (d, p)");
@@ -965,6 +1309,57 @@ pcpf_status pcpf_kernel_times(pcpf_ctx* c, double* ms, int64_t* launches, int32_
         }
     }
     return PCPF_OK;
+}
+
+pcpf_status pcpf_set_velocity_amplitude(pcpf_ctx* c, double amp) {
+    if (check_ctx(c) != PCPF_OK) return PCPF_EINVAL;
+    if (!std::isfinite(amp)) return fail(&c->err, PCPF_EINVAL, "amplitude must be finite");
+    c->prm.vel_amp = amp;
+    return PCPF_OK;
+}
+
+pcpf_status pcpf_ckpt_bytes(const pcpf_ctx* c, int64_t nsteps, int64_t every, size_t* nbytes) {
+    if (!c || !nbytes) return fail(nullptr, PCPF_EINVAL, "ckpt_bytes: NULL argument");
+    if (nsteps < 1 || every < 1) return fail(nullptr, PCPF_EINVAL, "nsteps and every must be >= 1");
+    const size_t r = c->prm.precision == PCPF_FP32 ? 4 : 8;
+    *nbytes = (size_t)((nsteps + every - 1) / every) * 2 * (size_t)c->mi.E * c->mi.nu * r;
+    return PCPF_OK;
+}
+
+pcpf_status pcpf_forward_ckpt(pcpf_ctx* c, double dt, int64_t nsteps, int64_t every, void* d_ckpt,
+                              size_t ckpt_bytes) {
+    if (check_ctx(c) != PCPF_OK) return PCPF_EINVAL;
+    if (!c->has_state) return fail(&c->err, PCPF_ESTATE, "no state set");
+    size_t need = 0;
+    if (pcpf_ckpt_bytes(c, nsteps, every, &need) != PCPF_OK || !std::isfinite(dt))
+        return fail(&c->err, PCPF_EINVAL, "bad dt, nsteps or every");
+    if (!d_ckpt || ckpt_bytes < need) return fail(&c->err, PCPF_EINVAL, "checkpoint buffer too small");
+    const int N = c->prm.reset_every;
+    if (N > 0 && every > N)
+        return fail(&c->err, PCPF_EINVAL, "checkpoint interval must not exceed reset_every");
+    if (N > 0 && !c->has_psi && c->step % N != 0 && nsteps > 1)
+        return fail(&c->err, PCPF_EINVAL, "a forced reset off the reset schedule is not supported");
+    return DISPATCH(c, forward_ckpt_impl, dt, nsteps, every, d_ckpt);
+}
+
+pcpf_status pcpf_adjoint_bytes(const pcpf_ctx* c, int64_t every, size_t* nbytes) {
+    if (!c || !nbytes) return fail(nullptr, PCPF_EINVAL, "adjoint_bytes: NULL argument");
+    if (every < 1) return fail(nullptr, PCPF_EINVAL, "every must be >= 1");
+    *nbytes = adj_layout(c, every).total;
+    return PCPF_OK;
+}
+
+pcpf_status pcpf_adjoint(pcpf_ctx* c, const void* d_ckpt, void* d_scratch, size_t scratch_bytes,
+                         const void* d_gphi, const void* d_gpsi, void* d_gphi0, void* d_gpsi0,
+                         double* g_amp) {
+    if (check_ctx(c) != PCPF_OK) return PCPF_EINVAL;
+    if (!c->ck_valid) return fail(&c->err, PCPF_ESTATE, "no checkpointed forward run");
+    if (!d_ckpt || !d_gphi || !d_gphi0) return fail(&c->err, PCPF_EINVAL, "adjoint: NULL argument");
+    if (!d_scratch || scratch_bytes < adj_layout(c, c->ck_every).total)
+        return fail(&c->err, PCPF_EINVAL, "adjoint scratch smaller than pcpf_adjoint_bytes");
+    if (reinterpret_cast<uintptr_t>(d_scratch) % 256 != 0)
+        return fail(&c->err, PCPF_EINVAL, "adjoint scratch must be 256-byte aligned");
+    return DISPATCH(c, adjoint_impl, d_ckpt, d_scratch, d_gphi, d_gpsi, d_gphi0, d_gpsi0, g_amp);
 }
 
 }  // extern "C"

@@ -1,0 +1,159 @@
+// Device helpers shared by the forward and adjoint kernels (tensor-product line indexing,
+// analytic velocity fields, the viscosity ramp).
+#pragma once
+
+#include "pcpf_internal.h"
+
+namespace pcpf {
+namespace dev {
+
+template <typename R>
+struct Math;
+template <>
+struct Math<double> {
+    __device__ static double sqrt_(double x) { return ::sqrt(x); }
+    __device__ static void sincospi_(double x, double* s, double* c) { ::sincospi(x, s, c); }
+    __device__ static double tanh_(double x) { return ::tanh(x); }
+    __device__ static double log10_(double x) { return ::log10(x); }
+    __device__ static double sinpi_(double x) { return ::sinpi(x); }
+    __device__ static double fabs_(double x) { return ::fabs(x); }
+    __device__ static double rsqrt_(double x) { return ::rsqrt(x); }
+};
+template <>
+struct Math<float> {
+    __device__ static float sqrt_(float x) { return ::sqrtf(x); }
+    __device__ static void sincospi_(float x, float* s, float* c) { ::sincospif(x, s, c); }
+    __device__ static float tanh_(float x) { return ::tanhf(x); }
+    __device__ static float log10_(float x) { return ::log10f(x); }
+    __device__ static float sinpi_(float x) { return ::sinpif(x); }
+    __device__ static float fabs_(float x) { return ::fabsf(x); }
+    __device__ static float rsqrt_(float x) { return ::rsqrtf(x); }
+};
+
+template <int N>
+__device__ __forceinline__ constexpr int st(int k) {
+    return k == 0 ? 1 : (k == 1 ? N : N * N);
+}
+
+// Solution-point index of the point at line position 0 of the line through face point t
+// of a face normal to direction k (tangential indices ascending, first fastest).
+template <int D, int N>
+__device__ __forceinline__ int face_base(int k, int t) {
+    int idx = 0;
+#pragma unroll
+    for (int m = 0; m < D; ++m) {
+        if (m == k) continue;
+        idx += (t % N) * st<N>(m);
+        t /= N;
+    }
+    return idx;
+}
+
+// Face-point index, on the faces normal to k, of the line through point multi-index m.
+template <int D, int N>
+__device__ __forceinline__ int tang_index(int k, const int (&mi)[D]) {
+    int t = 0, mul = 1;
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+        if (q == k) continue;
+        t += mi[q] * mul;
+        mul *= N;
+    }
+    return t;
+}
+
+// v(x, t) = A g(t) v0(x) for the analytic fields of §4 (ampg = A g(t)).
+template <typename R, int D>
+__device__ __forceinline__ void velocity(const Phys<R>& ph, const R (&x)[D], R (&v)[D]) {
+    using M = Math<R>;
+    const R A = ph.ampg;
+    if (ph.vel_kind == PCPF_VEL_UNIFORM) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) v[k] = A * ph.u0[k];
+    } else if (ph.vel_kind == PCPF_VEL_ROTATION) {
+        v[0] = A * (R(0.5) - x[1]);
+        v[1] = A * (x[0] - R(0.5));
+#pragma unroll
+        for (int k = 2; k < D; ++k) v[k] = R(0);
+    } else if (ph.vel_kind == PCPF_VEL_SINGLE_VORTEX) {
+        R sx, cx, sy, cy;
+        M::sincospi_(x[0], &sx, &cx);
+        M::sincospi_(x[1], &sy, &cy);
+        v[0] = A * (-(sx * sx) * (R(2) * sy * cy));
+        v[1] = A * ((R(2) * sx * cx) * (sy * sy));
+#pragma unroll
+        for (int k = 2; k < D; ++k) v[k] = R(0);
+    } else {
+        R s[3], c[3];
+#pragma unroll
+        for (int k = 0; k < D; ++k) M::sincospi_(x[k], &s[k], &c[k]);
+        if (D == 3) {
+            const R s2x = R(2) * s[0] * c[0], s2y = R(2) * s[1] * c[1], s2z = R(2) * s[2] * c[2];
+            v[0] = A * (R(2) * (s[0] * s[0]) * s2y * s2z);
+            v[1] = A * (-s2x * (s[1] * s[1]) * s2z);
+            v[D - 1] = A * (-s2x * s2y * (s[2] * s[2]));
+        } else {
+#pragma unroll
+            for (int k = 0; k < D; ++k) v[k] = R(0);
+        }
+    }
+}
+
+// v(x, t) for the fields without trigonometric factors (uniform, rotation).
+template <typename R, int D>
+__device__ __forceinline__ void velocity_lin(const Phys<R>& ph, const R (&x)[D], R (&v)[D]) {
+    const R A = ph.ampg;
+    if (ph.vel_kind == PCPF_VEL_ROTATION) {
+        v[0] = A * (R(0.5) - x[1]);
+        v[1] = A * (x[0] - R(0.5));
+#pragma unroll
+        for (int k = 2; k < D; ++k) v[k] = R(0);
+    } else {
+#pragma unroll
+        for (int k = 0; k < D; ++k) v[k] = A * ph.u0[k];
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ R visc_ramp(R e_all, R e_top, R s0, R kappa, R nu_max) {
+    // §3.2: s_e = log10(<u-u^,u-u^>/<u,u>), smooth ramp of half width kappa around s0
+    if (!(e_all > R(0)) || !(e_top > R(0))) return R(0);
+    const R s = Math<R>::log10_(e_top / e_all);
+    if (s < s0 - kappa) return R(0);
+    if (s > s0 + kappa) return nu_max;
+    return R(0.5) * nu_max * (R(1) + Math<R>::sinpi_((s - s0) / (R(2) * kappa)));
+}
+
+// Velocity from the per-element (sin, cos)(pi x_k) tables of an axis-aligned element:
+// vt[(k * NTB + pos_k) * 2 + {0, 1}], pos_k the node index along k, or N / N + 1 for the
+// xi_k = -1 / +1 end of the element.
+template <typename R, int D, int NTB>
+__device__ __forceinline__ void velocity_tab(const Phys<R>& ph, const R* vt, const int (&pos)[D],
+                                             R (&v)[D]) {
+    const R A = ph.ampg;
+    R s[3], c[3];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        s[k] = vt[(k * NTB + pos[k]) * 2];
+        c[k] = vt[(k * NTB + pos[k]) * 2 + 1];
+    }
+    if (ph.vel_kind == PCPF_VEL_SINGLE_VORTEX) {
+        v[0] = A * (-(s[0] * s[0]) * (R(2) * s[1] * c[1]));
+        v[1] = A * ((R(2) * s[0] * c[0]) * (s[1] * s[1]));
+#pragma unroll
+        for (int k = 2; k < D; ++k) v[k] = R(0);
+    } else {
+        if (D == 3) {
+            const R s2x = R(2) * s[0] * c[0], s2y = R(2) * s[1] * c[1], s2z = R(2) * s[2] * c[2];
+            v[0] = A * (R(2) * (s[0] * s[0]) * s2y * s2z);
+            v[1] = A * (-s2x * (s[1] * s[1]) * s2z);
+            v[D - 1] = A * (-s2x * s2y * (s[2] * s[2]));
+        } else {
+#pragma unroll
+            for (int k = 0; k < D; ++k) v[k] = R(0);
+        }
+    }
+}
+
+}  // namespace dev
+}  // namespace pcpf

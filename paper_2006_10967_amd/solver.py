@@ -214,3 +214,41 @@ class Solver:
 
     def l1(self, ref, field=None) -> float:
         return self.reduce(REDUCE_L1, field, ref)
+
+    # -- adjoint ------------------------------------------------------------------------
+    def set_velocity_amplitude(self, amp: float):
+        self._chk(self.lib.pcpf_set_velocity_amplitude(self.ctx, float(amp)))
+
+    def forward_ckpt(self, dt, nsteps, every=None):
+        """Advance nsteps steps keeping checkpoints every `every` steps (default: the
+        reset interval, or the whole run); returns the checkpoint buffer that
+        :meth:`adjoint` reads."""
+        if every is None:
+            every = int(self.cparams.reset_every) or int(nsteps)
+            every = min(every, int(nsteps))
+        nb = ctypes.c_size_t(0)
+        self._chk(self.lib.pcpf_ckpt_bytes(self.ctx, int(nsteps), int(every), ctypes.byref(nb)))
+        ck = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        self._chk(self.lib.pcpf_forward_ckpt(self.ctx, float(dt), int(nsteps), int(every),
+                                             _ptr(ck), ctypes.c_size_t(nb.value)))
+        self._ckpt, self._ckpt_every = ck, int(every)
+        return ck
+
+    def adjoint(self, gphi, gpsi=None, ckpt=None):
+        """Reverse sweep of the last :meth:`forward_ckpt` run for the seed
+        (dL/dphi(T), dL/dpsi(T)); returns (dL/dphi(0), dL/dpsi(0), dL/dA). Leaves the
+        context without a state."""
+        ck = ckpt if ckpt is not None else self._ckpt
+        nb = ctypes.c_size_t(0)
+        self._chk(self.lib.pcpf_adjoint_bytes(self.ctx, self._ckpt_every, ctypes.byref(nb)))
+        scratch = torch.empty(nb.value + 256, dtype=torch.uint8, device=self.device)
+        sp = (scratch.data_ptr() + 255) // 256 * 256
+        gphi_t = self._field(gphi)
+        gpsi_t = self._field(gpsi) if gpsi is not None else None
+        gphi0 = self.empty()
+        gpsi0 = self.empty()
+        ga = ctypes.c_double(0.0)
+        self._chk(self.lib.pcpf_adjoint(self.ctx, _ptr(ck), ctypes.c_void_p(sp),
+                                        ctypes.c_size_t(nb.value), _ptr(gphi_t), _ptr(gpsi_t),
+                                        _ptr(gphi0), _ptr(gpsi0), ctypes.byref(ga)))
+        return gphi0, gpsi0, ga.value
