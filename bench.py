@@ -61,7 +61,7 @@ def step_alg_bytes_per_dof(d, p, word):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("pcpf_kernels.hip", "pcpf_internal.h"):
+    for f in ("pcpf_kernels.hip", "pcpf_internal.h", "pcpf_device.h"):
         with open(os.path.join(ROOT, "paper_2006_10967_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -128,7 +128,14 @@ def cpu_baseline(cfg, mesh, phi0_np, nsteps):
         t += dt
     t_steps = time.perf_counter() - t0
     rate = cfg.dof * 4 * nsteps / t_steps
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu = next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {"value": rate, "unit": UNIT, "cores": torch.get_num_threads(), "kind": "oracle",
+            "cpu": cpu,
             "sample": f"full {cfg.n}x{cfg.n} p={cfg.order} mesh: {nsteps} RK4 steps "
                       f"({t_steps:.1f} s) after one reset + {cfg.params.precond_iters} "
                       f"pseudo iterations ({t_pc:.1f} s, not in value)",
