@@ -52,7 +52,7 @@ struct AJFinish {
 
 template <typename R>
 struct AdjLaunchers {
-    int nblocks_per_elem;
+    int epb;             // elements per block of the adjoint kernels (partial sums per block)
     void (*push)(int nvar, const AJPush<R>&, hipStream_t);
     void (*main)(int mode, const AJMain<R>&, hipStream_t);
     void (*finish)(int nvar, const AJFinish<R>&, hipStream_t);

@@ -28,8 +28,8 @@ using namespace dev;
 // sum_a cm[a] R^(line a) / |J_e|.
 // ------------------------------------------------------------------------------------
 template <typename R, int D, int P, int V>
-__global__ __launch_bounds__((Shape<D, P>::NT)) void k_adj_push(AJPush<R> a) {
-    using S = Shape<D, P>;
+__global__ __launch_bounds__((AShape<D, P>::NT)) void k_adj_push(AJPush<R> a) {
+    using S = AShape<D, P>;
     constexpr int N = S::N, NU = S::NU, NFA = S::NFA, EPB = S::EPB, NT = S::NT, G = S::GEO;
     constexpr int NMF = D * NFA;
     constexpr int I_T = (EPB * NMF + NT - 1) / NT;
@@ -93,8 +93,8 @@ __global__ __launch_bounds__((Shape<D, P>::NT)) void k_adj_push(AJPush<R> a) {
 // slots; a.apart[block] += dL/dA contribution (physical mode).
 // ------------------------------------------------------------------------------------
 template <typename R, int D, int P, int MODE>
-__global__ __launch_bounds__((Shape<D, P>::NT)) void k_adj_main(AJMain<R> a) {
-    using S = Shape<D, P>;
+__global__ __launch_bounds__((AShape<D, P>::NT)) void k_adj_main(AJMain<R> a) {
+    using S = AShape<D, P>;
     constexpr int N = S::N, NU = S::NU, NFA = S::NFA, EPB = S::EPB, NT = S::NT, G = S::GEO;
     constexpr int V = (MODE == AD_PHYS) ? 2 : 1;
     constexpr int NOPS = ops_size(N);
@@ -734,8 +734,8 @@ __global__ __launch_bounds__((Shape<D, P>::NT)) void k_adj_main(AJMain<R> a) {
 // RK4 combine:  ya += Y^;  next R^ = c_prev * yb + c_cur * Y^  (when c_prev or c_cur set)
 // ------------------------------------------------------------------------------------
 template <typename R, int D, int P, int V>
-__global__ __launch_bounds__((Shape<D, P>::NT)) void k_adj_finish(AJFinish<R> a) {
-    using S = Shape<D, P>;
+__global__ __launch_bounds__((AShape<D, P>::NT)) void k_adj_finish(AJFinish<R> a) {
+    using S = AShape<D, P>;
     constexpr int N = S::N, NU = S::NU, NFA = S::NFA, EPB = S::EPB, NT = S::NT;
     __shared__ R s_lm[N];
     __shared__ int s_nbr[EPB * 2 * D];
@@ -822,7 +822,7 @@ __global__ void k_loss_seed(R* out, const R* phi, const R* target, const R* geo,
 
 template <typename R, int D, int P>
 struct AImpl {
-    using S = Shape<D, P>;
+    using S = AShape<D, P>;
     static unsigned grid(int64_t E) { return (unsigned)((E + S::EPB - 1) / S::EPB); }
     static void push(int nvar, const AJPush<R>& a, hipStream_t st) {
         const dim3 g(grid(a.E)), b(S::NT);
@@ -844,7 +844,7 @@ struct AImpl {
 
 template <typename R, int D, int P>
 bool afill(AdjLaunchers<R>* L) {
-    L->nblocks_per_elem = Shape<D, P>::EPB;
+    L->epb = AShape<D, P>::EPB;
     L->push = &AImpl<R, D, P>::push;
     L->main = &AImpl<R, D, P>::main;
     L->finish = &AImpl<R, D, P>::finish;

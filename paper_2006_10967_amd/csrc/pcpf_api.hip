@@ -787,7 +787,7 @@ AdjLayout adj_layout(const pcpf_ctx* c, int64_t every) {
     const size_t r = c->prm.precision == PCPF_FP32 ? 4 : 8;
     const size_t S = (size_t)c->mi.E * c->mi.nu;
     const size_t F = (size_t)c->mi.E * c->mi.d * c->mi.nfa;
-    const int epb = c->prm.precision == PCPF_FP32 ? c->L32.epb : c->L64.epb;
+    const int epb = c->prm.precision == PCPF_FP32 ? c->A32.epb : c->A64.epb;
     const size_t nblocks = (size_t)((c->mi.E + epb - 1) / epb);
     AdjLayout L{};
     size_t off = 0;
@@ -1058,7 +1058,7 @@ pcpf_status adjoint_impl(const Ctx<R>& C, const void* d_ckpt, void* d_scratch,
     }
     HIPCHK(c, hipMemcpyAsync(d_gphi0, yb[0], Sb, hipMemcpyDeviceToDevice, c->stream));
     if (d_gpsi0) HIPCHK(c, hipMemcpyAsync(d_gpsi0, yb[1], Sb, hipMemcpyDeviceToDevice, c->stream));
-    const int epb = C.Lk().epb;
+    const int epb = adj_launchers<R>(c).epb;
     const int nb = (int)((c->mi.E + epb - 1) / epb);
     double* red = C.template at<double>(c->L.red);
     launch_reduce_final(apart, nb, red, c->stream);

@@ -30,6 +30,19 @@ struct Math<float> {
     __device__ static float rsqrt_(float x) { return ::rsqrtf(x); }
 };
 
+// Global accesses: a wave-uniform base pointer plus an unsigned 32-bit byte offset per
+// lane (every array of a context is below 4 GiB, which pcpf_create checks). This selects
+// the scalar-base + 32-bit-offset addressing of global loads and stores, which needs no
+// 64-bit address arithmetic per lane.
+template <typename T>
+__device__ __forceinline__ T gld(const T* base, uint32_t i) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + i * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void gst(T* base, uint32_t i, T v) {
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (uint32_t)sizeof(T)) = v;
+}
+
 template <int N>
 __device__ __forceinline__ constexpr int st(int k) {
     return k == 0 ? 1 : (k == 1 ? N : N * N);

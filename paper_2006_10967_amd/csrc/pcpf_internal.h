@@ -12,10 +12,31 @@ namespace pcpf {
 
 constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 
+// Block shape of the forward kernels for a (d, p) element: one thread per solution point,
+// EPB = floor(256 / N_u) whole elements per block (at least one), NT = EPB N_u rounded up
+// to whole 64-wide waves. The face phases split the block's face points by reference
+// direction into units of one wave (KSEG = EPB N_fa points per direction, WK waves each),
+// so that the direction, and with it every stride of the face code, is uniform in a wave.
+template <int D, int P>
+struct Shape {
+    static constexpr int N = P + 1;
+    static constexpr int NU = ipow(N, D);
+    static constexpr int NFA = ipow(N, D - 1);
+    static constexpr int NF = 2 * D * NFA;
+    static constexpr int EPB = (256 / NU) >= 1 ? 256 / NU : 1;
+    static constexpr int NT = (EPB * NU + 63) / 64 * 64;
+    static constexpr int NW = NT / 64;
+    static constexpr int KSEG = EPB * NFA;
+    static constexpr int WK = (KSEG + 63) / 64;
+    static constexpr int NUNITS = D * WK;
+    static constexpr int UPW = (NUNITS + NW - 1) / NW;   // face units per wave
+    static constexpr int GEO = D + 2 * D * D + 1;   // x0[D], J[D][D], Jinv[D][D], detJ
+};
+
 // Lane utilisation (per mille) of nt-thread blocks holding whole elements of nu points.
 constexpr int lane_util(int nu, int nt) { return nt >= nu ? (nt / nu) * nu * 1000 / nt : 0; }
 // Smallest block (64, 128 or 256 threads) that keeps >= 90% of the lanes busy, else the
-// best of the three: small blocks give fine-grained scheduling and cheap barriers.
+// best of the three.
 constexpr int pick_nt(int nu) {
     return lane_util(nu, 64) >= 900    ? 64
            : lane_util(nu, 128) >= 900 ? 128
@@ -23,16 +44,17 @@ constexpr int pick_nt(int nu) {
            : (lane_util(nu, 128) >= lane_util(nu, 256) ? 128 : 256);
 }
 
-// Block shape of a (d, p) element: one thread per solution point, EPB elements per block.
+// Block shape of the adjoint kernels: one thread per solution point in the smallest block
+// that keeps >= 90% of the lanes busy.
 template <int D, int P>
-struct Shape {
+struct AShape {
     static constexpr int N = P + 1;
     static constexpr int NU = ipow(N, D);
     static constexpr int NFA = ipow(N, D - 1);
     static constexpr int NF = 2 * D * NFA;
     static constexpr int NT = pick_nt(NU);
     static constexpr int EPB = NT / NU;
-    static constexpr int GEO = D + 2 * D * D + 1;   // x0[D], J[D][D], Jinv[D][D], detJ
+    static constexpr int GEO = D + 2 * D * D + 1;
 };
 
 // Operator block (compute type), n = p + 1:

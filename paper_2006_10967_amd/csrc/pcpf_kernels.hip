@@ -21,6 +21,7 @@
 #include <hip/hip_ext.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "pcpf_device.h"
 #include "pcpf_internal.h"
@@ -69,7 +70,6 @@ void k_grad_flux(GFArgs<R> a) {
     constexpr int NTB = N + 2;                           // table positions per axis
     constexpr int XST = EPB * NU;                        // stride of one field in s_x / s_f
     constexpr int NX = (V * D > 2 ? V * D : 2) * XST;
-    constexpr int FI = (2 * EPB * NPF + NT - 1) / NT;    // face items per thread
     using M = Math<R>;
 
     __shared__ R s_ops[NOPS];
@@ -80,7 +80,7 @@ void k_grad_flux(GFArgs<R> a) {
     __shared__ R s_nb[GRAD ? V : 1][GRAD ? EPB * NPF : 1];  // + face neighbour traces
     __shared__ R s_vt[TAB ? EPB * D * NTB * 2 : 1];
     __shared__ R s_nu[EPB];
-    __shared__ R s_fn[FLUX ? EPB * D * (D + 1) : 1];     // + face unit normal and scale
+    __shared__ R s_fn[FLUX && !AXIS ? EPB * D * (D + 1) : 1];  // + face unit normal, scale
     __shared__ int s_nbr[EPB * 2 * D];
 
     const int tid = threadIdx.x;
@@ -114,35 +114,35 @@ void k_grad_flux(GFArgs<R> a) {
 #pragma unroll
     for (int j = 0; j < I_OPS; ++j) {
         const int i = tid + j * NT;
-        r_ops[j] = (i < NOPS) ? a.ops[i] : R(0);
+        r_ops[j] = (i < NOPS) ? gld(a.ops, i) : R(0);
     }
 #pragma unroll
     for (int j = 0; j < I_GEO; ++j) {
         const int i = tid + j * NT;
-        r_geo[j] = (i < nel * G) ? a.geo[e0 * G + i] : R(0);
+        r_geo[j] = (i < nel * G) ? gld(a.geo + e0 * G, i) : R(0);
     }
 #pragma unroll
     for (int j = 0; j < I_NBR; ++j) {
         const int i = tid + j * NT;
-        r_nbr[j] = (i < nel * 2 * D) ? a.nbr[e0 * 2 * D + i] : -1;
+        r_nbr[j] = (i < nel * 2 * D) ? gld(a.nbr + e0 * 2 * D, i) : -1;
     }
 #pragma unroll
     for (int v = 0; v < V; ++v)
 #pragma unroll
         for (int j = 0; j < I_U; ++j) {
             const int i = tid + j * NT;
-            r_u[v][j] = (i < nel * NU) ? a.u[v][e0 * NU + i] : R(0);
+            r_u[v][j] = (i < nel * NU) ? gld(a.u[v] + e0 * NU, i) : R(0);
         }
     // + face normal inputs (row k of J^-1 and |J|) of this thread's (element, face)
     R r_ji[FLUX ? D : 1], r_det = R(1);
-    const bool fn_thread = FLUX && tid < nel * D;
+    const bool fn_thread = FLUX && !AXIS && tid < nel * D;
     if constexpr (FLUX) {
         if (fn_thread) {
             const int el = tid / D, k = tid - el * D;
-            const R* gg = a.geo + (e0 + el) * G;
+            const R* gb = a.geo + e0 * G;
 #pragma unroll
-            for (int i = 0; i < D; ++i) r_ji[i] = gg[D + D * D + k * D + i];
-            r_det = gg[D + 2 * D * D];
+            for (int i = 0; i < D; ++i) r_ji[i] = gld(gb, el * G + D + D * D + k * D + i);
+            r_det = gld(gb, el * G + D + 2 * D * D);
         }
     }
     // velocity-table inputs: x0_k, J_kk and the reference position of each table entry
@@ -154,9 +154,9 @@ void k_grad_flux(GFArgs<R> a) {
             r_tx[j] = R(0);
             if (trig && it < nel * D * NTB) {
                 const int el = it / (D * NTB), r = it - el * (D * NTB), k = r / NTB, jj = r - k * NTB;
-                const R* gg = a.geo + (e0 + el) * G;
-                const R xi = jj < N ? a.ops[op_xi(N) + jj] : (jj == N ? R(-1) : R(1));
-                r_tx[j] = gg[k] + gg[D + k * D + k] * (xi + R(1));
+                const R* gb = a.geo + e0 * G;
+                const R xi = jj < N ? gld(a.ops + op_xi(N), jj) : (jj == N ? R(-1) : R(1));
+                r_tx[j] = gld(gb, el * G + k) + gld(gb, el * G + D + k * D + k) * (xi + R(1));
             }
         }
     }
@@ -168,7 +168,7 @@ void k_grad_flux(GFArgs<R> a) {
         for (int j = 0; j < I_NB; ++j) {
             const int it = tid + j * NT;
 #pragma unroll
-            for (int v = 0; v < V; ++v) r_nb[j][v] = (it < nel * NPF) ? a.Tp[v][e0 * NPF + it] : R(0);
+            for (int v = 0; v < V; ++v) r_nb[j][v] = (it < nel * NPF) ? gld(a.Tp[v] + e0 * NPF, it) : R(0);
         }
     }
     // registers -> LDS
@@ -194,7 +194,7 @@ void k_grad_flux(GFArgs<R> a) {
                 for (int v = 0; v < V; ++v) s_nb[v][tid + j * NT] = r_nb[j][v];
     }
     // outward unit normal n = J^-T e_k / |J^-T e_k| and scale |J| |J^-T e_k| of face +k
-    if constexpr (FLUX) {
+    if constexpr (FLUX && !AXIS) {
         if (fn_thread) {
             R mag2 = R(0);
 #pragma unroll
@@ -221,7 +221,14 @@ void k_grad_flux(GFArgs<R> a) {
             }
         }
     }
-    __syncthreads();
+    // does any - face of the block lie on a boundary (face 2k of an element, no neighbour)?
+    int my_bnd = 0;
+#pragma unroll
+    for (int j = 0; j < I_NBR; ++j) {
+        const int i = tid + j * NT;
+        if (i < nel * 2 * D && (i & 1) == 0 && r_nbr[j] < 0) my_bnd = 1;
+    }
+    const int has_bnd = __syncthreads_or(my_bnd);
 
     // ---- sensor (§3.2): modal coefficients by one 1D transform per direction -----------
     if constexpr (SENS) {
@@ -255,7 +262,7 @@ void k_grad_flux(GFArgs<R> a) {
             }
             const R nu = visc_ramp(ea, et, a.ph.s0, a.ph.kappa, a.ph.nu_max);
             s_nu[tid] = nu;
-            if constexpr (MODE == GF_SENSOR) a.out[e0 + tid] = nu;
+            if constexpr (MODE == GF_SENSOR) gst(a.out + e0, tid, nu);
         }
         __syncthreads();
         if constexpr (MODE == GF_SENSOR) return;
@@ -307,7 +314,7 @@ void k_grad_flux(GFArgs<R> a) {
                 for (int i = 0; i < D; ++i) g2 += q[0][i] * q[0][i];
                 R g = M::sqrt_(g2);
                 if (!(g > a.ph.delta_g)) g = a.ph.delta_g;
-                a.out[(e0 + le) * NU + ip] = M::tanh_(s_u[0][tid] / g);
+                gst(a.out + e0 * NU, tid, M::tanh_(s_u[0][tid] / g));
             }
             if constexpr (MODE == GF_PHYS) {
                 const R* xi = &s_ops[op_xi(N)];
@@ -374,7 +381,7 @@ void k_grad_flux(GFArgs<R> a) {
                 R g2 = R(0);
 #pragma unroll
                 for (int i = 0; i < D; ++i) g2 += q[0][i] * q[0][i];
-                Sdet = det * a.sgn[(e0 + le) * NU + ip] * (R(1) - M::sqrt_(g2));
+                Sdet = det * gld(a.sgn + e0 * NU, tid) * (R(1) - M::sqrt_(g2));
 #pragma unroll
                 for (int k = 0; k < D; ++k) {
                     R acc;
@@ -393,50 +400,58 @@ void k_grad_flux(GFArgs<R> a) {
         __syncthreads();
 
         // ---- C: common normal fluxes on owned face points (Step 5) ----------------------
-        // items [0, nel*NPF): + faces (owned); [nel*NPF, 2*nel*NPF): - faces, computed here
-        // only on boundaries (ghost state = interior state)
-#pragma unroll
-        for (int j = 0; j < FI; ++j) {
-            const int it = tid + j * NT;
-            if (it >= 2 * nel * NPF) continue;
-            const bool plus = it < nel * NPF;
-            const int itf = plus ? it : it - nel * NPF;
-            const int el = itf / NPF, r = itf - el * NPF, k = r / NFA, t = r - k * NFA;
-            const int s = plus ? 1 : 0;
-            const int32_t en = s_nbr[el * 2 * D + 2 * k + s];
-            if (!plus && en >= 0) continue;
-            const int64_t e = e0 + el;
-            const int base = el * NU + face_base<D, N>(k, t);
-            const R* l = &s_ops[s ? op_lp(N) : op_lm(N)];
+        // One face point per lane; each wave takes the points of one reference direction
+        // K (compile-time in the body below). + faces are owned; - faces are computed here
+        // only on boundaries (ghost state = interior state).
+        auto face = [&](auto KC, auto SC, int el, int t, int32_t en) {
+            constexpr int K = decltype(KC)::value;
+            constexpr int SD = decltype(SC)::value;      // 1: + face, 0: - face
+            constexpr int SK = st<N>(K);
+            const int base = el * NU + face_base<D, N>(K, t);
+            const R* l = &s_ops[SD ? op_lp(N) : op_lm(N)];
             const R* gg = &s_geo[el * G];
-            const R* fn = &s_fn[(el * D + k) * (D + 1)];
-            const R sc = fn[D];
-            R nrm[D];
+            R nrm[D], sc;
+            if constexpr (AXIS) {
+                // diagonal J: the unit normal of face +K is sign(Jinv_KK) e_K
+                const R jk = gg[D + D * D + K * D + K];
+                sc = gg[D + 2 * D * D] * M::fabs_(jk);
 #pragma unroll
-            for (int i = 0; i < D; ++i) nrm[i] = s ? fn[i] : -fn[i];
+                for (int i = 0; i < D; ++i) nrm[i] = R(0);
+                nrm[K] = ((jk > R(0)) == (SD == 1)) ? R(1) : R(-1);
+            } else {
+                const R* fn = &s_fn[(el * D + K) * (D + 1)];
+                sc = fn[D];
+#pragma unroll
+                for (int i = 0; i < D; ++i) nrm[i] = SD ? fn[i] : -fn[i];
+            }
             R uL[V], uR[V], qn[V], g2 = R(0);
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 R acc = R(0);
 #pragma unroll
-                for (int q = 0; q < N; ++q) acc += l[q] * s_u[v][base + q * st<N>(k)];
+                for (int q = 0; q < N; ++q) acc += l[q] * s_u[v][base + q * SK];
                 uL[v] = acc;
-                uR[v] = (en >= 0) ? s_nb[v][el * NPF + k * NFA + t] : acc;
-                // the psi gradient at the face point enters |grad psi| of the normal
-                const bool full = (MODE == GF_PHYS && v == V - 1) || !AXIS;
+                uR[v] = (en >= 0) ? s_nb[v][el * NPF + K * NFA + t] : acc;
+                // the normal component; for psi in the physical mode all components (they
+                // enter |grad psi| of the interface normal)
                 R acc_n = R(0);
 #pragma unroll
                 for (int i = 0; i < D; ++i) {
-                    if (!full && i != k) continue;
+                    const bool need = !AXIS || (MODE == GF_PHYS && v == V - 1) || i == K;
+                    if (!need) continue;
                     R qa = R(0);
 #pragma unroll
-                    for (int q = 0; q < N; ++q) qa += l[q] * s_x[(v * D + i) * XST + base + q * st<N>(k)];
-                    acc_n += qa * nrm[i];
+                    for (int q = 0; q < N; ++q) qa += l[q] * s_x[(v * D + i) * XST + base + q * SK];
+                    if constexpr (AXIS) {
+                        if (i == K) acc_n = qa * nrm[K];
+                    } else {
+                        acc_n += qa * nrm[i];
+                    }
                     if (MODE == GF_PHYS && v == V - 1) g2 += qa * qa;
                 }
                 qn[v] = acc_n;
             }
-            const int64_t fo = (e * D + k) * NFA + t;
+            const uint32_t fo = (el * D + K) * NFA + t;   // from the block's first element
             if constexpr (MODE == GF_PHYS) {
                 const R* xi = &s_ops[op_xi(N)];
                 R vel[D];
@@ -445,8 +460,8 @@ void k_grad_flux(GFArgs<R> a) {
                     int tt = t;
 #pragma unroll
                     for (int m = 0; m < D; ++m) {
-                        if (m == k) {
-                            pos[m] = N + s;
+                        if (m == K) {
+                            pos[m] = N + SD;
                         } else {
                             pos[m] = tt % N;
                             tt /= N;
@@ -460,7 +475,7 @@ void k_grad_flux(GFArgs<R> a) {
                         R x[D];
 #pragma unroll
                         for (int m = 0; m < D; ++m) {
-                            const R xr = (m == k) ? (s ? R(2) : R(0)) : xi[pos[m]] + R(1);
+                            const R xr = (m == K) ? (SD ? R(2) : R(0)) : xi[pos[m]] + R(1);
                             x[m] = gg[m] + gg[D + m * D + m] * xr;
                         }
                         velocity_lin<R, D>(a.ph, x, vel);
@@ -472,7 +487,7 @@ void k_grad_flux(GFArgs<R> a) {
                         R acc = gg[i];
 #pragma unroll
                         for (int m = 0; m < D; ++m) {
-                            const R xr = (m == k) ? (s ? R(2) : R(0)) : xi[pos[m]] + R(1);
+                            const R xr = (m == K) ? (SD ? R(2) : R(0)) : xi[pos[m]] + R(1);
                             acc += gg[D + i * D + m] * xr;
                         }
                         x[i] = acc;
@@ -483,7 +498,11 @@ void k_grad_flux(GFArgs<R> a) {
 #pragma unroll
                 for (int i = 0; i < D; ++i) {
                     v2 += vel[i] * vel[i];
-                    if (!AXIS || i == k) vn += vel[i] * nrm[i];
+                    if constexpr (AXIS) {
+                        if (i == K) vn = vel[K] * nrm[K];
+                    } else {
+                        vn += vel[i] * nrm[i];
+                    }
                 }
                 R mm = M::sqrt_(v2);
                 if (!(mm > a.ph.gamma)) mm = a.ph.gamma;
@@ -493,30 +512,56 @@ void k_grad_flux(GFArgs<R> a) {
                 const R F0 = R(0.5) * (pL + pR) * vn - fvn + a.ph.tau * (pL - pR);
                 const R F1 = R(0.5) * (sL + sR) * vn + a.ph.tau * (sL - sR);
                 const R G0 = sc * F0, G1 = sc * F1;
-                if (s) {
-                    a.Fp[0][fo] = G0;
-                    a.Fp[1][fo] = G1;
+                if constexpr (SD == 1) {
+                    gst(a.Fp[0] + e0 * NPF, fo, G0);
+                    gst(a.Fp[1] + e0 * NPF, fo, G1);
                     if (en >= 0) {
                         // the neighbour's - face: same flux, its outward normal is -n
-                        const int64_t fn_ = ((int64_t)en * D + k) * NFA + t;
-                        a.Fm[0][fn_] = -G0;
-                        a.Fm[1][fn_] = -G1;
+                        const uint32_t fn_ = ((uint32_t)en * D + K) * NFA + t;
+                        gst(a.Fm[0], fn_, -G0);
+                        gst(a.Fm[1], fn_, -G1);
                     }
                 } else {
-                    a.Fm[0][fo] = G0;
-                    a.Fm[1][fo] = G1;
+                    gst(a.Fm[0] + e0 * NPF, fo, G0);
+                    gst(a.Fm[1] + e0 * NPF, fo, G1);
                 }
             } else {
                 const R F = -s_nu[el] * qn[0] + a.ph.tau * (uL[0] - uR[0]);
                 const R G0 = sc * F;
-                if (s) {
-                    a.Fp[0][fo] = G0;
-                    if (en >= 0) a.Fm[0][((int64_t)en * D + k) * NFA + t] = -G0;
+                if constexpr (SD == 1) {
+                    gst(a.Fp[0] + e0 * NPF, fo, G0);
+                    if (en >= 0) gst(a.Fm[0], ((uint32_t)en * D + K) * NFA + t, -G0);
                 } else {
-                    a.Fm[0][fo] = G0;
+                    gst(a.Fm[0] + e0 * NPF, fo, G0);
                 }
             }
-        }
+        };
+        // wave-uniform direction: each unit is one wave's worth of one direction's points
+        const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+        const int lane = tid & 63;
+        auto face_pass = [&](auto SC) {
+            constexpr int SD = decltype(SC)::value;
+#pragma unroll
+            for (int j = 0; j < S::UPW; ++j) {
+                const int u = wave + j * S::NW;
+                if (u >= S::NUNITS) break;
+                const int k = u / S::WK;
+                const int item = (u - k * S::WK) * 64 + lane;
+                if (item >= nel * NFA) continue;
+                const int el = item / NFA, t = item - el * NFA;
+                const int32_t en = s_nbr[el * 2 * D + 2 * k + SD];
+                if (SD == 0 && en >= 0) continue;
+                if (k == 0) {
+                    face(std::integral_constant<int, 0>{}, SC, el, t, en);
+                } else if (k == 1) {
+                    face(std::integral_constant<int, 1>{}, SC, el, t, en);
+                } else if constexpr (D == 3) {
+                    face(std::integral_constant<int, 2>{}, SC, el, t, en);
+                }
+            }
+        };
+        face_pass(std::integral_constant<int, 1>{});
+        if (has_bnd) face_pass(std::integral_constant<int, 0>{});
 
         // ---- E: volume part of Step 6, P = sum_k DH_k f~_k (- |J| S) ---------------------
         if (pt) {
@@ -531,8 +576,66 @@ void k_grad_flux(GFArgs<R> a) {
                     for (int b = 0; b < N; ++b) acc += DH[mi[k] * N + b] * s_f[(v * D + k) * XST + b0 + b * st<N>(k)];
                 }
                 if constexpr (MODE == GF_PRECOND) acc -= Sdet;
-                a.P[v][(e0 + le) * NU + ip] = acc;
+                gst(a.P[v] + e0 * NU, tid, acc);
             }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// - face traces of the block's elements pushed into the owners' + face slots. Face unit
+// j of a wave covers direction k = u / WK, points (u % WK) * 64 + lane of that direction
+// (u = wave + j NW), so the direction is uniform in the wave.
+// ------------------------------------------------------------------------------------
+template <int D, int P, int U>
+__device__ __forceinline__ void load_owners(int32_t (&r_own)[U], const int32_t* nbr, int64_t e0,
+                                            int nel, int wave, int lane) {
+    using S = Shape<D, P>;
+#pragma unroll
+    for (int j = 0; j < S::UPW; ++j) {
+        const int u = wave + j * S::NW;
+        r_own[j] = -1;
+        if (u < S::NUNITS) {
+            const int k = u / S::WK;
+            const int item = (u - k * S::WK) * 64 + lane;
+            if (item < nel * S::NFA) r_own[j] = gld(nbr + e0 * 2 * D, (item / S::NFA) * 2 * D + 2 * k);
+        }
+    }
+}
+
+template <typename R, int D, int P, int V, int U>
+__device__ __forceinline__ void push_traces(R* const* Tp, const R* lm, const R* su0,
+                                            const R* su1, const int32_t (&r_own)[U], int nel,
+                                            int wave, int lane) {
+    using S = Shape<D, P>;
+    constexpr int N = S::N, NU = S::NU, NFA = S::NFA;
+    auto push = [&](auto KC, int el, int t, int32_t own) {
+        constexpr int K = decltype(KC)::value;
+        constexpr int SK = st<N>(K);
+        const int base = el * NU + face_base<D, N>(K, t);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const R* su = v ? su1 : su0;
+            R acc = R(0);
+#pragma unroll
+            for (int q = 0; q < N; ++q) acc += lm[q] * su[base + q * SK];
+            gst(Tp[v], ((uint32_t)own * D + K) * NFA + t, acc);
+        }
+    };
+#pragma unroll
+    for (int j = 0; j < S::UPW; ++j) {
+        const int u = wave + j * S::NW;
+        if (u >= S::NUNITS) break;
+        const int k = u / S::WK;
+        const int item = (u - k * S::WK) * 64 + lane;
+        if (item >= nel * NFA || r_own[j] < 0) continue;
+        const int el = item / NFA, t = item - el * NFA;
+        if (k == 0) {
+            push(std::integral_constant<int, 0>{}, el, t, r_own[j]);
+        } else if (k == 1) {
+            push(std::integral_constant<int, 1>{}, el, t, r_own[j]);
+        } else if constexpr (D == 3) {
+            push(std::integral_constant<int, 2>{}, el, t, r_own[j]);
         }
     }
 }
@@ -558,40 +661,33 @@ __global__ __launch_bounds__((Shape<D, P>::NT)) void k_update(UPArgs<R> a) {
     const bool pt = tid < nel * NU;
     const int le = tid / NU;
     const int ip = tid - le * NU;
-    const int64_t idx = (e0 + le) * NU + ip;
     // every global load is issued before the first wait; all are indexed by this block's
     // own elements (the owners pushed the - face fluxes here). The adjacency is only needed
     // for the addresses of the trace pushes at the end.
     constexpr int I_F = (EPB * NFE + NT - 1) / NT;
-    constexpr int NMF = D * NFA;
-    constexpr int I_T = (EPB * NMF + NT - 1) / NT;
-    int32_t r_own[KIND == UP_RK ? I_T : 1];
-    if constexpr (KIND == UP_RK) {
-#pragma unroll
-        for (int j = 0; j < I_T; ++j) {
-            const int it = tid + j * NT;
-            const int el = it / NMF, k = (it - el * NMF) / NFA;
-            r_own[j] = (it < nel * NMF) ? a.nbr[(e0 + el) * 2 * D + 2 * k] : -1;
-        }
-    }
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    int32_t r_own[S::UPW];
+    if constexpr (KIND == UP_RK) load_owners<D, P, S::UPW>(r_own, a.nbr, e0, nel, wave, lane);
     R rP[V], rU[V], rA[V];
     R det = R(1);
+    const uint32_t so = e0 * NU;     // first state value of the block (per plane)
     if (pt) {
-        det = a.geo[(e0 + le) * G + D + 2 * D * D];
+        det = gld(a.geo + e0 * G, le * G + D + 2 * D * D);
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            rP[v] = a.P[v][idx];
+            rP[v] = gld(a.P[v] + so, tid);
             if constexpr (KIND == UP_RK) {
-                rU[v] = a.un[v][idx];
-                rA[v] = a.first ? R(0) : a.acc[v][idx];
+                rU[v] = gld(a.un[v] + so, tid);
+                rA[v] = a.first ? R(0) : gld(a.acc[v] + so, tid);
             }
         }
     }
     R r_c[3] = {R(0), R(0), R(0)};
     if (tid < N) {
-        r_c[0] = a.ops[op_cm(N) + tid];
-        r_c[1] = a.ops[op_cp(N) + tid];
-        r_c[2] = a.ops[op_lm(N) + tid];
+        r_c[0] = gld(a.ops + op_cm(N), tid);
+        r_c[1] = gld(a.ops + op_cp(N), tid);
+        r_c[2] = gld(a.ops + op_lm(N), tid);
     }
     R r_F[I_F][V];
 #pragma unroll
@@ -602,11 +698,10 @@ __global__ __launch_bounds__((Shape<D, P>::NT)) void k_update(UPArgs<R> a) {
         const int f = r / NFA;
         const int t = r - f * NFA;
         const int k = f >> 1, s = f & 1;
-        const int64_t e = e0 + el;
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             R F = R(0);
-            if (it < nel * NFE) F = (s ? a.Fp[v] : a.Fm[v])[(e * D + k) * NFA + t];
+            if (it < nel * NFE) F = gld((s ? a.Fp[v] : a.Fm[v]) + e0 * D * NFA, (el * D + k) * NFA + t);
             r_F[j][v] = F;
         }
     }
@@ -644,16 +739,16 @@ __global__ __launch_bounds__((Shape<D, P>::NT)) void k_update(UPArgs<R> a) {
             }
             const R res = -acc * rdet;
             if constexpr (KIND == UP_RESID) {
-                a.res[v][idx] = res;
+                gst(a.res[v] + so, tid, res);
             } else {
                 R nx;
                 if (!a.last) {
-                    a.acc[v][idx] = rA[v] + a.bcoef * res;
+                    gst(a.acc[v] + so, tid, rA[v] + a.bcoef * res);
                     nx = rU[v] + a.ccoef * res;
-                    a.us[v][idx] = nx;
+                    gst(a.us[v] + so, tid, nx);
                 } else {
                     nx = rU[v] + a.ccoef * (rA[v] + a.bcoef * res);
-                    a.un[v][idx] = nx;
+                    gst(a.un[v] + so, tid, nx);
                 }
                 s_u[v][tid] = nx;
                 const R lim = (v == 0 && V == 2) ? R(10) : R(1e30);
@@ -664,24 +759,7 @@ __global__ __launch_bounds__((Shape<D, P>::NT)) void k_update(UPArgs<R> a) {
     if constexpr (KIND == UP_RK) {
         __syncthreads();
         // - face traces of the next stage input, pushed into the owners' + face slots
-        const R* lm = &s_c[2 * N];
-#pragma unroll
-        for (int j = 0; j < I_T; ++j) {
-            const int it = tid + j * NT;
-            if (it >= nel * NMF || r_own[j] < 0) continue;
-            const int el = it / NMF;
-            const int r = it - el * NMF;
-            const int k = r / NFA;
-            const int t = r - k * NFA;
-            const int base = el * NU + face_base<D, N>(k, t);
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-                R acc = R(0);
-#pragma unroll
-                for (int q = 0; q < N; ++q) acc += lm[q] * s_u[v][base + q * st<N>(k)];
-                a.Tp[v][((int64_t)r_own[j] * D + k) * NFA + t] = acc;
-            }
-        }
+        push_traces<R, D, P, V, S::UPW>(a.Tp, &s_c[2 * N], s_u[0], s_u[V - 1], r_own, nel, wave, lane);
     }
 }
 
@@ -690,31 +768,26 @@ __global__ __launch_bounds__((Shape<D, P>::NT)) void k_update(UPArgs<R> a) {
 template <typename R, int D, int P, int V>
 __global__ __launch_bounds__((Shape<D, P>::NT)) void k_trace(TRArgs<R> a) {
     using S = Shape<D, P>;
-    constexpr int N = S::N, NU = S::NU, NFA = S::NFA, EPB = S::EPB, NT = S::NT;
-    constexpr int NMF = D * NFA;
-    constexpr int I_T = (EPB * NMF + NT - 1) / NT;
+    constexpr int N = S::N, NU = S::NU, EPB = S::EPB, NT = S::NT;
     constexpr int I_U = (EPB * NU + NT - 1) / NT;
     __shared__ R s_lm[N];
     __shared__ R s_u[V][EPB * NU];
     const int tid = threadIdx.x;
     const int64_t e0 = (int64_t)blockIdx.x * EPB;
     const int nel = (int)((a.E - e0) < EPB ? (a.E - e0) : EPB);
-    int32_t r_own[I_T];
-#pragma unroll
-    for (int j = 0; j < I_T; ++j) {
-        const int it = tid + j * NT;
-        const int el = it / NMF, k = (it - el * NMF) / NFA;
-        r_own[j] = (it < nel * NMF) ? a.nbr[(e0 + el) * 2 * D + 2 * k] : -1;
-    }
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    int32_t r_own[S::UPW];
+    load_owners<D, P, S::UPW>(r_own, a.nbr, e0, nel, wave, lane);
     R r_u[V][I_U];
 #pragma unroll
     for (int v = 0; v < V; ++v)
 #pragma unroll
         for (int j = 0; j < I_U; ++j) {
             const int i = tid + j * NT;
-            r_u[v][j] = (i < nel * NU) ? a.u[v][e0 * NU + i] : R(0);
+            r_u[v][j] = (i < nel * NU) ? gld(a.u[v] + e0 * NU, i) : R(0);
         }
-    R r_l = (tid < N) ? a.ops[op_lm(N) + tid] : R(0);
+    R r_l = (tid < N) ? gld(a.ops + op_lm(N), tid) : R(0);
     if (tid < N) s_lm[tid] = r_l;
 #pragma unroll
     for (int v = 0; v < V; ++v)
@@ -722,23 +795,7 @@ __global__ __launch_bounds__((Shape<D, P>::NT)) void k_trace(TRArgs<R> a) {
         for (int j = 0; j < I_U; ++j)
             if (tid + j * NT < nel * NU) s_u[v][tid + j * NT] = r_u[v][j];
     __syncthreads();
-#pragma unroll
-    for (int j = 0; j < I_T; ++j) {
-        const int it = tid + j * NT;
-        if (it >= nel * NMF || r_own[j] < 0) continue;
-        const int el = it / NMF;
-        const int r = it - el * NMF;
-        const int k = r / NFA;
-        const int t = r - k * NFA;
-        const int base = el * NU + face_base<D, N>(k, t);
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-            R acc = R(0);
-#pragma unroll
-            for (int q = 0; q < N; ++q) acc += s_lm[q] * s_u[v][base + q * st<N>(k)];
-            a.Tp[v][((int64_t)r_own[j] * D + k) * NFA + t] = acc;
-        }
-    }
+    push_traces<R, D, P, V, S::UPW>(a.Tp, s_lm, s_u[0], s_u[V - 1], r_own, nel, wave, lane);
 }
 
 // FP64 quadrature reduction, first pass: block partial sums in a fixed order.
