@@ -31,7 +31,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 METRIC = "DOF-stage updates/s FP64 vs FP32/BF16 at equal interface L1 error; adjoint s/step"
 UNIT = "DOF-stage updates/s"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_vortex2d_128x128_p4.json")
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def log(*a):
@@ -181,9 +181,11 @@ def adjoint_leg(precision, steps, every):
             "max_abs_dL_dphi0": float(gphi0.abs().max())}
 
 
-def load_traffic(kernel, hsh):
+def load_traffic(workload, kernel, hsh):
+    """Counter-measured HBM bytes per launch of a kernel on a workload, recorded in
+    profiles/traffic_<workload>.json for the kernel sources of hash hsh (else None)."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(os.path.join(PROFILES, f"traffic_{workload}.json")) as fh:
             data = json.load(fh)
     except OSError:
         return None
@@ -246,7 +248,7 @@ def main():
     bytes_launch = kernel_bytes(cfg.ndims, cfg.order, word, kern) * cfg.nelem
     achieved = bytes_launch / avg_s / 1e9
     hsh = kernel_source_hash()
-    traffic = load_traffic(kern, hsh)
+    traffic = load_traffic(cfg.name, kern, hsh)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kern,
                 "alg_bytes_per_launch": bytes_launch,
@@ -263,9 +265,9 @@ def main():
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": K, "warmup": Wm,
         "ms_per_step": wall64 * 1e3 / K, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": cfg.name, "mesh": f"{cfg.n}x{cfg.n} quads", "order": cfg.order,
-                   "dof": cfg.dof, "velocity": "single vortex T=8", "dt": cfg.dt(mesh),
-                   "reset_every": cfg.params.reset_every,
+        "config": {"workload": cfg.name, "description": cfg.description,
+                   "elements": cfg.nelem, "order": cfg.order, "dof": cfg.dof,
+                   "dt": cfg.dt(mesh), "reset_every": cfg.params.reset_every,
                    "precond_iters": cfg.params.precond_iters},
         "roofline": roofline,
         "kernels_fp64": kernels,

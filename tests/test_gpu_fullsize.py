@@ -1,0 +1,120 @@
+"""Full-size 3D parity: the 64^3 p=3 and 96^3 p=4 (perturbed) LeVeque meshes, in the
+launch configuration the benchmark times, against the FP64 CPU oracle on sampled outputs
+and against properties that hold at any size.
+
+Sampled outputs: the residual of an element depends only on its own state, its face
+neighbours' traces and the fluxes its - face neighbours compute, which need their own
++ face neighbours (every element within one layer, diagonals included). The oracle
+therefore reproduces, on a 7^3 sub-block cut out of the full mesh with copy boundaries,
+the full-mesh residual of every sub-block element that is not on the sub-block's outer
+layer (5^3 = 125 elements). The sub-block is placed across the interface.
+
+Properties: per-residual mass conservation (the common flux is shared exactly by the two
+elements of a face, so on a periodic mesh sum |J| W R_phi vanishes to round-off) and
+free-stream preservation under a uniform velocity: a constant psi has R_psi = 0, and a
+constant phi in {0, 1} (where phi (1 - phi) vanishes) has R_phi = 0 for any psi. (A
+constant phi strictly inside (0, 1) with a constant psi is not a steady state: the
+interface normal grad psi / |grad psi| is then rounding noise.)
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import Oracle
+from oracle import residual as ores
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+CASES = [("C3", (10, 19, 19)), ("C5", (16, 30, 30))]
+M = 7
+
+
+def _solver(mesh, p, prm):
+    from paper_2006_10967_amd import Solver
+    return Solver.from_box(mesh, p, prm, precision="fp64")
+
+
+def _rel(a, b):
+    return float((a - b).abs().max()) / float(b.abs().max())
+
+
+def _sub_block(mesh, lo, m):
+    """The m^3 element sub-block starting at element (lo) as a copy-boundary box mesh, and
+    the full-mesh index of each of its elements."""
+    d = mesh.ndims
+    planes = [np.asarray(mesh.planes[k])[lo[k]:lo[k] + m + 1] for k in range(d)]
+    sub = W.box_mesh(planes, [False] * d)
+    e = np.arange(sub.nelem)
+    c = [(e // m ** k) % m + lo[k] for k in range(d)]
+    n = mesh.shape
+    full = c[0] + n[0] * (c[1] + n[1] * c[2])
+    inner = np.all([(e // m ** k) % m >= 1 for k in range(d)]
+                   + [(e // m ** k) % m <= m - 2 for k in range(d)], axis=0)
+    return sub, full, inner
+
+
+def _state(cfg, x):
+    phi = torch.tensor(W.ic_phi(x, cfg.centre, cfg.radius, cfg.params.eps_w))
+    psi = torch.tensor(W.signed_distance_ball(x, cfg.centre, cfg.radius))
+    return phi, psi
+
+
+@pytest.mark.parametrize("name,lo", CASES, ids=[c[0] for c in CASES])
+def test_full_size_sampled_residuals(name, lo):
+    cfg = W.config(name)
+    mesh = cfg.mesh()
+    s = _solver(mesh, cfg.order, cfg.params)
+    phi, psi = _state(cfg, s.solution_coords())
+    t = 0.4
+    gp, gs = s.residual(phi, psi, t)
+    s.set_state(phi)
+    s.precondition(0)                     # reset only: the smeared sign of psi0
+    gsgn = s.sign()
+    # the preconditioning residual at its starting point psi0 = phi - 1/2 (a distance
+    # function would make 1 - |grad psi| vanish to rounding and the residual ill-scaled)
+    psi0 = phi - 0.5
+    _, gpc = s.residual(None, psi0, 0.0, mode=1)
+
+    sub, full, inner = _sub_block(mesh, lo, M)
+    o = Oracle(cfg.ndims, cfg.order, sub, cfg.params)
+    full_t = torch.as_tensor(full)
+    sphi, spsi = phi[full_t], psi[full_t]
+    assert float((sphi * (1 - sphi)).max()) > 0.2, "the sub-block must contain the interface"
+    Rp, Rs = o.residual(sphi, spsi, t)
+    osgn = ores.smeared_sign(o.disc, cfg.params, sphi - 0.5)
+    Rpc = o.precond_residual(sphi - 0.5, osgn)
+    sel = full_t[torch.as_tensor(inner)]
+    ins = torch.as_tensor(inner)
+    for g, r, what in ((gp, Rp, "R_phi"), (gs, Rs, "R_psi"), (gsgn, osgn, "sign"),
+                       (gpc, Rpc, "R_pc")):
+        e = _rel(g[sel.to(g.device)].double().cpu(), r[ins])
+        print(f"[fullsize] {name} {what}: rel L_inf over {int(ins.sum())} elements {e:.2e}")
+        assert e <= TOL, (name, what, e)
+
+
+@pytest.mark.parametrize("name", ["C3", "C5"])
+def test_full_size_mass_conservation_and_free_stream(name):
+    from paper_2006_10967_amd import REDUCE_L1, REDUCE_MASS
+    cfg = W.config(name)
+    mesh = cfg.mesh()
+    s = _solver(mesh, cfg.order, cfg.params)
+    phi, psi = _state(cfg, s.solution_coords())
+    gp, _ = s.residual(phi, psi, 0.7)
+    m = s.reduce(REDUCE_MASS, gp)
+    a = s.reduce(REDUCE_L1, gp, torch.zeros_like(gp))
+    print(f"[fullsize] {name}: |int R_phi| / int |R_phi| = {abs(m) / a:.2e}")
+    assert abs(m) <= 1e-13 * a
+    # free stream: uniform velocity, constant state
+    prm = W.default_params(cfg.ndims, cfg.order, cfg.h, vel_kind=W.VEL_UNIFORM,
+                           vel_u0=(0.7, -0.4, 0.3))
+    s2 = _solver(mesh, cfg.order, prm)
+    scale = 1.0 / cfg.h
+    rs = s2.residual(torch.zeros_like(phi), torch.full_like(phi, -0.2), 0.0)[1]
+    worst = float(rs.abs().max())
+    for c in (0.0, 1.0):
+        rp = s2.residual(torch.full_like(phi, c), psi, 0.0)[0]
+        worst = max(worst, float(rp.abs().max()))
+    print(f"[fullsize] {name}: free stream max|R| = {worst:.2e} (scale {scale:.0f})")
+    assert worst <= 1e-12 * scale

@@ -337,3 +337,36 @@ def test_energy_stability_detects_flipped_penalty():
     A = _assemble(o, "psi", E, Nu)
     B = sq[:, None] * A / sq[None, :]
     assert np.linalg.eigvalsh(0.5 * (B + B.T)).max() > 1e-3
+
+
+def test_residual_is_local_to_one_element_layer():
+    """The residual of an element depends only on the elements within one layer of it
+    (diagonals included): on a copy-boundary sub-block cut out of a periodic mesh, every
+    element off the sub-block's outer layer has exactly the full-mesh residual. (The
+    full-size GPU tests sample their outputs this way.)"""
+    import torch as _t
+    from oracle import residual as ores
+    mesh, prm = W.small_case(3, 2, (9, 9, 9), perturb=0.2, vel_kind=W.VEL_LEVEQUE3D,
+                             vel_period=3.0)
+    o = Oracle(3, 2, mesh, prm)
+    x = o.coords()
+    c = (0.45, 0.5, 0.5)
+    phi = _t.tensor(W.ic_phi(x, c, 0.25, 0.05))
+    psi = _t.tensor(W.signed_distance_ball(x, c, 0.25))
+    Rp, Rs = o.residual(phi, psi, 0.3)
+    sgn = ores.smeared_sign(o.disc, prm, phi - 0.5)
+    Rpc = o.precond_residual(psi, sgn)
+    m, lo = 7, (1, 2, 1)
+    planes = [np.asarray(mesh.planes[k])[lo[k]:lo[k] + m + 1] for k in range(3)]
+    sub = W.box_mesh(planes, [False] * 3)
+    e = np.arange(sub.nelem)
+    ck = [(e // m ** k) % m for k in range(3)]
+    full = _t.as_tensor((ck[0] + lo[0]) + 9 * ((ck[1] + lo[1]) + 9 * (ck[2] + lo[2])))
+    inner = _t.as_tensor(np.all([(a >= 1) & (a <= m - 2) for a in ck], axis=0))
+    os_ = Oracle(3, 2, sub, prm)
+    rp, rs = os_.residual(phi[full], psi[full], 0.3)
+    ssgn = ores.smeared_sign(os_.disc, prm, phi[full] - 0.5)
+    rpc = os_.precond_residual(psi[full], ssgn)
+    for a, b in ((rp, Rp), (rs, Rs), (ssgn, sgn), (rpc, Rpc)):
+        assert _t.equal(a[inner], b[full][inner])
+        assert float((a[~inner] - b[full][~inner]).abs().max()) > 0   # the boundary differs
