@@ -201,6 +201,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--config", default="C2")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-bf16", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-adjoint", action="store_true")
@@ -276,21 +277,27 @@ def main():
         "precondition_ms_fp64": pc64,
     }
 
-    if not args.no_fp32:
-        s32, wall32, _, kt32, pc32, phi32 = run_form(cfg, mesh, "fp32", K, Wm, phi0)
-        v32 = cfg.dof * 4 * K / wall32
-        l1 = s64.l1(phi64, phi32.double())
+    forms = [f for f, off in (("fp32", args.no_fp32), ("bf16", args.no_bf16)) if not off]
+    if forms:
+        out["forms"] = {}
         mass64 = s64.mass(phi64)
         mass0 = s64.mass(torch.as_tensor(phi0))
-        mass32 = s64.mass(phi32.double())
-        out["forms"] = {"fp32": {
-            "value": v32, "ms_per_step": wall32 * 1e3 / K, "speedup_vs_fp64": v32 / value,
-            "interface_l1_vs_fp64": l1, "mass_drift_fp32": (mass32 - mass0) / mass0,
-            "mass_drift_fp64": (mass64 - mass0) / mass0, "precondition_ms": pc32,
+        ref = s64.mass(phi64)
+    for form in forms:
+        sf, wallf, _, ktf, pcf, phif = run_form(cfg, mesh, form, K, Wm, phi0)
+        vf = cfg.dof * 4 * K / wallf
+        l1 = s64.l1(phi64, phif.double())
+        massf = s64.mass(phif.double())
+        out["forms"][form] = {
+            "value": vf, "ms_per_step": wallf * 1e3 / K, "speedup_vs_fp64": vf / value,
+            "interface_l1_vs_fp64": l1, "interface_l1_vs_fp64_rel": l1 / ref,
+            "mass_drift": (massf - mass0) / mass0,
+            "mass_drift_fp64": (mass64 - mass0) / mass0, "precondition_ms": pcf,
             "kernels": {k: {"avg_us": (v[0] / v[1] * 1e3) if v[1] else None}
-                        for k, v in kt32.items()}}}
-        log(f"[bench] fp32: {wall32 * 1e3 / K:.4f} ms/step, {v32:.4e} DOF-stage/s, "
-            f"int|phi32-phi64| = {l1:.3e}")
+                        for k, v in ktf.items()}}
+        log(f"[bench] {form}: {wallf * 1e3 / K:.4f} ms/step, {vf:.4e} DOF-stage/s, "
+            f"int|phi_{form}-phi64| = {l1:.3e}")
+        del sf
 
     if not args.no_adjoint:
         adj = {}

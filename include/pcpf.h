@@ -24,7 +24,7 @@
  *   - Element e, solution point i: i = sum_k i_k n^k over the n = p+1 Gauss-Legendre
  *     points per direction (i_0 fastest). A per-point field is an array [E][N_u],
  *     N_u = n^d, in the state type of the context (double for PCPF_FP64, float for
- *     PCPF_FP32).
+ *     PCPF_FP32 and PCPF_BF16).
  *   - Face f = 2k + s of an element is the face at reference coordinate xi_k = -1 (s = 0)
  *     or +1 (s = 1). Face 2k+1 of element e must meet face 2k of nbr[e][2k+1] with the
  *     tangential reference axes of both faces pointing the same way in space.
@@ -51,7 +51,12 @@ typedef enum pcpf_status {
     PCPF_ENONFINITE = 5     /* the state became non-finite or |phi| > 10; state kept */
 } pcpf_status;
 
-enum { PCPF_FP64 = 0, PCPF_FP32 = 1 };                       /* precision of the form */
+/* Precision of the form. PCPF_FP64: everything in float64. PCPF_FP32: float32 state and
+ * arithmetic. PCPF_BF16: float32 state and pointwise arithmetic, with the element line
+ * operators of the gradient and the divergence (§3.1 Steps 3 and 6) applied on the matrix
+ * cores with bfloat16 operands and float32 accumulation. Reductions and the LOGIT reset
+ * are float64 in every form. */
+enum { PCPF_FP64 = 0, PCPF_FP32 = 1, PCPF_BF16 = 2 };
 enum { PCPF_VEL_UNIFORM = 0, PCPF_VEL_ROTATION = 1,           /* analytic velocity kinds */
        PCPF_VEL_SINGLE_VORTEX = 2, PCPF_VEL_LEVEQUE3D = 3 };
 enum { PCPF_RESET_LINEAR = 0, PCPF_RESET_LOGIT = 1 };         /* psi reset transform */
@@ -104,7 +109,7 @@ typedef struct pcpf_params {
     int32_t reset_mode;  /* PCPF_RESET_* */
     int32_t reset_every; /* reset + precondition before steps with index % N == 0 (0: never) */
     int32_t precond_iters; /* pseudo-time RK4 iterations per reset (>= 0) */
-    int32_t precision;   /* PCPF_FP64 or PCPF_FP32 */
+    int32_t precision;   /* PCPF_FP64, PCPF_FP32 or PCPF_BF16 */
     int32_t reserved[3]; /* must be 0 */
 } pcpf_params;
 
@@ -240,7 +245,8 @@ pcpf_status pcpf_ckpt_bytes(const pcpf_ctx* ctx, int64_t nsteps, int64_t every,
  * time and step, dt, nsteps, every, A, whether psi was set) for pcpf_adjoint. When resets
  * are scheduled, every <= reset_every is required (at most one reset per segment), and a
  * run that starts without psi must start on the reset schedule. Synchronous. ESTATE
- * without a state, EINVAL, ENONFINITE (the run is then not recorded). */
+ * without a state, EINVAL, ENONFINITE (the run is then not recorded), EUNSUPPORTED for
+ * the PCPF_BF16 form (the adjoint kernels differentiate the FP64 and FP32 forms). */
 pcpf_status pcpf_forward_ckpt(pcpf_ctx* ctx, double dt, int64_t nsteps, int64_t every,
                               void* d_ckpt, size_t ckpt_bytes);
 

@@ -12,7 +12,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "pcpf.h")
 PCPF_OK, PCPF_EINVAL, PCPF_EDEVICE, PCPF_EUNSUPPORTED, PCPF_ESTATE, PCPF_ENONFINITE = range(6)
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "EDEVICE", 3: "EUNSUPPORTED", 4: "ESTATE",
                 5: "ENONFINITE"}
-PCPF_FP64, PCPF_FP32 = 0, 1
+PCPF_FP64, PCPF_FP32, PCPF_BF16 = 0, 1, 2
 PCPF_MODE_PHYS, PCPF_MODE_PRECOND = 0, 1
 PCPF_REDUCE_MASS, PCPF_REDUCE_L1 = 0, 1
 MAX_ORDER = 6

@@ -251,7 +251,7 @@ struct Layout {
 };
 
 Layout layout(const MeshInfo& mi, int precision) {
-    const size_t r = precision == PCPF_FP32 ? 4 : 8;
+    const size_t r = precision != PCPF_FP64 ? 4 : 8;
     const size_t E = (size_t)mi.E;
     const size_t state = 2 * E * mi.nu * r;              // two variables
     const size_t face = 2 * E * mi.d * mi.nfa * r;
@@ -403,6 +403,7 @@ GFArgs<R> gf_args(const Ctx<R>& C, const R* u0, const R* u1, double t) {
     a.E = c->mi.E;
     a.ph = phys<R>(c->prm, t);
     a.axis = c->axis ? 1 : 0;
+    a.mf = c->prm.precision == PCPF_BF16 ? 1 : 0;
     return a;
 }
 
@@ -784,10 +785,10 @@ struct AdjLayout {
 };
 
 AdjLayout adj_layout(const pcpf_ctx* c, int64_t every) {
-    const size_t r = c->prm.precision == PCPF_FP32 ? 4 : 8;
+    const size_t r = c->prm.precision != PCPF_FP64 ? 4 : 8;
     const size_t S = (size_t)c->mi.E * c->mi.nu;
     const size_t F = (size_t)c->mi.E * c->mi.d * c->mi.nfa;
-    const int epb = c->prm.precision == PCPF_FP32 ? c->A32.epb : c->A64.epb;
+    const int epb = c->prm.precision != PCPF_FP64 ? c->A32.epb : c->A64.epb;
     const size_t nblocks = (size_t)((c->mi.E + epb - 1) / epb);
     AdjLayout L{};
     size_t off = 0;
@@ -1078,13 +1079,13 @@ pcpf_status check_ctx(pcpf_ctx* c) {
 }
 
 #define DISPATCH(c, fn, ...) \
-    ((c)->prm.precision == PCPF_FP32 ? fn<float>(Ctx<float>{c}, __VA_ARGS__) \
+    ((c)->prm.precision != PCPF_FP64 ? fn<float>(Ctx<float>{c}, __VA_ARGS__) \
                                      : fn<double>(Ctx<double>{c}, __VA_ARGS__))
 
 pcpf_status check_params(const pcpf_params* p, std::string* err) {
     if (!p) return fail(err, PCPF_EINVAL, "params is NULL");
-    if (p->precision != PCPF_FP64 && p->precision != PCPF_FP32)
-        return fail(err, PCPF_EUNSUPPORTED, "precision must be PCPF_FP64 or PCPF_FP32");
+    if (p->precision != PCPF_FP64 && p->precision != PCPF_FP32 && p->precision != PCPF_BF16)
+        return fail(err, PCPF_EUNSUPPORTED, "precision must be PCPF_FP64, PCPF_FP32 or PCPF_BF16");
     if (p->vel_kind < 0 || p->vel_kind > 3) return fail(err, PCPF_EINVAL, "unknown vel_kind");
     if (p->reset_mode != PCPF_RESET_LINEAR && p->reset_mode != PCPF_RESET_LOGIT)
         return fail(err, PCPF_EINVAL, "unknown reset_mode");
@@ -1170,14 +1171,14 @@ pcpf_status pcpf_create(const pcpf_mesh* m, const pcpf_params* p, void* d_ws, si
         for (int i = 0; i < mi.d; ++i)
             for (int j = 0; j < mi.d; ++j)
                 if (i != j && m->jac[(e * mi.d + i) * mi.d + j] != 0.0) c->axis = false;
-    bool ok = p->precision == PCPF_FP32
+    bool ok = p->precision != PCPF_FP64
                   ? (get_launchers<float>(mi.d, mi.p, &c->L32) && get_adj_launchers<float>(mi.d, mi.p, &c->A32))
                   : (get_launchers<double>(mi.d, mi.p, &c->L64) && get_adj_launchers<double>(mi.d, mi.p, &c->A64));
     if (!ok) {
         delete c;
         return fail(nullptr, PCPF_EUNSUPPORTED, "no kernels built for this (d, p)");
     }
-    st = p->precision == PCPF_FP32 ? upload<float>(c, m) : upload<double>(c, m);
+    st = p->precision != PCPF_FP64 ? upload<float>(c, m) : upload<double>(c, m);
     if (st != PCPF_OK) {
         g_err = c->err;
         delete c;
@@ -1201,7 +1202,7 @@ pcpf_status pcpf_set_state(pcpf_ctx* c, const void* d_phi, const void* d_psi, do
     if (check_ctx(c) != PCPF_OK) return PCPF_EINVAL;
     if (!d_phi) return fail(&c->err, PCPF_EINVAL, "d_phi is NULL");
     if (step < 0) return fail(&c->err, PCPF_EINVAL, "step must be >= 0");
-    const size_t bytes = (size_t)c->mi.E * c->mi.nu * (c->prm.precision == PCPF_FP32 ? 4 : 8);
+    const size_t bytes = (size_t)c->mi.E * c->mi.nu * (c->prm.precision != PCPF_FP64 ? 4 : 8);
     HIPCHK(c, hipMemcpyAsync(c->ws + c->L.un, d_phi, bytes, hipMemcpyDeviceToDevice, c->stream));
     if (d_psi)
         HIPCHK(c, hipMemcpyAsync(c->ws + c->L.un + bytes, d_psi, bytes, hipMemcpyDeviceToDevice,
@@ -1217,7 +1218,7 @@ pcpf_status pcpf_set_state(pcpf_ctx* c, const void* d_phi, const void* d_psi, do
 pcpf_status pcpf_get_state(pcpf_ctx* c, void* d_phi, void* d_psi, double* t, int64_t* step) {
     if (check_ctx(c) != PCPF_OK) return PCPF_EINVAL;
     if (!c->has_state) return fail(&c->err, PCPF_ESTATE, "no state set");
-    const size_t bytes = (size_t)c->mi.E * c->mi.nu * (c->prm.precision == PCPF_FP32 ? 4 : 8);
+    const size_t bytes = (size_t)c->mi.E * c->mi.nu * (c->prm.precision != PCPF_FP64 ? 4 : 8);
     if (d_phi)
         HIPCHK(c, hipMemcpyAsync(d_phi, c->ws + c->L.un, bytes, hipMemcpyDeviceToDevice, c->stream));
     if (d_psi) {
@@ -1265,7 +1266,7 @@ pcpf_status pcpf_get_sign(pcpf_ctx* c, void* d_sgn) {
     if (check_ctx(c) != PCPF_OK) return PCPF_EINVAL;
     if (!c->has_sign) return fail(&c->err, PCPF_ESTATE, "no reset has run");
     if (!d_sgn) return fail(&c->err, PCPF_EINVAL, "d_sgn is NULL");
-    const size_t bytes = (size_t)c->mi.E * c->mi.nu * (c->prm.precision == PCPF_FP32 ? 4 : 8);
+    const size_t bytes = (size_t)c->mi.E * c->mi.nu * (c->prm.precision != PCPF_FP64 ? 4 : 8);
     HIPCHK(c, hipMemcpyAsync(d_sgn, c->ws + c->L.sgn, bytes, hipMemcpyDeviceToDevice, c->stream));
     return PCPF_OK;
 }
@@ -1321,7 +1322,7 @@ pcpf_status pcpf_set_velocity_amplitude(pcpf_ctx* c, double amp) {
 pcpf_status pcpf_ckpt_bytes(const pcpf_ctx* c, int64_t nsteps, int64_t every, size_t* nbytes) {
     if (!c || !nbytes) return fail(nullptr, PCPF_EINVAL, "ckpt_bytes: NULL argument");
     if (nsteps < 1 || every < 1) return fail(nullptr, PCPF_EINVAL, "nsteps and every must be >= 1");
-    const size_t r = c->prm.precision == PCPF_FP32 ? 4 : 8;
+    const size_t r = c->prm.precision != PCPF_FP64 ? 4 : 8;
     *nbytes = (size_t)((nsteps + every - 1) / every) * 2 * (size_t)c->mi.E * c->mi.nu * r;
     return PCPF_OK;
 }
@@ -1329,6 +1330,8 @@ pcpf_status pcpf_ckpt_bytes(const pcpf_ctx* c, int64_t nsteps, int64_t every, si
 pcpf_status pcpf_forward_ckpt(pcpf_ctx* c, double dt, int64_t nsteps, int64_t every, void* d_ckpt,
                               size_t ckpt_bytes) {
     if (check_ctx(c) != PCPF_OK) return PCPF_EINVAL;
+    if (c->prm.precision == PCPF_BF16)
+        return fail(&c->err, PCPF_EUNSUPPORTED, "no adjoint of the PCPF_BF16 form");
     if (!c->has_state) return fail(&c->err, PCPF_ESTATE, "no state set");
     size_t need = 0;
     if (pcpf_ckpt_bytes(c, nsteps, every, &need) != PCPF_OK || !std::isfinite(dt))

@@ -105,6 +105,7 @@ struct GFArgs {
     Phys<R> ph;
     int axis;            // every element axis-aligned (diagonal J): diagonal-Jacobian
                          // arithmetic and velocity from per-element 1D sin/cos tables
+    int mf;              // line operators on the matrix cores, bf16 operands (float only)
 };
 
 // update kernel kinds

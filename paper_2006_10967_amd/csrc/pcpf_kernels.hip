@@ -25,6 +25,7 @@
 
 #include "pcpf_device.h"
 #include "pcpf_internal.h"
+#include "pcpf_mfma.h"
 
 namespace pcpf {
 namespace {
@@ -52,12 +53,17 @@ using namespace dev;
 #define PCPF_GF_WAVES 0
 #endif
 
-template <typename R, int D, int P, int MODE, bool AXIS>
+// MF: the line operators of the gradient (DT, and lp for the own traces) and of the
+// divergence (DH) run on the matrix cores with bf16 operands and fp32 accumulation (the
+// BF16 form; R = float); the pointwise flux math, the face interpolations and the sensor
+// stay in fp32 on the vector units.
+template <typename R, int D, int P, int MODE, bool AXIS, bool MF = false>
 __global__ __launch_bounds__((Shape<D, P>::NT))
 #if PCPF_GF_WAVES > 0
 __attribute__((amdgpu_waves_per_eu(PCPF_GF_WAVES)))
 #endif
 void k_grad_flux(GFArgs<R> a) {
+    static_assert(!MF || std::is_same<R, float>::value, "the matrix-core form is fp32");
     using S = Shape<D, P>;
     constexpr int N = S::N, NU = S::NU, NFA = S::NFA, EPB = S::EPB, NT = S::NT, G = S::GEO;
     constexpr int V = (MODE == GF_PHYS) ? 2 : 1;
@@ -82,6 +88,7 @@ void k_grad_flux(GFArgs<R> a) {
     __shared__ R s_nu[EPB];
     __shared__ R s_fn[FLUX && !AXIS ? EPB * D * (D + 1) : 1];  // + face unit normal, scale
     __shared__ int s_nbr[EPB * 2 * D];
+    __shared__ R s_tr[MF ? V * D * EPB * NFA : 1];       // own + face traces (MF)
 
     const int tid = threadIdx.x;
     const int64_t e0 = (int64_t)blockIdx.x * EPB;
@@ -270,6 +277,54 @@ void k_grad_flux(GFArgs<R> a) {
 
     if constexpr (GRAD) {
         // ---- B: corrected gradient (Steps 1-3) and fluxes at solution points (Step 4) ---
+        // The matrix-core form first applies [DT; lp] along the lines of every direction
+        // (16 lines per instruction): s_x <- DT u, s_tr <- the own + face trace lp u.
+        const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+        const int lane = tid & 63;
+        // every lane of a wave takes part: unit j of the wave is direction k = u / WK,
+        // lines (u % WK) * 64 + 16 g + lane % 16, g = 0..3 (wave-uniform k)
+        auto mf_lines = [&](auto body) {
+#pragma unroll
+            for (int j = 0; j < S::UPW; ++j) {
+                const int u = wave + j * S::NW;
+                if (u >= S::NUNITS) break;
+                const int k = u / S::WK;
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const int item = (u - k * S::WK) * 64 + 16 * g + (lane & 15);
+                    const bool ok = item < nel * NFA;
+                    const int el = ok ? item / NFA : 0, t = ok ? item - el * NFA : 0;
+                    if (k == 0) {
+                        body(std::integral_constant<int, 0>{}, ok, el, t, item);
+                    } else if (k == 1) {
+                        body(std::integral_constant<int, 1>{}, ok, el, t, item);
+                    } else if constexpr (D == 3) {
+                        body(std::integral_constant<int, 2>{}, ok, el, t, item);
+                    }
+                }
+            }
+        };
+        if constexpr (MF) {
+            const bf16x4 aG = mfma_rows<N + 1, N>(
+                [&](int i, int k) { return i < N ? s_ops[op_dt(N) + i * N + k] : s_ops[op_lp(N) + k]; },
+                lane);
+            mf_lines([&](auto KC, bool ok, int el, int t, int item) {
+                constexpr int K = decltype(KC)::value;
+                constexpr int SK = st<N>(K);
+                const int base = el * NU + face_base<D, N>(K, t);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const f32x4 r = mfma_lines<N>(aG, s_u[v], ok, base, SK, lane);
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) {
+                        const int row = 4 * (lane >> 4) + jj;
+                        if (ok && row < N) s_x[(v * D + K) * XST + base + row * SK] = r[jj];
+                        if (ok && row == N) s_tr[(v * D + K) * EPB * NFA + item] = r[jj];
+                    }
+                }
+            });
+            __syncthreads();
+        }
         R Sdet = R(0);
         if (pt) {
             const R* gg = &s_geo[le * G];
@@ -285,14 +340,23 @@ void k_grad_flux(GFArgs<R> a) {
                     // + face with a neighbour: the LDG jump (nb - own trace) is lifted; the
                     // own-trace part is folded into DT = D1 - cp (x) lp
                     const bool hk = s_nbr[le * 2 * D + 2 * k + 1] >= 0;
-                    const R* Dk = &s_ops[hk ? op_dt(N) : OP_D1] + mi[k] * N;
-                    const int b0 = le * NU + ip - mi[k] * st<N>(k);
-                    R acc = R(0);
+                    const int tk = tang_index<D, N>(k, mi);
+                    if constexpr (MF) {
+                        // DT u from the matrix cores; on a boundary + face the "neighbour"
+                        // trace is the own trace (no jump)
+                        const R nbk = hk ? s_nb[v][le * NPF + k * NFA + tk]
+                                         : s_tr[(v * D + k) * EPB * NFA + le * NFA + tk];
+                        qt[k] = s_x[(v * D + k) * XST + tid] + cp[mi[k]] * nbk;
+                    } else {
+                        const R* Dk = &s_ops[hk ? op_dt(N) : OP_D1] + mi[k] * N;
+                        const int b0 = le * NU + ip - mi[k] * st<N>(k);
+                        R acc = R(0);
 #pragma unroll
-                    for (int b = 0; b < N; ++b) acc += Dk[b] * s_u[v][b0 + b * st<N>(k)];
-                    // boundary + faces: s_nb holds 0 (those slots are never written)
-                    acc += cp[mi[k]] * s_nb[v][le * NPF + k * NFA + tang_index<D, N>(k, mi)];
-                    qt[k] = acc;
+                        for (int b = 0; b < N; ++b) acc += Dk[b] * s_u[v][b0 + b * st<N>(k)];
+                        // boundary + faces: s_nb holds 0 (those slots are never written)
+                        acc += cp[mi[k]] * s_nb[v][le * NPF + k * NFA + tk];
+                        qt[k] = acc;
+                    }
                 }
 #pragma unroll
                 for (int i = 0; i < D; ++i) {
@@ -537,8 +601,6 @@ void k_grad_flux(GFArgs<R> a) {
             }
         };
         // wave-uniform direction: each unit is one wave's worth of one direction's points
-        const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-        const int lane = tid & 63;
         auto face_pass = [&](auto SC) {
             constexpr int SD = decltype(SC)::value;
 #pragma unroll
@@ -564,7 +626,40 @@ void k_grad_flux(GFArgs<R> a) {
         if (has_bnd) face_pass(std::integral_constant<int, 0>{});
 
         // ---- E: volume part of Step 6, P = sum_k DH_k f~_k (- |J| S) ---------------------
-        if (pt) {
+        if constexpr (MF) {
+            // DH along the lines of every direction on the matrix cores, in place (the
+            // direction-K field of s_f is touched only by the direction-K lines), then the
+            // directions summed per point
+            const bf16x4 aH = mfma_rows<N, N>(
+                [&](int i, int k) { return s_ops[op_dh(N) + i * N + k]; }, lane);
+            mf_lines([&](auto KC, bool ok, int el, int t, int item) {
+                (void)item;
+                constexpr int K = decltype(KC)::value;
+                constexpr int SK = st<N>(K);
+                const int base = el * NU + face_base<D, N>(K, t);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    R* fk = &s_f[(v * D + K) * XST];
+                    const f32x4 r = mfma_lines<N>(aH, fk, ok, base, SK, lane);
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) {
+                        const int row = 4 * (lane >> 4) + jj;
+                        if (ok && row < N) fk[base + row * SK] = r[jj];
+                    }
+                }
+            });
+            __syncthreads();
+            if (pt) {
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    R acc = R(0);
+#pragma unroll
+                    for (int k = 0; k < D; ++k) acc += s_f[(v * D + k) * XST + tid];
+                    if constexpr (MODE == GF_PRECOND) acc -= Sdet;
+                    gst(a.P[v] + e0 * NU, tid, acc);
+                }
+            }
+        } else if (pt) {
             const R* DH = &s_ops[op_dh(N)];
 #pragma unroll
             for (int v = 0; v < V; ++v) {
@@ -870,6 +965,27 @@ struct Impl {
                           hipEvent_t e1) {
         (void)nvar;
         const dim3 g(grid(a.E)), b(S::NT);
+        if constexpr (std::is_same<R, float>::value) {
+            if (a.mf) {
+                switch (mode) {
+                    case GF_PHYS:
+                        if (a.axis)
+                            hipExtLaunchKernelGGL((k_grad_flux<R, D, P, GF_PHYS, true, true>), g, b, 0, st, e0, e1, 0, a);
+                        else
+                            hipExtLaunchKernelGGL((k_grad_flux<R, D, P, GF_PHYS, false, true>), g, b, 0, st, e0, e1, 0, a);
+                        break;
+                    case GF_PRECOND:
+                        if (a.axis)
+                            hipExtLaunchKernelGGL((k_grad_flux<R, D, P, GF_PRECOND, true, true>), g, b, 0, st, e0, e1, 0, a);
+                        else
+                            hipExtLaunchKernelGGL((k_grad_flux<R, D, P, GF_PRECOND, false, true>), g, b, 0, st, e0, e1, 0, a);
+                        break;
+                    case GF_SIGN: hipExtLaunchKernelGGL((k_grad_flux<R, D, P, GF_SIGN, false, true>), g, b, 0, st, e0, e1, 0, a); break;
+                    default: hipExtLaunchKernelGGL((k_grad_flux<R, D, P, GF_SENSOR, false>), g, b, 0, st, e0, e1, 0, a); break;
+                }
+                return;
+            }
+        }
         switch (mode) {
             case GF_PHYS:
                 if (a.axis)

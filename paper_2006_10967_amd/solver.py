@@ -14,12 +14,12 @@ import torch
 from . import _lib
 from ._lib import PcpfMesh, PcpfParams, check
 
-FP64, FP32 = _lib.PCPF_FP64, _lib.PCPF_FP32
+FP64, FP32, BF16 = _lib.PCPF_FP64, _lib.PCPF_FP32, _lib.PCPF_BF16
 MODE_PHYS, MODE_PRECOND = _lib.PCPF_MODE_PHYS, _lib.PCPF_MODE_PRECOND
 REDUCE_MASS, REDUCE_L1 = _lib.PCPF_REDUCE_MASS, _lib.PCPF_REDUCE_L1
 
-_PRECISIONS = {"fp64": FP64, "fp32": FP32, FP64: FP64, FP32: FP32}
-_DTYPES = {FP64: torch.float64, FP32: torch.float32}
+_PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16, FP64: FP64, FP32: FP32, BF16: BF16}
+_DTYPES = {FP64: torch.float64, FP32: torch.float32, BF16: torch.float32}
 
 
 def _dptr(a: np.ndarray):
