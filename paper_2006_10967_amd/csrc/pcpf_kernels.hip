@@ -254,10 +254,12 @@ void k_grad_flux(GFArgs<R> a) {
             __syncthreads();
         }
         const R* chi = s_x + ((D - 1) & 1) * XST;
-        if (tid < nel) {
-            R ea = R(0), et = R(0);
-            for (int i = 0; i < NU; ++i) {
-                const R c = chi[tid * NU + i];
+        // modal energies of each element. Small elements: one thread per element sums its
+        // points in order; large elements (N_u >= 64): a wave per element, lanes over its
+        // points, then a fixed butterfly (lane 0's sum is used: deterministic).
+        auto energies = [&](int el, int i0, int di, R& ea, R& et) {
+            for (int i = i0; i < NU; i += di) {
+                const R c = chi[el * NU + i];
                 ea += c * c;
                 int r = i, top = 0;
 #pragma unroll
@@ -267,9 +269,31 @@ void k_grad_flux(GFArgs<R> a) {
                 }
                 if (top) et += c * c;
             }
+        };
+        auto set_nu = [&](int el, R ea, R et) {
             const R nu = visc_ramp(ea, et, a.ph.s0, a.ph.kappa, a.ph.nu_max);
-            s_nu[tid] = nu;
-            if constexpr (MODE == GF_SENSOR) gst(a.out + e0, tid, nu);
+            s_nu[el] = nu;
+            if constexpr (MODE == GF_SENSOR) gst(a.out + e0, el, nu);
+        };
+        if constexpr (NU < 64) {
+            if (tid < nel) {
+                R ea = R(0), et = R(0);
+                energies(tid, 0, 1, ea, et);
+                set_nu(tid, ea, et);
+            }
+        } else {
+            const int swave = __builtin_amdgcn_readfirstlane(tid >> 6);
+            const int slane = tid & 63;
+            for (int el = swave; el < nel; el += S::NW) {
+                R ea = R(0), et = R(0);
+                energies(el, slane, 64, ea, et);
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) {
+                    ea += __shfl_xor(ea, off, 64);
+                    et += __shfl_xor(et, off, 64);
+                }
+                if (slane == 0) set_nu(el, ea, et);
+            }
         }
         __syncthreads();
         if constexpr (MODE == GF_SENSOR) return;
