@@ -150,6 +150,12 @@ pcpf_status check_mesh(const pcpf_mesh* m, MeshInfo* mi, std::string* err) {
     mi->nu = ipow(mi->n, mi->d);
     mi->nfa = ipow(mi->n, mi->d - 1);
     mi->E = m->nelem;
+    // the kernels address every per-element array with 32-bit byte offsets
+    const int64_t geo = mi->d + 2 * mi->d * mi->d + 1;
+    const int64_t per = std::max<int64_t>({mi->nu, geo, 2 * (int64_t)mi->d * mi->nfa});
+    if (mi->E * per * 8 >= ((int64_t)1 << 32))
+        return fail(err, PCPF_EUNSUPPORTED,
+                    "mesh too large: every per-element array must stay below 4 GiB");
     return PCPF_OK;
 }
 

@@ -145,3 +145,25 @@ def test_workspace_bytes_scale_with_precision():
     # five state registers + three face fields dominate
     E, nu, nfa = 64, 64, 16
     assert sizes[0] >= 8 * (5 * 2 * E * nu + 3 * 2 * E * 3 * nfa)
+
+
+def test_meshes_beyond_32_bit_array_offsets_are_refused():
+    """Every per-element array must stay below 4 GiB (the kernels use 32-bit byte
+    offsets): a 3D p=5 mesh of 3 M elements (216 points each) is refused before any
+    array is read, and the 96^3 p=4 workload is accepted."""
+    lib = _lib.load()
+    prm = make_params(W.small_case(3, 5, (1, 1, 1))[1], "fp64")
+    m = MeshArgs(3, 5, np.zeros((1, 3)), np.eye(3)[None], -np.ones((1, 6)),
+                 ops=P.line_operators(5))
+    m.c.nelem = 3_000_000
+    nb = ctypes.c_size_t()
+    st = lib.pcpf_workspace_bytes(ctypes.byref(m.c), ctypes.byref(prm), ctypes.byref(nb))
+    assert st == _lib.PCPF_EUNSUPPORTED
+    assert "4 GiB" in lib.pcpf_last_error(None).decode()
+    m.c.order = 4
+    m.c.nelem = 96 ** 3
+    m4 = MeshArgs(3, 4, np.zeros((1, 3)), np.eye(3)[None], -np.ones((1, 6)),
+                  ops=P.line_operators(4))
+    m4.c.nelem = 96 ** 3
+    st = lib.pcpf_workspace_bytes(ctypes.byref(m4.c), ctypes.byref(prm), ctypes.byref(nb))
+    assert st == _lib.PCPF_OK and nb.value > 10 * 2 ** 30
