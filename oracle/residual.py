@@ -69,7 +69,11 @@ def _unit(q, delta):
 
 
 def physical_residual(disc, prm, phi, psi, t, amp=None):
-    """du/dt of the physical system at time t: returns (R_phi, R_psi), each [E, Nu]."""
+    """du/dt of the physical system at time t: returns (R_phi, R_psi), each [E, Nu].
+
+    The interface normal of the sharpening flux is grad(psi)/|grad psi| (§2, the
+    preconditioned method); with prm.normal_mode == 1 it is grad(phi)/|grad phi|, the
+    normal of Eq. conservativephasefieldeq in its original (unpreconditioned) form."""
     A = prm.vel_amp if amp is None else amp
     kind, T, u0 = prm.vel_kind, prm.vel_period, prm.vel_u0
     vs = vel.velocity(kind, disc.txs, t, A, T, u0)          # [E, Nu, d]
@@ -79,21 +83,23 @@ def physical_residual(disc, prm, phi, psi, t, amp=None):
 
     phif, qphi = corrected_gradient(disc, phi)
     psif, qpsi = corrected_gradient(disc, psi)
+    from_phi = getattr(prm, "normal_mode", 0) == 1
+    qnrm = qphi if from_phi else qpsi          # the field the interface normal comes from
 
     # Step 4: fluxes at solution points
     m_s = torch.clamp(torch.linalg.vector_norm(vs, dim=-1), min=gamma)
     fvis_s = m_s[..., None] * (eps * qphi - gamma * (phi * (1 - phi))[..., None]
-                               * _unit(qpsi, prm.delta_n))
+                               * _unit(qnrm, prm.delta_n))
     ft_phi = _transform_flux(disc, phi[..., None] * vs - fvis_s)
     ft_psi = _transform_flux(disc, psi[..., None] * vs)
 
     # Step 5: common normal fluxes
     n = disc.tnormal
     beta = disc.tbeta
-    qphif, qpsif = _M0(disc, qphi), _M0(disc, qpsi)
+    qphif, qnrmf = _M0(disc, qphi), _M0(disc, qnrm)
     m_f = torch.clamp(torch.linalg.vector_norm(vf, dim=-1), min=gamma)
     fvis_f = m_f[..., None] * (eps * qphif - gamma * (phif * (1 - phif))[..., None]
-                               * _unit(qpsif, prm.delta_n))
+                               * _unit(qnrmf, prm.delta_n))
     fvis_n = disc.neighbour(fvis_f)
     phin, psin = disc.neighbour(phif), disc.neighbour(psif)
 

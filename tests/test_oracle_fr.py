@@ -370,3 +370,26 @@ def test_residual_is_local_to_one_element_layer():
     for a, b in ((rp, Rp), (rs, Rs), (ssgn, sgn), (rpc, Rpc)):
         assert _t.equal(a[inner], b[full][inner])
         assert float((a[~inner] - b[full][~inner]).abs().max()) > 0   # the boundary differs
+
+
+def test_unpreconditioned_normal_reduces_to_psi_equal_phi():
+    """The unpreconditioned form takes the interface normal from phi (the original
+    conservative phase field, §2): its phi residual is the preconditioned one evaluated
+    with psi := phi, for any psi, and its psi residual is unchanged."""
+    import dataclasses
+    import torch as _t
+    mesh, prm = W.small_case(2, 3, (5, 4), vel_kind=W.VEL_SINGLE_VORTEX, vel_period=4.0)
+    o0 = Oracle(2, 3, mesh, prm)
+    o1 = Oracle(2, 3, mesh, dataclasses.replace(prm, normal_mode=W.NORMAL_PHI))
+    x = o0.coords()
+    rng = np.random.default_rng(4)
+    phi = _t.tensor(W.ic_phi(x, (0.5, 0.55), 0.3, 0.05))
+    psi = _t.tensor(rng.standard_normal(phi.shape))
+    Rp1, Rs1 = o1.residual(phi, psi, 0.2)
+    Rp0, _ = o0.residual(phi, phi, 0.2)
+    _, Rs0 = o0.residual(phi, psi, 0.2)
+    assert _t.equal(Rp1, Rp0)
+    assert _t.equal(Rs1, Rs0)
+    # and it differs from the preconditioned residual with the given psi
+    Rpp, _ = o0.residual(phi, psi, 0.2)
+    assert float((Rpp - Rp1).abs().max()) > 1e-3 * float(Rp1.abs().max())

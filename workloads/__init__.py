@@ -30,6 +30,8 @@ VEL_LEVEQUE3D = 3
 
 RESET_LINEAR = 0
 RESET_LOGIT = 1
+NORMAL_PSI = 0   # interface normal from the preconditioned level set psi (§2, the method)
+NORMAL_PHI = 1   # normal from phi itself: the unpreconditioned conservative phase field
 
 
 # --------------------------------------------------------------------------------------
@@ -178,6 +180,7 @@ class Params:
     vel_amp: float = 1.0
     vel_period: float = 1.0
     vel_u0: tuple = (0.0, 0.0, 0.0)
+    normal_mode: int = NORMAL_PSI
 
 
 def default_params(ndims: int, order: int, h: float, *, eps_w: Optional[float] = None,
