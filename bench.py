@@ -61,7 +61,8 @@ def step_alg_bytes_per_dof(d, p, word):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("pcpf_kernels.hip", "pcpf_internal.h", "pcpf_device.h"):
+    for f in ("pcpf_kernels.hip", "pcpf_kernels_impl.h", "pcpf_internal.h", "pcpf_device.h",
+              "pcpf_mfma.h"):
         with open(os.path.join(ROOT, "paper_2006_10967_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

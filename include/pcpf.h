@@ -62,6 +62,9 @@ enum { PCPF_VEL_UNIFORM = 0, PCPF_VEL_ROTATION = 1,           /* analytic veloci
 enum { PCPF_RESET_LINEAR = 0, PCPF_RESET_LOGIT = 1 };         /* psi reset transform */
 enum { PCPF_MODE_PHYS = 0, PCPF_MODE_PRECOND = 1 };           /* residual kind */
 enum { PCPF_REDUCE_MASS = 0, PCPF_REDUCE_L1 = 1 };            /* FP64 reductions */
+enum { PCPF_NORMAL_PSI = 0,  /* interface normal grad psi / |grad psi| (§2, the method) */
+       PCPF_NORMAL_PHI = 1 };/* grad phi / |grad phi|: the unpreconditioned conservative phase
+                                field of §2 (psi is still advected but not used) */
 
 /* Mesh and FR operators (host memory, float64, row-major). */
 typedef struct pcpf_mesh {
@@ -110,7 +113,8 @@ typedef struct pcpf_params {
     int32_t reset_every; /* reset + precondition before steps with index % N == 0 (0: never) */
     int32_t precond_iters; /* pseudo-time RK4 iterations per reset (>= 0) */
     int32_t precision;   /* PCPF_FP64, PCPF_FP32 or PCPF_BF16 */
-    int32_t reserved[3]; /* must be 0 */
+    int32_t normal_mode; /* PCPF_NORMAL_PSI (default) or PCPF_NORMAL_PHI */
+    int32_t reserved[2]; /* must be 0 */
 } pcpf_params;
 
 typedef struct pcpf_ctx pcpf_ctx;
@@ -246,7 +250,8 @@ pcpf_status pcpf_ckpt_bytes(const pcpf_ctx* ctx, int64_t nsteps, int64_t every,
  * are scheduled, every <= reset_every is required (at most one reset per segment), and a
  * run that starts without psi must start on the reset schedule. Synchronous. ESTATE
  * without a state, EINVAL, ENONFINITE (the run is then not recorded), EUNSUPPORTED for
- * the PCPF_BF16 form (the adjoint kernels differentiate the FP64 and FP32 forms). */
+ * the PCPF_BF16 form and for PCPF_NORMAL_PHI (the adjoint kernels differentiate the
+ * FP64 and FP32 forms of the method with the psi normal). */
 pcpf_status pcpf_forward_ckpt(pcpf_ctx* ctx, double dt, int64_t nsteps, int64_t every,
                               void* d_ckpt, size_t ckpt_bytes);
 

@@ -14,6 +14,7 @@ STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "EDEVICE", 3: "EUNSUPPORTED", 4: "ESTAT
                 5: "ENONFINITE"}
 PCPF_FP64, PCPF_FP32, PCPF_BF16 = 0, 1, 2
 PCPF_MODE_PHYS, PCPF_MODE_PRECOND = 0, 1
+PCPF_NORMAL_PSI, PCPF_NORMAL_PHI = 0, 1
 PCPF_REDUCE_MASS, PCPF_REDUCE_L1 = 0, 1
 MAX_ORDER = 6
 
@@ -37,7 +38,8 @@ class PcpfParams(ctypes.Structure):
                 ("vel_period", ctypes.c_double), ("vel_u0", ctypes.c_double * 3),
                 ("vel_kind", ctypes.c_int32), ("reset_mode", ctypes.c_int32),
                 ("reset_every", ctypes.c_int32), ("precond_iters", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("precision", ctypes.c_int32), ("normal_mode", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class PcpfError(RuntimeError):

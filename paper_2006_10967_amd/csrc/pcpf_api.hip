@@ -410,6 +410,7 @@ GFArgs<R> gf_args(const Ctx<R>& C, const R* u0, const R* u1, double t) {
     a.ph = phys<R>(c->prm, t);
     a.axis = c->axis ? 1 : 0;
     a.mf = c->prm.precision == PCPF_BF16 ? 1 : 0;
+    a.nphi = c->prm.normal_mode == PCPF_NORMAL_PHI ? 1 : 0;
     return a;
 }
 
@@ -1107,7 +1108,9 @@ pcpf_status check_params(const pcpf_params* p, std::string* err) {
         return fail(err, PCPF_EINVAL, "vel_period must be > 0");
     if (p->reset_mode == PCPF_RESET_LOGIT && !(p->eps_w > 0))
         return fail(err, PCPF_EINVAL, "eps_w must be > 0 for the LOGIT reset");
-    if (p->reserved[0] || p->reserved[1] || p->reserved[2])
+    if (p->normal_mode != PCPF_NORMAL_PSI && p->normal_mode != PCPF_NORMAL_PHI)
+        return fail(err, PCPF_EINVAL, "unknown normal_mode");
+    if (p->reserved[0] || p->reserved[1])
         return fail(err, PCPF_EINVAL, "reserved fields must be 0");
     return PCPF_OK;
 }
@@ -1338,6 +1341,8 @@ pcpf_status pcpf_forward_ckpt(pcpf_ctx* c, double dt, int64_t nsteps, int64_t ev
     if (check_ctx(c) != PCPF_OK) return PCPF_EINVAL;
     if (c->prm.precision == PCPF_BF16)
         return fail(&c->err, PCPF_EUNSUPPORTED, "no adjoint of the PCPF_BF16 form");
+    if (c->prm.normal_mode == PCPF_NORMAL_PHI)
+        return fail(&c->err, PCPF_EUNSUPPORTED, "no adjoint of the PCPF_NORMAL_PHI form");
     if (!c->has_state) return fail(&c->err, PCPF_ESTATE, "no state set");
     size_t need = 0;
     if (pcpf_ckpt_bytes(c, nsteps, every, &need) != PCPF_OK || !std::isfinite(dt))

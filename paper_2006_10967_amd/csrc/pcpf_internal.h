@@ -106,6 +106,7 @@ struct GFArgs {
     int axis;            // every element axis-aligned (diagonal J): diagonal-Jacobian
                          // arithmetic and velocity from per-element 1D sin/cos tables
     int mf;              // line operators on the matrix cores, bf16 operands (float only)
+    int nphi;            // interface normal from phi (the unpreconditioned form)
 };
 
 // update kernel kinds

@@ -1,0 +1,7 @@
+// The 2D kernels in float: one translation unit per dimension and precision, so that the
+// instantiations compile in parallel.
+#include "pcpf_kernels_impl.h"
+
+namespace pcpf {
+template bool get_launchers_dim<float, 2>(int, Launchers<float>*);
+}  // namespace pcpf

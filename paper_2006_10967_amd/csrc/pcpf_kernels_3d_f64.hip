@@ -1,0 +1,7 @@
+// The 3D kernels in double: one translation unit per dimension and precision, so that the
+// instantiations compile in parallel.
+#include "pcpf_kernels_impl.h"
+
+namespace pcpf {
+template bool get_launchers_dim<double, 3>(int, Launchers<double>*);
+}  // namespace pcpf

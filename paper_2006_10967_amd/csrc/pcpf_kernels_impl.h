@@ -1,0 +1,1076 @@
+// HIP kernels of the FR-PCPF residual for gfx950 (tensor-product quads/hexes):
+// templates, instantiated per dimension and precision by pcpf_kernels_{2d,3d}_{f64,f32}.hip.
+//
+// Work decomposition: one thread per solution point, EPB whole elements per block, the
+// element data staged in LDS. Every element operator of the tensor-product element acts
+// along one reference direction at a time (line form): the interpolation to a face point
+// reads the p+1 points of one line, the derivative along xi_k reads the line through the
+// point, and the correction (lifting) functions of a face touch only the line ending at
+// that face point. This is the sum-factorised form of the dense operators of §3.1
+// (Steps 1, 3, 4 and 6), exact in exact arithmetic.
+//
+// LDG orientation (§3.1 Step 2 with beta = +-1/2): the element on the - side of a face
+// owns it. Its common solution is the neighbour's trace (so only + faces carry a jump in
+// the corrected gradient), and it computes the common normal flux (Step 5) from its own
+// viscous flux. Hence only two fields cross element boundaries per stage, and both are
+// pushed by their producer into the consumer's own slots, so that every load of both
+// kernels is indexed by the loading element: the traces of - faces (written by update
+// into the owner's + face slots Tp) and the common flux (written by grad_flux into its own
+// + face slots Fp and, negated, into the neighbour's - face slots Fm). Boundary faces (no
+// neighbour) use the ghost state B(u) = u, B(q) = q of §3.3 and are computed by the
+// element itself.
+#pragma once
+
+#include <hip/hip_ext.h>
+
+#include <cmath>
+#include <type_traits>
+
+#include "pcpf_device.h"
+#include "pcpf_internal.h"
+#include "pcpf_mfma.h"
+
+namespace pcpf {
+namespace {
+
+using namespace dev;
+
+// ------------------------------------------------------------------------------------
+// grad_flux: Steps 1-5 for the elements of one block.
+//   GF_PHYS     u = [phi, psi]: corrected gradients, fluxes at solution points, partial
+//               divergence P = sum_k DH_k f~_k, common fluxes on owned faces.
+//   GF_PRECOND  psi only: sensor nu_e, g = -nu_e grad psi, source S = sgn (1 - |q|),
+//               P = sum_k DH_k g~_k - |J| S, common fluxes on owned faces.
+//   GF_SIGN     psi0 only: smeared sign tanh(psi0 / max(|grad psi0|, delta_g)).
+//   GF_SENSOR   psi only: the element viscosity nu_e.
+// AXIS: every element is axis-aligned (diagonal J): the metric terms reduce to one
+// product per component, face normals are +-e_k, and trigonometric velocity fields come
+// from per-element tables of sin/cos(pi x_k) at the n node positions and both ends.
+// Phases: A loads (state, operators, geometry, neighbour traces, face normals, velocity
+// tables) | B corrected gradient q and fluxes f~ at solution points -> LDS | C common
+// fluxes on owned face points -> global, and P = sum_k DH_k f~_k -> global.
+// ------------------------------------------------------------------------------------
+// Occupancy target (waves per SIMD) of the physical grad_flux kernel; 0 leaves the
+// register budget to the compiler.
+#ifndef PCPF_GF_WAVES
+#define PCPF_GF_WAVES 0
+#endif
+
+// MF: the line operators of the gradient (DT, and lp for the own traces) and of the
+// divergence (DH) run on the matrix cores with bf16 operands and fp32 accumulation (the
+// BF16 form; R = float); the pointwise flux math, the face interpolations and the sensor
+// stay in fp32 on the vector units.
+// NPHI (physical mode): the interface normal of the sharpening flux comes from phi instead
+// of psi, the unpreconditioned conservative phase field of §2.
+template <typename R, int D, int P, int MODE, bool AXIS, bool MF = false, bool NPHI = false>
+__global__ __launch_bounds__((Shape<D, P>::NT))
+#if PCPF_GF_WAVES > 0
+__attribute__((amdgpu_waves_per_eu(PCPF_GF_WAVES)))
+#endif
+void k_grad_flux(GFArgs<R> a) {
+    static_assert(!MF || std::is_same<R, float>::value, "the matrix-core form is fp32");
+    using S = Shape<D, P>;
+    constexpr int N = S::N, NU = S::NU, NFA = S::NFA, EPB = S::EPB, NT = S::NT, G = S::GEO;
+    constexpr int V = (MODE == GF_PHYS) ? 2 : 1;
+    constexpr int NV = NPHI ? 0 : V - 1;                // variable the interface normal is of
+    constexpr int NOPS = ops_size(N);
+    constexpr bool FLUX = (MODE == GF_PHYS || MODE == GF_PRECOND);
+    constexpr bool SENS = (MODE == GF_PRECOND || MODE == GF_SENSOR);
+    constexpr bool GRAD = (MODE != GF_SENSOR);
+    constexpr bool TAB = (MODE == GF_PHYS) && AXIS;      // velocity tables possible
+    constexpr int NPF = D * NFA;                         // points on the + faces of one element
+    constexpr int NTB = N + 2;                           // table positions per axis
+    constexpr int XST = EPB * NU;                        // stride of one field in s_x / s_f
+    constexpr int NX = (V * D > 2 ? V * D : 2) * XST;
+    using M = Math<R>;
+
+    __shared__ R s_ops[NOPS];
+    __shared__ R s_geo[EPB * G];
+    __shared__ R s_u[V][EPB * NU];
+    __shared__ R s_x[NX];                                // q (or sensor scratch)
+    __shared__ R s_f[FLUX ? V * D * XST : 1];            // f~ at solution points
+    __shared__ R s_nb[GRAD ? V : 1][GRAD ? EPB * NPF : 1];  // + face neighbour traces
+    __shared__ R s_vt[TAB ? EPB * D * NTB * 2 : 1];
+    __shared__ R s_nu[EPB];
+    __shared__ R s_fn[FLUX && !AXIS ? EPB * D * (D + 1) : 1];  // + face unit normal, scale
+    __shared__ int s_nbr[EPB * 2 * D];
+    __shared__ R s_tr[MF ? V * D * EPB * NFA : 1];       // own + face traces (MF)
+
+    const int tid = threadIdx.x;
+    const int64_t e0 = (int64_t)blockIdx.x * EPB;
+    const int nel = (int)((a.E - e0) < EPB ? (a.E - e0) : EPB);
+    const bool pt = tid < nel * NU;
+    const int le = tid / NU;
+    const int ip = tid - le * NU;
+    int mi[D];
+    {
+        int r = ip;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            mi[k] = r % N;
+            r /= N;
+        }
+    }
+    const bool trig = a.ph.vel_kind == PCPF_VEL_SINGLE_VORTEX || a.ph.vel_kind == PCPF_VEL_LEVEQUE3D;
+
+    // ---- A: loads. Every global load of the phase is issued into registers before the
+    // first wait, then the values go to LDS. All loads are indexed by this block's own
+    // elements: the neighbours pushed their traces into this element's + face slots.
+    constexpr int I_OPS = (NOPS + NT - 1) / NT;
+    constexpr int I_GEO = (EPB * G + NT - 1) / NT;
+    constexpr int I_NBR = (EPB * 2 * D + NT - 1) / NT;
+    constexpr int I_U = (EPB * NU + NT - 1) / NT;
+    constexpr int I_NB = (EPB * NPF + NT - 1) / NT;
+    constexpr int I_TB = TAB ? (EPB * D * NTB + NT - 1) / NT : 1;
+    R r_ops[I_OPS], r_geo[I_GEO], r_u[V][I_U];
+    int32_t r_nbr[I_NBR];
+#pragma unroll
+    for (int j = 0; j < I_OPS; ++j) {
+        const int i = tid + j * NT;
+        r_ops[j] = (i < NOPS) ? gld(a.ops, i) : R(0);
+    }
+#pragma unroll
+    for (int j = 0; j < I_GEO; ++j) {
+        const int i = tid + j * NT;
+        r_geo[j] = (i < nel * G) ? gld(a.geo + e0 * G, i) : R(0);
+    }
+#pragma unroll
+    for (int j = 0; j < I_NBR; ++j) {
+        const int i = tid + j * NT;
+        r_nbr[j] = (i < nel * 2 * D) ? gld(a.nbr + e0 * 2 * D, i) : -1;
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+        for (int j = 0; j < I_U; ++j) {
+            const int i = tid + j * NT;
+            r_u[v][j] = (i < nel * NU) ? gld(a.u[v] + e0 * NU, i) : R(0);
+        }
+    // + face normal inputs (row k of J^-1 and |J|) of this thread's (element, face)
+    R r_ji[FLUX ? D : 1], r_det = R(1);
+    const bool fn_thread = FLUX && !AXIS && tid < nel * D;
+    if constexpr (FLUX) {
+        if (fn_thread) {
+            const int el = tid / D, k = tid - el * D;
+            const R* gb = a.geo + e0 * G;
+#pragma unroll
+            for (int i = 0; i < D; ++i) r_ji[i] = gld(gb, el * G + D + D * D + k * D + i);
+            r_det = gld(gb, el * G + D + 2 * D * D);
+        }
+    }
+    // velocity-table inputs: x0_k, J_kk and the reference position of each table entry
+    R r_tx[I_TB];
+    if constexpr (TAB) {
+#pragma unroll
+        for (int j = 0; j < I_TB; ++j) {
+            const int it = tid + j * NT;
+            r_tx[j] = R(0);
+            if (trig && it < nel * D * NTB) {
+                const int el = it / (D * NTB), r = it - el * (D * NTB), k = r / NTB, jj = r - k * NTB;
+                const R* gb = a.geo + e0 * G;
+                const R xi = jj < N ? gld(a.ops + op_xi(N), jj) : (jj == N ? R(-1) : R(1));
+                r_tx[j] = gld(gb, el * G + k) + gld(gb, el * G + D + k * D + k) * (xi + R(1));
+            }
+        }
+    }
+    // neighbour traces on the + faces, pushed here by the neighbours (boundary + face
+    // slots are zeroed when the context is created and never written)
+    R r_nb[GRAD ? I_NB : 1][V];
+    if constexpr (GRAD) {
+#pragma unroll
+        for (int j = 0; j < I_NB; ++j) {
+            const int it = tid + j * NT;
+#pragma unroll
+            for (int v = 0; v < V; ++v) r_nb[j][v] = (it < nel * NPF) ? gld(a.Tp[v] + e0 * NPF, it) : R(0);
+        }
+    }
+    // registers -> LDS
+#pragma unroll
+    for (int j = 0; j < I_OPS; ++j)
+        if (tid + j * NT < NOPS) s_ops[tid + j * NT] = r_ops[j];
+#pragma unroll
+    for (int j = 0; j < I_GEO; ++j)
+        if (tid + j * NT < nel * G) s_geo[tid + j * NT] = r_geo[j];
+#pragma unroll
+    for (int j = 0; j < I_NBR; ++j)
+        if (tid + j * NT < nel * 2 * D) s_nbr[tid + j * NT] = r_nbr[j];
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+        for (int j = 0; j < I_U; ++j)
+            if (tid + j * NT < nel * NU) s_u[v][tid + j * NT] = r_u[v][j];
+    if constexpr (GRAD) {
+#pragma unroll
+        for (int j = 0; j < I_NB; ++j)
+            if (tid + j * NT < nel * NPF)
+#pragma unroll
+                for (int v = 0; v < V; ++v) s_nb[v][tid + j * NT] = r_nb[j][v];
+    }
+    // outward unit normal n = J^-T e_k / |J^-T e_k| and scale |J| |J^-T e_k| of face +k
+    if constexpr (FLUX && !AXIS) {
+        if (fn_thread) {
+            R mag2 = R(0);
+#pragma unroll
+            for (int i = 0; i < D; ++i) mag2 += r_ji[i] * r_ji[i];
+            const R mag = M::sqrt_(mag2);
+            R* fn = &s_fn[tid * (D + 1)];
+#pragma unroll
+            for (int i = 0; i < D; ++i) fn[i] = r_ji[i] / mag;
+            fn[D] = r_det * mag;
+        }
+    }
+    if constexpr (TAB) {
+        // one sincospi per line position of each axis
+        if (trig) {
+#pragma unroll
+            for (int j = 0; j < I_TB; ++j) {
+                const int it = tid + j * NT;
+                if (it < nel * D * NTB) {
+                    R sn, cs;
+                    M::sincospi_(r_tx[j], &sn, &cs);
+                    s_vt[2 * it] = sn;
+                    s_vt[2 * it + 1] = cs;
+                }
+            }
+        }
+    }
+    // does any - face of the block lie on a boundary (face 2k of an element, no neighbour)?
+    int my_bnd = 0;
+#pragma unroll
+    for (int j = 0; j < I_NBR; ++j) {
+        const int i = tid + j * NT;
+        if (i < nel * 2 * D && (i & 1) == 0 && r_nbr[j] < 0) my_bnd = 1;
+    }
+    const int has_bnd = __syncthreads_or(my_bnd);
+
+    // ---- sensor (§3.2): modal coefficients by one 1D transform per direction -----------
+    if constexpr (SENS) {
+        const R* VI = &s_ops[op_vinv(N)];
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const R* src = (k == 0) ? s_u[0] : s_x + ((k - 1) & 1) * XST;
+            R* dst = s_x + (k & 1) * XST;
+            if (pt) {
+                R acc = R(0);
+                const int b0 = le * NU + ip - mi[k] * st<N>(k);
+#pragma unroll
+                for (int q = 0; q < N; ++q) acc += VI[mi[k] * N + q] * src[b0 + q * st<N>(k)];
+                dst[tid] = acc;
+            }
+            __syncthreads();
+        }
+        const R* chi = s_x + ((D - 1) & 1) * XST;
+        // modal energies of each element. Small elements: one thread per element sums its
+        // points in order; large elements (N_u >= 64): a wave per element, lanes over its
+        // points, then a fixed butterfly (lane 0's sum is used: deterministic).
+        auto energies = [&](int el, int i0, int di, R& ea, R& et) {
+            for (int i = i0; i < NU; i += di) {
+                const R c = chi[el * NU + i];
+                ea += c * c;
+                int r = i, top = 0;
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    top |= ((r % N) == P);
+                    r /= N;
+                }
+                if (top) et += c * c;
+            }
+        };
+        auto set_nu = [&](int el, R ea, R et) {
+            const R nu = visc_ramp(ea, et, a.ph.s0, a.ph.kappa, a.ph.nu_max);
+            s_nu[el] = nu;
+            if constexpr (MODE == GF_SENSOR) gst(a.out + e0, el, nu);
+        };
+        if constexpr (NU < 64) {
+            if (tid < nel) {
+                R ea = R(0), et = R(0);
+                energies(tid, 0, 1, ea, et);
+                set_nu(tid, ea, et);
+            }
+        } else {
+            const int swave = __builtin_amdgcn_readfirstlane(tid >> 6);
+            const int slane = tid & 63;
+            for (int el = swave; el < nel; el += S::NW) {
+                R ea = R(0), et = R(0);
+                energies(el, slane, 64, ea, et);
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) {
+                    ea += __shfl_xor(ea, off, 64);
+                    et += __shfl_xor(et, off, 64);
+                }
+                if (slane == 0) set_nu(el, ea, et);
+            }
+        }
+        __syncthreads();
+        if constexpr (MODE == GF_SENSOR) return;
+    }
+
+    if constexpr (GRAD) {
+        // ---- B: corrected gradient (Steps 1-3) and fluxes at solution points (Step 4) ---
+        // The matrix-core form first applies [DT; lp] along the lines of every direction
+        // (16 lines per instruction): s_x <- DT u, s_tr <- the own + face trace lp u.
+        const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+        const int lane = tid & 63;
+        // every lane of a wave takes part: unit j of the wave is direction k = u / WK,
+        // lines (u % WK) * 64 + 16 g + lane % 16, g = 0..3 (wave-uniform k)
+        auto mf_lines = [&](auto body) {
+#pragma unroll
+            for (int j = 0; j < S::UPW; ++j) {
+                const int u = wave + j * S::NW;
+                if (u >= S::NUNITS) break;
+                const int k = u / S::WK;
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const int item = (u - k * S::WK) * 64 + 16 * g + (lane & 15);
+                    const bool ok = item < nel * NFA;
+                    const int el = ok ? item / NFA : 0, t = ok ? item - el * NFA : 0;
+                    if (k == 0) {
+                        body(std::integral_constant<int, 0>{}, ok, el, t, item);
+                    } else if (k == 1) {
+                        body(std::integral_constant<int, 1>{}, ok, el, t, item);
+                    } else if constexpr (D == 3) {
+                        body(std::integral_constant<int, 2>{}, ok, el, t, item);
+                    }
+                }
+            }
+        };
+        if constexpr (MF) {
+            const bf16x4 aG = mfma_rows<N + 1, N>(
+                [&](int i, int k) { return i < N ? s_ops[op_dt(N) + i * N + k] : s_ops[op_lp(N) + k]; },
+                lane);
+            mf_lines([&](auto KC, bool ok, int el, int t, int item) {
+                constexpr int K = decltype(KC)::value;
+                constexpr int SK = st<N>(K);
+                const int base = el * NU + face_base<D, N>(K, t);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const f32x4 r = mfma_lines<N>(aG, s_u[v], ok, base, SK, lane);
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) {
+                        const int row = 4 * (lane >> 4) + jj;
+                        if (ok && row < N) s_x[(v * D + K) * XST + base + row * SK] = r[jj];
+                        if (ok && row == N) s_tr[(v * D + K) * EPB * NFA + item] = r[jj];
+                    }
+                }
+            });
+            __syncthreads();
+        }
+        R Sdet = R(0);
+        if (pt) {
+            const R* gg = &s_geo[le * G];
+            const R det = gg[D + 2 * D * D];
+            const R* Ji = gg + D + D * D;            // Jinv[k][i] = Ji[k*D + i]
+            const R* cp = &s_ops[op_cp(N)];
+            R q[V][D];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                R qt[D];
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    // + face with a neighbour: the LDG jump (nb - own trace) is lifted; the
+                    // own-trace part is folded into DT = D1 - cp (x) lp
+                    const bool hk = s_nbr[le * 2 * D + 2 * k + 1] >= 0;
+                    const int tk = tang_index<D, N>(k, mi);
+                    if constexpr (MF) {
+                        // DT u from the matrix cores; on a boundary + face the "neighbour"
+                        // trace is the own trace (no jump)
+                        const R nbk = hk ? s_nb[v][le * NPF + k * NFA + tk]
+                                         : s_tr[(v * D + k) * EPB * NFA + le * NFA + tk];
+                        qt[k] = s_x[(v * D + k) * XST + tid] + cp[mi[k]] * nbk;
+                    } else {
+                        const R* Dk = &s_ops[hk ? op_dt(N) : OP_D1] + mi[k] * N;
+                        const int b0 = le * NU + ip - mi[k] * st<N>(k);
+                        R acc = R(0);
+#pragma unroll
+                        for (int b = 0; b < N; ++b) acc += Dk[b] * s_u[v][b0 + b * st<N>(k)];
+                        // boundary + faces: s_nb holds 0 (those slots are never written)
+                        acc += cp[mi[k]] * s_nb[v][le * NPF + k * NFA + tk];
+                        qt[k] = acc;
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    R acc;
+                    if constexpr (AXIS) {
+                        acc = Ji[i * D + i] * qt[i];
+                    } else {
+                        acc = R(0);
+#pragma unroll
+                        for (int k = 0; k < D; ++k) acc += Ji[k * D + i] * qt[k];
+                    }
+                    q[v][i] = acc;
+                    s_x[(v * D + i) * XST + tid] = acc;
+                }
+            }
+            if constexpr (MODE == GF_SIGN) {
+                R g2 = R(0);
+#pragma unroll
+                for (int i = 0; i < D; ++i) g2 += q[0][i] * q[0][i];
+                R g = M::sqrt_(g2);
+                if (!(g > a.ph.delta_g)) g = a.ph.delta_g;
+                gst(a.out + e0 * NU, tid, M::tanh_(s_u[0][tid] / g));
+            }
+            if constexpr (MODE == GF_PHYS) {
+                const R* xi = &s_ops[op_xi(N)];
+                R vel[D];
+                if constexpr (TAB) {
+                    if (trig) {
+                        velocity_tab<R, D, NTB>(a.ph, &s_vt[le * D * NTB * 2], mi, vel);
+                    } else {
+                        R x[D];
+#pragma unroll
+                        for (int i = 0; i < D; ++i) x[i] = gg[i] + gg[D + i * D + i] * (xi[mi[i]] + R(1));
+                        velocity_lin<R, D>(a.ph, x, vel);
+                    }
+                } else {
+                    R x[D];
+#pragma unroll
+                    for (int i = 0; i < D; ++i) {
+                        R acc = gg[i];
+#pragma unroll
+                        for (int j = 0; j < D; ++j) acc += gg[D + i * D + j] * (xi[mi[j]] + R(1));
+                        x[i] = acc;
+                    }
+                    velocity<R, D>(a.ph, x, vel);
+                }
+                R v2 = R(0), g2 = R(0);
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    v2 += vel[i] * vel[i];
+                    g2 += q[NV][i] * q[NV][i];
+                }
+                R mm = M::sqrt_(v2);
+                if (!(mm > a.ph.gamma)) mm = a.ph.gamma;
+                const R rn = M::rsqrt_(g2 + a.ph.delta_n * a.ph.delta_n);
+                const R phi = s_u[0][tid], psi = s_u[1][tid];
+                const R sharp = a.ph.gamma * phi * (R(1) - phi) * rn;
+                R f0[D], f1[D];
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    const R fvis = mm * (a.ph.eps * q[0][i] - sharp * q[NV][i]);
+                    f0[i] = phi * vel[i] - fvis;
+                    f1[i] = psi * vel[i];
+                }
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    R a0, a1;
+                    if constexpr (AXIS) {
+                        a0 = Ji[k * D + k] * f0[k];
+                        a1 = Ji[k * D + k] * f1[k];
+                    } else {
+                        a0 = R(0);
+                        a1 = R(0);
+#pragma unroll
+                        for (int i = 0; i < D; ++i) {
+                            a0 += Ji[k * D + i] * f0[i];
+                            a1 += Ji[k * D + i] * f1[i];
+                        }
+                    }
+                    s_f[(0 * D + k) * XST + tid] = det * a0;
+                    s_f[((V - 1) * D + k) * XST + tid] = det * a1;
+                }
+            }
+            if constexpr (MODE == GF_PRECOND) {
+                const R nu = s_nu[le];
+                R g2 = R(0);
+#pragma unroll
+                for (int i = 0; i < D; ++i) g2 += q[0][i] * q[0][i];
+                Sdet = det * gld(a.sgn + e0 * NU, tid) * (R(1) - M::sqrt_(g2));
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    R acc;
+                    if constexpr (AXIS) {
+                        acc = Ji[k * D + k] * q[0][k];
+                    } else {
+                        acc = R(0);
+#pragma unroll
+                        for (int i = 0; i < D; ++i) acc += Ji[k * D + i] * q[0][i];
+                    }
+                    s_f[k * XST + tid] = -det * nu * acc;
+                }
+            }
+        }
+        if constexpr (MODE == GF_SIGN) return;
+        __syncthreads();
+
+        // ---- C: common normal fluxes on owned face points (Step 5) ----------------------
+        // One face point per lane; each wave takes the points of one reference direction
+        // K (compile-time in the body below). + faces are owned; - faces are computed here
+        // only on boundaries (ghost state = interior state).
+        auto face = [&](auto KC, auto SC, int el, int t, int32_t en) {
+            constexpr int K = decltype(KC)::value;
+            constexpr int SD = decltype(SC)::value;      // 1: + face, 0: - face
+            constexpr int SK = st<N>(K);
+            const int base = el * NU + face_base<D, N>(K, t);
+            const R* l = &s_ops[SD ? op_lp(N) : op_lm(N)];
+            const R* gg = &s_geo[el * G];
+            R nrm[D], sc;
+            if constexpr (AXIS) {
+                // diagonal J: the unit normal of face +K is sign(Jinv_KK) e_K
+                const R jk = gg[D + D * D + K * D + K];
+                sc = gg[D + 2 * D * D] * M::fabs_(jk);
+#pragma unroll
+                for (int i = 0; i < D; ++i) nrm[i] = R(0);
+                nrm[K] = ((jk > R(0)) == (SD == 1)) ? R(1) : R(-1);
+            } else {
+                const R* fn = &s_fn[(el * D + K) * (D + 1)];
+                sc = fn[D];
+#pragma unroll
+                for (int i = 0; i < D; ++i) nrm[i] = SD ? fn[i] : -fn[i];
+            }
+            R uL[V], uR[V], qn[V], g2 = R(0);
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                R acc = R(0);
+#pragma unroll
+                for (int q = 0; q < N; ++q) acc += l[q] * s_u[v][base + q * SK];
+                uL[v] = acc;
+                uR[v] = (en >= 0) ? s_nb[v][el * NPF + K * NFA + t] : acc;
+                // the normal component; in the physical mode all components of the variable
+                // the interface normal is of (they enter its |grad|)
+                R acc_n = R(0);
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    const bool need = !AXIS || (MODE == GF_PHYS && v == NV) || i == K;
+                    if (!need) continue;
+                    R qa = R(0);
+#pragma unroll
+                    for (int q = 0; q < N; ++q) qa += l[q] * s_x[(v * D + i) * XST + base + q * SK];
+                    if constexpr (AXIS) {
+                        if (i == K) acc_n = qa * nrm[K];
+                    } else {
+                        acc_n += qa * nrm[i];
+                    }
+                    if (MODE == GF_PHYS && v == NV) g2 += qa * qa;
+                }
+                qn[v] = acc_n;
+            }
+            const uint32_t fo = (el * D + K) * NFA + t;   // from the block's first element
+            if constexpr (MODE == GF_PHYS) {
+                const R* xi = &s_ops[op_xi(N)];
+                R vel[D];
+                int pos[D];
+                {
+                    int tt = t;
+#pragma unroll
+                    for (int m = 0; m < D; ++m) {
+                        if (m == K) {
+                            pos[m] = N + SD;
+                        } else {
+                            pos[m] = tt % N;
+                            tt /= N;
+                        }
+                    }
+                }
+                if constexpr (TAB) {
+                    if (trig) {
+                        velocity_tab<R, D, NTB>(a.ph, &s_vt[el * D * NTB * 2], pos, vel);
+                    } else {
+                        R x[D];
+#pragma unroll
+                        for (int m = 0; m < D; ++m) {
+                            const R xr = (m == K) ? (SD ? R(2) : R(0)) : xi[pos[m]] + R(1);
+                            x[m] = gg[m] + gg[D + m * D + m] * xr;
+                        }
+                        velocity_lin<R, D>(a.ph, x, vel);
+                    }
+                } else {
+                    R x[D];
+#pragma unroll
+                    for (int i = 0; i < D; ++i) {
+                        R acc = gg[i];
+#pragma unroll
+                        for (int m = 0; m < D; ++m) {
+                            const R xr = (m == K) ? (SD ? R(2) : R(0)) : xi[pos[m]] + R(1);
+                            acc += gg[D + i * D + m] * xr;
+                        }
+                        x[i] = acc;
+                    }
+                    velocity<R, D>(a.ph, x, vel);
+                }
+                R v2 = R(0), vn = R(0);
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    v2 += vel[i] * vel[i];
+                    if constexpr (AXIS) {
+                        if (i == K) vn = vel[K] * nrm[K];
+                    } else {
+                        vn += vel[i] * nrm[i];
+                    }
+                }
+                R mm = M::sqrt_(v2);
+                if (!(mm > a.ph.gamma)) mm = a.ph.gamma;
+                const R rn = M::rsqrt_(g2 + a.ph.delta_n * a.ph.delta_n);
+                const R pL = uL[0], pR = uR[0], sL = uL[1], sR = uR[1];
+                const R fvn = mm * (a.ph.eps * qn[0] - a.ph.gamma * pL * (R(1) - pL) * qn[NV] * rn);
+                const R F0 = R(0.5) * (pL + pR) * vn - fvn + a.ph.tau * (pL - pR);
+                const R F1 = R(0.5) * (sL + sR) * vn + a.ph.tau * (sL - sR);
+                const R G0 = sc * F0, G1 = sc * F1;
+                if constexpr (SD == 1) {
+                    gst(a.Fp[0] + e0 * NPF, fo, G0);
+                    gst(a.Fp[1] + e0 * NPF, fo, G1);
+                    if (en >= 0) {
+                        // the neighbour's - face: same flux, its outward normal is -n
+                        const uint32_t fn_ = ((uint32_t)en * D + K) * NFA + t;
+                        gst(a.Fm[0], fn_, -G0);
+                        gst(a.Fm[1], fn_, -G1);
+                    }
+                } else {
+                    gst(a.Fm[0] + e0 * NPF, fo, G0);
+                    gst(a.Fm[1] + e0 * NPF, fo, G1);
+                }
+            } else {
+                const R F = -s_nu[el] * qn[0] + a.ph.tau * (uL[0] - uR[0]);
+                const R G0 = sc * F;
+                if constexpr (SD == 1) {
+                    gst(a.Fp[0] + e0 * NPF, fo, G0);
+                    if (en >= 0) gst(a.Fm[0], ((uint32_t)en * D + K) * NFA + t, -G0);
+                } else {
+                    gst(a.Fm[0] + e0 * NPF, fo, G0);
+                }
+            }
+        };
+        // wave-uniform direction: each unit is one wave's worth of one direction's points
+        auto face_pass = [&](auto SC) {
+            constexpr int SD = decltype(SC)::value;
+#pragma unroll
+            for (int j = 0; j < S::UPW; ++j) {
+                const int u = wave + j * S::NW;
+                if (u >= S::NUNITS) break;
+                const int k = u / S::WK;
+                const int item = (u - k * S::WK) * 64 + lane;
+                if (item >= nel * NFA) continue;
+                const int el = item / NFA, t = item - el * NFA;
+                const int32_t en = s_nbr[el * 2 * D + 2 * k + SD];
+                if (SD == 0 && en >= 0) continue;
+                if (k == 0) {
+                    face(std::integral_constant<int, 0>{}, SC, el, t, en);
+                } else if (k == 1) {
+                    face(std::integral_constant<int, 1>{}, SC, el, t, en);
+                } else if constexpr (D == 3) {
+                    face(std::integral_constant<int, 2>{}, SC, el, t, en);
+                }
+            }
+        };
+        face_pass(std::integral_constant<int, 1>{});
+        if (has_bnd) face_pass(std::integral_constant<int, 0>{});
+
+        // ---- E: volume part of Step 6, P = sum_k DH_k f~_k (- |J| S) ---------------------
+        if constexpr (MF) {
+            // DH along the lines of every direction on the matrix cores, in place (the
+            // direction-K field of s_f is touched only by the direction-K lines), then the
+            // directions summed per point
+            const bf16x4 aH = mfma_rows<N, N>(
+                [&](int i, int k) { return s_ops[op_dh(N) + i * N + k]; }, lane);
+            mf_lines([&](auto KC, bool ok, int el, int t, int item) {
+                (void)item;
+                constexpr int K = decltype(KC)::value;
+                constexpr int SK = st<N>(K);
+                const int base = el * NU + face_base<D, N>(K, t);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    R* fk = &s_f[(v * D + K) * XST];
+                    const f32x4 r = mfma_lines<N>(aH, fk, ok, base, SK, lane);
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) {
+                        const int row = 4 * (lane >> 4) + jj;
+                        if (ok && row < N) fk[base + row * SK] = r[jj];
+                    }
+                }
+            });
+            __syncthreads();
+            if (pt) {
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    R acc = R(0);
+#pragma unroll
+                    for (int k = 0; k < D; ++k) acc += s_f[(v * D + k) * XST + tid];
+                    if constexpr (MODE == GF_PRECOND) acc -= Sdet;
+                    gst(a.P[v] + e0 * NU, tid, acc);
+                }
+            }
+        } else if (pt) {
+            const R* DH = &s_ops[op_dh(N)];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                R acc = R(0);
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    const int b0 = le * NU + ip - mi[k] * st<N>(k);
+#pragma unroll
+                    for (int b = 0; b < N; ++b) acc += DH[mi[k] * N + b] * s_f[(v * D + k) * XST + b0 + b * st<N>(k)];
+                }
+                if constexpr (MODE == GF_PRECOND) acc -= Sdet;
+                gst(a.P[v] + e0 * NU, tid, acc);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// - face traces of the block's elements pushed into the owners' + face slots. Face unit
+// j of a wave covers direction k = u / WK, points (u % WK) * 64 + lane of that direction
+// (u = wave + j NW), so the direction is uniform in the wave.
+// ------------------------------------------------------------------------------------
+template <int D, int P, int U>
+__device__ __forceinline__ void load_owners(int32_t (&r_own)[U], const int32_t* nbr, int64_t e0,
+                                            int nel, int wave, int lane) {
+    using S = Shape<D, P>;
+#pragma unroll
+    for (int j = 0; j < S::UPW; ++j) {
+        const int u = wave + j * S::NW;
+        r_own[j] = -1;
+        if (u < S::NUNITS) {
+            const int k = u / S::WK;
+            const int item = (u - k * S::WK) * 64 + lane;
+            if (item < nel * S::NFA) r_own[j] = gld(nbr + e0 * 2 * D, (item / S::NFA) * 2 * D + 2 * k);
+        }
+    }
+}
+
+template <typename R, int D, int P, int V, int U>
+__device__ __forceinline__ void push_traces(R* const* Tp, const R* lm, const R* su0,
+                                            const R* su1, const int32_t (&r_own)[U], int nel,
+                                            int wave, int lane) {
+    using S = Shape<D, P>;
+    constexpr int N = S::N, NU = S::NU, NFA = S::NFA;
+    auto push = [&](auto KC, int el, int t, int32_t own) {
+        constexpr int K = decltype(KC)::value;
+        constexpr int SK = st<N>(K);
+        const int base = el * NU + face_base<D, N>(K, t);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const R* su = v ? su1 : su0;
+            R acc = R(0);
+#pragma unroll
+            for (int q = 0; q < N; ++q) acc += lm[q] * su[base + q * SK];
+            gst(Tp[v], ((uint32_t)own * D + K) * NFA + t, acc);
+        }
+    };
+#pragma unroll
+    for (int j = 0; j < S::UPW; ++j) {
+        const int u = wave + j * S::NW;
+        if (u >= S::NUNITS) break;
+        const int k = u / S::WK;
+        const int item = (u - k * S::WK) * 64 + lane;
+        if (item >= nel * NFA || r_own[j] < 0) continue;
+        const int el = item / NFA, t = item - el * NFA;
+        if (k == 0) {
+            push(std::integral_constant<int, 0>{}, el, t, r_own[j]);
+        } else if (k == 1) {
+            push(std::integral_constant<int, 1>{}, el, t, r_own[j]);
+        } else if constexpr (D == 3) {
+            push(std::integral_constant<int, 2>{}, el, t, r_own[j]);
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// update: Step 6 face part and the RK4 stage combine.
+//   R = -(P + sum_faces c_face F~) / |J|; then either the residual is written (UP_RESID)
+//   or the classic RK4 registers are advanced and the - face traces of the next stage
+//   input are written (UP_RK).
+// ------------------------------------------------------------------------------------
+template <typename R, int D, int P, int V, int KIND>
+__global__ __launch_bounds__((Shape<D, P>::NT)) void k_update(UPArgs<R> a) {
+    using S = Shape<D, P>;
+    constexpr int N = S::N, NU = S::NU, NFA = S::NFA, EPB = S::EPB, NT = S::NT, G = S::GEO;
+    constexpr int NFE = 2 * D * NFA;
+    __shared__ R s_c[3 * N];                 // cm, cp, lm
+    __shared__ R s_F[V][EPB * NFE];
+    __shared__ R s_u[V][KIND == UP_RK ? EPB * NU : 1];
+
+    const int tid = threadIdx.x;
+    const int64_t e0 = (int64_t)blockIdx.x * EPB;
+    const int nel = (int)((a.E - e0) < EPB ? (a.E - e0) : EPB);
+    const bool pt = tid < nel * NU;
+    const int le = tid / NU;
+    const int ip = tid - le * NU;
+    // every global load is issued before the first wait; all are indexed by this block's
+    // own elements (the owners pushed the - face fluxes here). The adjacency is only needed
+    // for the addresses of the trace pushes at the end.
+    constexpr int I_F = (EPB * NFE + NT - 1) / NT;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    int32_t r_own[S::UPW];
+    if constexpr (KIND == UP_RK) load_owners<D, P, S::UPW>(r_own, a.nbr, e0, nel, wave, lane);
+    R rP[V], rU[V], rA[V];
+    R det = R(1);
+    const uint32_t so = e0 * NU;     // first state value of the block (per plane)
+    if (pt) {
+        det = gld(a.geo + e0 * G, le * G + D + 2 * D * D);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            rP[v] = gld(a.P[v] + so, tid);
+            if constexpr (KIND == UP_RK) {
+                rU[v] = gld(a.un[v] + so, tid);
+                rA[v] = a.first ? R(0) : gld(a.acc[v] + so, tid);
+            }
+        }
+    }
+    R r_c[3] = {R(0), R(0), R(0)};
+    if (tid < N) {
+        r_c[0] = gld(a.ops + op_cm(N), tid);
+        r_c[1] = gld(a.ops + op_cp(N), tid);
+        r_c[2] = gld(a.ops + op_lm(N), tid);
+    }
+    R r_F[I_F][V];
+#pragma unroll
+    for (int j = 0; j < I_F; ++j) {
+        const int it = tid + j * NT;
+        const int el = it / NFE;
+        const int r = it - el * NFE;
+        const int f = r / NFA;
+        const int t = r - f * NFA;
+        const int k = f >> 1, s = f & 1;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            R F = R(0);
+            if (it < nel * NFE) F = gld((s ? a.Fp[v] : a.Fm[v]) + e0 * D * NFA, (el * D + k) * NFA + t);
+            r_F[j][v] = F;
+        }
+    }
+    if (tid < N) {
+        s_c[tid] = r_c[0];
+        s_c[N + tid] = r_c[1];
+        s_c[2 * N + tid] = r_c[2];
+    }
+#pragma unroll
+    for (int j = 0; j < I_F; ++j)
+        if (tid + j * NT < nel * NFE)
+#pragma unroll
+            for (int v = 0; v < V; ++v) s_F[v][tid + j * NT] = r_F[j][v];
+    __syncthreads();
+
+    if (pt) {
+        int mi[D];
+        {
+            int r = ip;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                mi[k] = r % N;
+                r /= N;
+            }
+        }
+        const R rdet = R(1) / det;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            R acc = rP[v];
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const int tk = tang_index<D, N>(k, mi);
+                acc += s_c[N + mi[k]] * s_F[v][le * NFE + (2 * k + 1) * NFA + tk]
+                     + s_c[mi[k]] * s_F[v][le * NFE + (2 * k) * NFA + tk];
+            }
+            const R res = -acc * rdet;
+            if constexpr (KIND == UP_RESID) {
+                gst(a.res[v] + so, tid, res);
+            } else {
+                R nx;
+                if (!a.last) {
+                    gst(a.acc[v] + so, tid, rA[v] + a.bcoef * res);
+                    nx = rU[v] + a.ccoef * res;
+                    gst(a.us[v] + so, tid, nx);
+                } else {
+                    nx = rU[v] + a.ccoef * (rA[v] + a.bcoef * res);
+                    gst(a.un[v] + so, tid, nx);
+                }
+                s_u[v][tid] = nx;
+                const R lim = (v == 0 && V == 2) ? R(10) : R(1e30);
+                if (!(Math<R>::fabs_(nx) <= lim)) *a.flag = 1;
+            }
+        }
+    }
+    if constexpr (KIND == UP_RK) {
+        __syncthreads();
+        // - face traces of the next stage input, pushed into the owners' + face slots
+        push_traces<R, D, P, V, S::UPW>(a.Tp, &s_c[2 * N], s_u[0], s_u[V - 1], r_own, nel, wave, lane);
+    }
+}
+
+// - face traces of a given state pushed into the owners' + face slots (after set_state /
+// reset)
+template <typename R, int D, int P, int V>
+__global__ __launch_bounds__((Shape<D, P>::NT)) void k_trace(TRArgs<R> a) {
+    using S = Shape<D, P>;
+    constexpr int N = S::N, NU = S::NU, EPB = S::EPB, NT = S::NT;
+    constexpr int I_U = (EPB * NU + NT - 1) / NT;
+    __shared__ R s_lm[N];
+    __shared__ R s_u[V][EPB * NU];
+    const int tid = threadIdx.x;
+    const int64_t e0 = (int64_t)blockIdx.x * EPB;
+    const int nel = (int)((a.E - e0) < EPB ? (a.E - e0) : EPB);
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    int32_t r_own[S::UPW];
+    load_owners<D, P, S::UPW>(r_own, a.nbr, e0, nel, wave, lane);
+    R r_u[V][I_U];
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+        for (int j = 0; j < I_U; ++j) {
+            const int i = tid + j * NT;
+            r_u[v][j] = (i < nel * NU) ? gld(a.u[v] + e0 * NU, i) : R(0);
+        }
+    R r_l = (tid < N) ? gld(a.ops + op_lm(N), tid) : R(0);
+    if (tid < N) s_lm[tid] = r_l;
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+        for (int j = 0; j < I_U; ++j)
+            if (tid + j * NT < nel * NU) s_u[v][tid + j * NT] = r_u[v][j];
+    __syncthreads();
+    push_traces<R, D, P, V, S::UPW>(a.Tp, s_lm, s_u[0], s_u[V - 1], r_own, nel, wave, lane);
+}
+
+// FP64 quadrature reduction, first pass: block partial sums in a fixed order.
+__device__ __forceinline__ double block_sum(double x) {
+    __shared__ double s_w[REDUCE_THREADS / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) s_w[w] = x;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < REDUCE_THREADS / 64; ++i) r += s_w[i];
+    }
+    return r;
+}
+
+template <typename R, int D, int P>
+__global__ __launch_bounds__(REDUCE_THREADS) void k_reduce(RDArgs<R> a) {
+    using S = Shape<D, P>;
+    constexpr int N = S::N, NU = S::NU;
+    const int64_t total = a.E * NU;
+    double acc = 0.0;
+    for (int64_t idx = (int64_t)blockIdx.x * REDUCE_THREADS + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * REDUCE_THREADS) {
+        const int64_t e = idx / NU;
+        int r = (int)(idx - e * NU);
+        double W = 1.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            W *= a.w64[r % N];
+            r /= N;
+        }
+        double f = (double)a.field[idx];
+        if (a.kind == 1) f = ::fabs(f - (double)a.ref[idx]);
+        acc += a.det64[e] * W * f;
+    }
+    const double b = block_sum(acc);
+    if (threadIdx.x == 0) a.partial[blockIdx.x] = b;
+}
+
+// ------------------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------------------
+template <typename R, int D, int P>
+struct Impl {
+    using S = Shape<D, P>;
+    static unsigned grid(int64_t E) { return (unsigned)((E + S::EPB - 1) / S::EPB); }
+
+    template <int MODE, bool AXIS, bool MF, bool NPHI>
+    static void gf_launch(const GFArgs<R>& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+        hipExtLaunchKernelGGL((k_grad_flux<R, D, P, MODE, AXIS, MF, NPHI>), dim3(grid(a.E)),
+                              dim3(S::NT), 0, st, e0, e1, 0, a);
+    }
+    template <int MODE, bool MF>
+    static void gf_mode(const GFArgs<R>& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+        if constexpr (MODE == GF_PHYS) {
+            if (a.axis) {
+                if (a.nphi) gf_launch<MODE, true, MF, true>(a, st, e0, e1);
+                else gf_launch<MODE, true, MF, false>(a, st, e0, e1);
+            } else {
+                if (a.nphi) gf_launch<MODE, false, MF, true>(a, st, e0, e1);
+                else gf_launch<MODE, false, MF, false>(a, st, e0, e1);
+            }
+        } else if constexpr (MODE == GF_PRECOND) {
+            if (a.axis) gf_launch<MODE, true, MF, false>(a, st, e0, e1);
+            else gf_launch<MODE, false, MF, false>(a, st, e0, e1);
+        } else {
+            gf_launch<MODE, false, MF && MODE != GF_SENSOR, false>(a, st, e0, e1);
+        }
+    }
+    template <bool MF>
+    static void gf_dispatch(int mode, const GFArgs<R>& a, hipStream_t st, hipEvent_t e0,
+                            hipEvent_t e1) {
+        switch (mode) {
+            case GF_PHYS: gf_mode<GF_PHYS, MF>(a, st, e0, e1); break;
+            case GF_PRECOND: gf_mode<GF_PRECOND, MF>(a, st, e0, e1); break;
+            case GF_SIGN: gf_mode<GF_SIGN, MF>(a, st, e0, e1); break;
+            default: gf_mode<GF_SENSOR, MF>(a, st, e0, e1); break;
+        }
+    }
+    static void grad_flux(int mode, int nvar, const GFArgs<R>& a, hipStream_t st, hipEvent_t e0,
+                          hipEvent_t e1) {
+        (void)nvar;
+        if constexpr (std::is_same<R, float>::value) {
+            if (a.mf) {
+                gf_dispatch<true>(mode, a, st, e0, e1);
+                return;
+            }
+        }
+        gf_dispatch<false>(mode, a, st, e0, e1);
+    }
+    static void update(int kind, int nvar, const UPArgs<R>& a, hipStream_t st, hipEvent_t e0,
+                       hipEvent_t e1) {
+        const dim3 g(grid(a.E)), b(S::NT);
+        if (nvar == 2) {
+            if (kind == UP_RK) hipExtLaunchKernelGGL((k_update<R, D, P, 2, UP_RK>), g, b, 0, st, e0, e1, 0, a);
+            else hipExtLaunchKernelGGL((k_update<R, D, P, 2, UP_RESID>), g, b, 0, st, e0, e1, 0, a);
+        } else {
+            if (kind == UP_RK) hipExtLaunchKernelGGL((k_update<R, D, P, 1, UP_RK>), g, b, 0, st, e0, e1, 0, a);
+            else hipExtLaunchKernelGGL((k_update<R, D, P, 1, UP_RESID>), g, b, 0, st, e0, e1, 0, a);
+        }
+    }
+    static void trace(int nvar, const TRArgs<R>& a, hipStream_t st) {
+        const dim3 g(grid(a.E)), b(S::NT);
+        if (nvar == 2) hipLaunchKernelGGL((k_trace<R, D, P, 2>), g, b, 0, st, a);
+        else hipLaunchKernelGGL((k_trace<R, D, P, 1>), g, b, 0, st, a);
+    }
+};
+
+template <typename R, int D, int P>
+void reduce_launch(const RDArgs<R>& a, int nblocks, hipStream_t st);
+
+template <typename R, int D, int P>
+bool fill(Launchers<R>* L) {
+    using S = Shape<D, P>;
+    L->epb = S::EPB;
+    L->nt = S::NT;
+    L->ngeo = S::GEO;
+    L->grad_flux = &Impl<R, D, P>::grad_flux;
+    L->update = &Impl<R, D, P>::update;
+    L->trace = &Impl<R, D, P>::trace;
+    L->reduce = &reduce_launch<R, D, P>;
+    return true;
+}
+
+}  // namespace
+
+namespace {
+template <typename R, int D, int P>
+void reduce_launch(const RDArgs<R>& a, int nblocks, hipStream_t st) {
+    hipLaunchKernelGGL((k_reduce<R, D, P>), dim3(nblocks), dim3(REDUCE_THREADS), 0, st, a);
+}
+}  // namespace
+
+// Launch table of one (d, p) for the orders built for dimension D (defined here, explicitly
+// instantiated once per dimension and precision).
+template <typename R, int D>
+bool get_launchers_dim(int p, Launchers<R>* L) {
+    switch (p) {
+        case 1: return fill<R, D, 1>(L);
+        case 2: return fill<R, D, 2>(L);
+        case 3: return fill<R, D, 3>(L);
+        case 4: return fill<R, D, 4>(L);
+        case 5: return fill<R, D, 5>(L);
+        case 6:
+            if constexpr (D == 2) return fill<R, D, 6>(L);
+            return false;
+        default: return false;
+    }
+}
+
+}  // namespace pcpf

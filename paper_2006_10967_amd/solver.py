@@ -82,6 +82,7 @@ def make_params(prm, precision) -> PcpfParams:
     c.reset_every = int(prm.reset_every)
     c.precond_iters = int(prm.precond_iters)
     c.precision = _PRECISIONS[precision]
+    c.normal_mode = int(getattr(prm, "normal_mode", 0))
     return c
 
 

@@ -187,3 +187,45 @@ def test_nonfinite_is_reported():
     with pytest.raises(PcpfError) as ei:
         s.step(100 * cfg.dt(mesh), 40)
     assert ei.value.status == 5
+
+
+NPHI_CASES = [c for c in CASES if c[0] in ("2d_p4_vortex_ragged", "2d_p3_copybc_rotation",
+                                           "2d_p2_sheared", "3d_p3_leveque_ragged",
+                                           "3d_p4_perturbed")]
+
+
+@pytest.mark.parametrize("cid,d,p,shape,kw", NPHI_CASES, ids=[c[0] for c in NPHI_CASES])
+def test_unpreconditioned_residual_parity(cid, d, p, shape, kw):
+    """The unpreconditioned form (interface normal from phi, §2): the residual against the
+    oracle in the same mode, on smooth and random states."""
+    import dataclasses
+    mesh, prm = W.small_case(d, p, shape, **kw)
+    prm = dataclasses.replace(prm, normal_mode=W.NORMAL_PHI)
+    o = Oracle(d, p, mesh, prm)
+    s = _solver(mesh, p, prm)
+    for kind in ("smooth", "random"):
+        rng = np.random.default_rng(zlib.crc32(f"nphi:{cid}:{kind}".encode()))
+        phi, psi = _states(o, rng, kind)
+        Rp, Rs = o.residual(phi, psi, 0.3)
+        gp, gs = s.residual(phi, psi, 0.3)
+        assert _rel(gp, Rp) <= TOL, (cid, kind, _rel(gp, Rp))
+        assert _rel(gs, Rs) <= TOL, (cid, kind, _rel(gs, Rs))
+
+
+def test_unpreconditioned_trajectory():
+    import dataclasses
+    cfg = W.config("C1")
+    mesh = cfg.mesh()
+    prm = dataclasses.replace(cfg.params, normal_mode=W.NORMAL_PHI, reset_every=0)
+    o = Oracle(2, 3, mesh, prm)
+    s = _solver(mesh, 3, prm)
+    x = o.coords()
+    phi0 = torch.tensor(W.ic_phi(x, cfg.centre, cfg.radius, cfg.params.eps_w))
+    psi0 = phi0 - 0.5
+    dt = cfg.dt(mesh)
+    with torch.no_grad():
+        phi_o, _, _ = o.run(phi0, psi0, 0.0, dt, 100)
+    s.set_state(phi0, psi0, 0.0, 0)
+    s.step(dt, 100)
+    phi_g = s.get_state(want_psi=False)[0]
+    assert _rel(phi_g, phi_o) <= 1e-10
