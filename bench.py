@@ -182,6 +182,44 @@ def adjoint_leg(precision, steps, every):
             "max_abs_dL_dphi0": float(gphi0.abs().max())}
 
 
+def accuracy_leg(cfg, mesh, phi0_np):
+    """The vortex test to t = T (§4): E_L1 = int|phi(T) - phi(0)|, E_r = E_L1 / int phi(0)
+    and E_m = (int phi(T) - int phi(0)) / int phi(0), FP64, with the preconditioned normal
+    (the method, default readings), with the normal from phi (the unpreconditioned form),
+    and with the method given four times the pseudo-time per reset (K = 20 at twice the
+    pseudo step) and resets every 500 steps, inside the ranges the paper quotes."""
+    import dataclasses
+    import torch
+    from paper_2006_10967_amd import Solver
+    T = cfg.params.vel_period
+    dt = cfg.dt(mesh)
+    nsteps = int(round(T / dt))
+    out = {"t_end": nsteps * dt, "steps": nsteps}
+    phi0 = None
+    longer = dataclasses.replace(cfg.params, precond_iters=20, dtau=2 * cfg.params.dtau,
+                                 reset_every=500)
+    for name, prm in (("preconditioned", cfg.params),
+                      ("unpreconditioned", dataclasses.replace(cfg.params, normal_mode=1,
+                                                               reset_every=0)),
+                      ("preconditioned_K20_dtau2x_N500", longer)):
+        s = Solver.from_box(mesh, cfg.order, prm, precision="fp64", device="cuda:0")
+        phi0 = torch.as_tensor(phi0_np).to("cuda:0", s.dtype)
+        s.set_state(phi0, phi0 - 0.5 if prm.normal_mode == 1 else None, 0.0, 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(dt, nsteps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        phiT = s.get_state(want_psi=False)[0]
+        m0 = s.mass(phi0)
+        e_l1 = s.l1(phi0, phiT)
+        out[name] = {"E_L1": e_l1, "E_r": e_l1 / m0, "E_m": (s.mass(phiT) - m0) / m0,
+                     "wall_s": wall}
+        log(f"[bench] {cfg.name} to t = T ({name}): E_L1 = {e_l1:.4e}, "
+            f"E_m = {out[name]['E_m']:.2e}, {wall:.2f} s")
+    return out
+
+
 def load_traffic(workload, kernel, hsh):
     """Counter-measured HBM bytes per launch of a kernel on a workload, recorded in
     profiles/traffic_<workload>.json for the kernel sources of hash hsh (else None)."""
@@ -206,6 +244,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the run to t = T of the vortex workload (both normal forms)")
     ap.add_argument("--adj-steps", type=int, default=512)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
@@ -299,6 +339,9 @@ def main():
         log(f"[bench] {form}: {wallf * 1e3 / K:.4f} ms/step, {vf:.4e} DOF-stage/s, "
             f"int|phi_{form}-phi64| = {l1:.3e}")
         del sf
+
+    if not args.no_accuracy and cfg.params.vel_kind == W.VEL_SINGLE_VORTEX:
+        out["accuracy"] = accuracy_leg(cfg, mesh, phi0)
 
     if not args.no_adjoint:
         adj = {}
