@@ -184,11 +184,8 @@ def adjoint_leg(precision, steps, every):
 
 def accuracy_leg(cfg, mesh, phi0_np):
     """The vortex test to t = T (§4): E_L1 = int|phi(T) - phi(0)|, E_r = E_L1 / int phi(0)
-    and E_m = (int phi(T) - int phi(0)) / int phi(0), FP64, with the preconditioned normal
-    (the method, default readings), with the normal from phi (the unpreconditioned form),
-    and with the method given four times the pseudo-time per reset (K = 20 at twice the
-    pseudo step) and resets every 500 steps, inside the ranges the paper quotes."""
-    import dataclasses
+    and E_m = (int phi(T) - int phi(0)) / int phi(0), FP64, for each form of
+    precond_variants."""
     import torch
     from paper_2006_10967_amd import Solver
     T = cfg.params.vel_period
@@ -196,12 +193,7 @@ def accuracy_leg(cfg, mesh, phi0_np):
     nsteps = int(round(T / dt))
     out = {"t_end": nsteps * dt, "steps": nsteps}
     phi0 = None
-    longer = dataclasses.replace(cfg.params, precond_iters=20, dtau=2 * cfg.params.dtau,
-                                 reset_every=500)
-    for name, prm in (("preconditioned", cfg.params),
-                      ("unpreconditioned", dataclasses.replace(cfg.params, normal_mode=1,
-                                                               reset_every=0)),
-                      ("preconditioned_K20_dtau2x_N500", longer)):
+    for name, prm in precond_variants(cfg.params):
         s = Solver.from_box(mesh, cfg.order, prm, precision="fp64", device="cuda:0")
         phi0 = torch.as_tensor(phi0_np).to("cuda:0", s.dtype)
         s.set_state(phi0, phi0 - 0.5 if prm.normal_mode == 1 else None, 0.0, 0)
@@ -217,6 +209,58 @@ def accuracy_leg(cfg, mesh, phi0_np):
                      "wall_s": wall}
         log(f"[bench] {cfg.name} to t = T ({name}): E_L1 = {e_l1:.4e}, "
             f"E_m = {out[name]['E_m']:.2e}, {wall:.2f} s")
+    return out
+
+
+def precond_variants(prm):
+    """The method with the default readings, the unpreconditioned form (normal from phi),
+    and the method given four times the pseudo-time per reset (K = 20 at twice the pseudo
+    step, resets every 500 steps: inside the 5-20 iterations and 500-2000 steps the paper
+    quotes, the pseudo step just under its RK4 limit)."""
+    import dataclasses
+    return (("preconditioned", prm),
+            ("unpreconditioned", dataclasses.replace(prm, normal_mode=1, reset_every=0)),
+            ("preconditioned_K20_dtau2x_N500",
+             dataclasses.replace(prm, precond_iters=20, dtau=2 * prm.dtau, reset_every=500)))
+
+
+def rotation_leg(orders=(2, 3, 4, 5)):
+    """The slotted-disc solid-body rotation tests of §4.1, one whole turn each, FP64:
+    Zalesak's disc on 100^2 and 200^2 quads and Rudman's disc on 200^2 quads of [0, 4]^2,
+    p = 2..5, for each form of precond_variants. Reports E_r, E_m, the wall time of the
+    turn (resets and pseudo-iterations included) and the DOF-stage rate, next to the
+    paper's E_r for the same mesh and order (context: the paper's tau, pseudo step, K and
+    CFL are not stated)."""
+    import torch
+    import workloads as W
+    from paper_2006_10967_amd import Solver
+    with open(os.path.join(ROOT, "tests", "golden", "paper_parameters.json")) as fh:
+        gold = json.load(fh)
+    runs = [(W.zalesak(n, p), gold["zalesak_E_r"][f"p{p}"][i])
+            for i, n in enumerate((100, 200)) for p in orders]
+    runs += [(W.rudman(p), gold["rudman_E_r"][f"p{p}"]) for p in orders]
+    out = {}
+    for cfg, paper in runs:
+        mesh = cfg.mesh()
+        dt = W.rotation_dt(cfg)
+        res = {"steps": cfg.steps, "dt": dt, "dof": cfg.dof, "E_r_paper": paper}
+        for name, prm in precond_variants(cfg.params):
+            s = Solver.from_box(mesh, cfg.order, prm, precision="fp64", device="cuda:0")
+            phi0 = torch.as_tensor(cfg.initial_phi(s.solution_coords())).to("cuda:0", s.dtype)
+            s.set_state(phi0, phi0 - 0.5 if prm.normal_mode == 1 else None, 0.0, 0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.step(dt, cfg.steps)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            m0 = s.mass(phi0)
+            e_l1 = s.l1(phi0)
+            res[name] = {"E_L1": e_l1, "E_r": e_l1 / m0, "E_m": (s.mass() - m0) / m0,
+                         "wall_s": wall, "dof_stage_per_s": cfg.dof * 4 * cfg.steps / wall}
+            log(f"[bench] {cfg.name} one turn ({name}): E_r = {e_l1 / m0:.3e} "
+                f"(paper {paper:.2e}), E_m = {res[name]['E_m']:.1e}, {wall:.2f} s")
+            del s
+        out[cfg.name] = res
     return out
 
 
@@ -246,6 +290,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the run to t = T of the vortex workload (both normal forms)")
+    ap.add_argument("--no-rotation", action="store_true",
+                    help="skip the slotted-disc rotation tests (Zalesak, Rudman; one turn each)")
     ap.add_argument("--adj-steps", type=int, default=512)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
@@ -342,6 +388,9 @@ def main():
 
     if not args.no_accuracy and cfg.params.vel_kind == W.VEL_SINGLE_VORTEX:
         out["accuracy"] = accuracy_leg(cfg, mesh, phi0)
+
+    if not args.no_rotation:
+        out["rotation"] = rotation_leg()
 
     if not args.no_adjoint:
         adj = {}

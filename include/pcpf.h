@@ -107,7 +107,8 @@ typedef struct pcpf_params {
     double delta_phi;    /* clamp of phi in the LOGIT reset (1e-12) */
     double vel_amp;      /* velocity amplitude A: v = A v0(x) g(t) */
     double vel_period;   /* T in g(t) = cos(pi t / T) (vortex and LeVeque kinds) */
-    double vel_u0[3];    /* constant velocity of PCPF_VEL_UNIFORM */
+    double vel_u0[3];    /* PCPF_VEL_UNIFORM: the constant velocity; PCPF_VEL_ROTATION: the
+                            centre (u0[0], u0[1]) of the rotation (c_y - y, x - c_x) */
     int32_t vel_kind;    /* PCPF_VEL_* */
     int32_t reset_mode;  /* PCPF_RESET_* */
     int32_t reset_every; /* reset + precondition before steps with index % N == 0 (0: never) */

@@ -2,7 +2,8 @@
 
 v(x, t) = A v0(x) g(t):
   uniform        v0 = u0, g = 1
-  rotation       v0 = (0.5 - y, x - 0.5), g = 1                       (§4.1, Zalesak)
+  rotation       v0 = (c_y - y, x - c_x) about c = (u0[0], u0[1]), g = 1
+                 (§4.1: Zalesak c = (0.5, 0.5), Rudman c = (2, 2))
   single vortex  v0 = (-sin^2(pi x) sin(2 pi y), sin(2 pi x) sin^2(pi y)),
                  g = cos(pi t / T)                                    (§4.2, Rider-Kothe)
   LeVeque 3D     v0 = (2 sin^2(pi x) sin(2 pi y) sin(2 pi z),
@@ -34,7 +35,7 @@ def spatial(kind: int, x: torch.Tensor, u0=(0.0, 0.0, 0.0)) -> torch.Tensor:
     if kind == ROTATION:
         if d != 2:
             raise ValueError("rotation field is 2D")
-        return torch.stack([0.5 - x[..., 1], x[..., 0] - 0.5], -1)
+        return torch.stack([float(u0[1]) - x[..., 1], x[..., 0] - float(u0[0])], -1)
     if kind == SINGLE_VORTEX:
         if d != 2:
             raise ValueError("single vortex is 2D")

@@ -84,8 +84,8 @@ __device__ __forceinline__ void velocity(const Phys<R>& ph, const R (&x)[D], R (
 #pragma unroll
         for (int k = 0; k < D; ++k) v[k] = A * ph.u0[k];
     } else if (ph.vel_kind == PCPF_VEL_ROTATION) {
-        v[0] = A * (R(0.5) - x[1]);
-        v[1] = A * (x[0] - R(0.5));
+        v[0] = A * (ph.u0[1] - x[1]);      // rigid rotation about (u0[0], u0[1])
+        v[1] = A * (x[0] - ph.u0[0]);
 #pragma unroll
         for (int k = 2; k < D; ++k) v[k] = R(0);
     } else if (ph.vel_kind == PCPF_VEL_SINGLE_VORTEX) {
@@ -117,8 +117,8 @@ template <typename R, int D>
 __device__ __forceinline__ void velocity_lin(const Phys<R>& ph, const R (&x)[D], R (&v)[D]) {
     const R A = ph.ampg;
     if (ph.vel_kind == PCPF_VEL_ROTATION) {
-        v[0] = A * (R(0.5) - x[1]);
-        v[1] = A * (x[0] - R(0.5));
+        v[0] = A * (ph.u0[1] - x[1]);      // rigid rotation about (u0[0], u0[1])
+        v[1] = A * (x[0] - ph.u0[0]);
 #pragma unroll
         for (int k = 2; k < D; ++k) v[k] = R(0);
     } else {

@@ -39,3 +39,25 @@ def test_workload_shapes():
     c5 = W.config("C5")
     assert c5.dof == 96 ** 3 * 125
     assert W.config("C1").dof == 4096
+
+
+def test_slotted_disc_workloads():
+    z, r = GOLD["zalesak"], GOLD["rudman"]
+    for n in z["meshes"]:
+        for p in (2, 3, 4, 5):
+            c = W.zalesak(n, p)
+            assert c.dof == n * n * (p + 1) ** 2 and c.length == 1.0
+            assert tuple(c.centre) == tuple(z["centre"]) and c.radius == z["radius"]
+            assert c.slot == (z["slot_half_width"], z["slot_top"])
+            assert tuple(c.params.vel_u0[:2]) == tuple(z["rotation_centre"])
+            assert c.params.vel_kind == W.VEL_ROTATION
+            # a whole number of steps makes exactly one turn, inside the CFL bound
+            assert math.isclose(W.rotation_dt(c) * c.steps, 2 * math.pi, rel_tol=1e-15)
+            assert W.rotation_dt(c) <= c.dt()
+    for p in (2, 3, 4, 5):
+        c = W.rudman(p)
+        assert c.n == r["mesh"] and c.length == r["domain"] and math.isclose(c.h, 0.02)
+        assert tuple(c.centre) == tuple(r["centre"]) and c.radius == r["radius"]
+        assert c.slot == (r["slot_half_width"], r["slot_top"])
+        assert tuple(c.params.vel_u0[:2]) == tuple(r["rotation_centre"])
+        assert float(c.mesh().planes[0][-1]) == r["domain"]

@@ -7,9 +7,10 @@ oracle. It holds problem definitions only and none of the FR-PCPF method's arith
   perturbation), the element corner and the constant Jacobian of each affine element,
   and the element adjacency of the box (including periodic wrap);
 * the initial condition of §4 (tanh profile of a signed distance, Eq. initialCond with the
-  disc/sphere distance of Eq. discEq), evaluated at coordinates the caller supplies;
+  disc/sphere distance of Eq. discEq, or the distance to a slotted disc of §4.1),
+  evaluated at coordinates the caller supplies;
 * velocity-field identifiers and the parameter values the paper fixes (§2, §3.2, §4);
-* the benchmark configurations (2D rotation/vortex and 3D deformation shapes).
+* the benchmark configurations (2D vortex, slotted-disc rotation and 3D deformation).
 
 Coordinates of solution points are NOT computed here: each side maps its own reference
 nodes.
@@ -142,6 +143,47 @@ def signed_distance_ball(x: np.ndarray, centre: Sequence[float], radius: float) 
     return radius - np.sqrt(np.sum((x - c) ** 2, axis=-1))
 
 
+def _segment_distance(x: np.ndarray, a, b) -> np.ndarray:
+    """Distance from points x[..., 2] to the segment [a, b]."""
+    a = np.asarray(a, dtype=np.float64)
+    ab = np.asarray(b, dtype=np.float64) - a
+    s = np.clip(np.sum((x - a) * ab, axis=-1) / float(ab @ ab), 0.0, 1.0)
+    return np.sqrt(np.sum((x - (a + s[..., None] * ab)) ** 2, axis=-1))
+
+
+def signed_distance_slotted_disc(x: np.ndarray, centre: Sequence[float], radius: float,
+                                 half_width: float, slot_top: float) -> np.ndarray:
+    """Signed distance (positive inside) to the slotted disc of §4.1: the disc of Eq. discEq
+    less the slot {|x - x_c| <= half_width, y <= slot_top}, which opens at the bottom of the
+    disc.
+
+    The boundary is the circle arc outside the slot and the three slot walls (the two
+    vertical sides from the circle up to ``slot_top`` and the top). The distance to the arc
+    is the radial distance where the radial projection lands on the arc and the distance to
+    the nearer arc end otherwise; the distance to the boundary is the least over the four
+    pieces, with the sign of membership."""
+    c = np.asarray(centre, dtype=np.float64)
+    w, top = float(half_width), float(slot_top)
+    if not (0.0 < w < radius and c[1] - radius < top < c[1] + radius):
+        raise ValueError("the slot must cut the bottom of the disc and end inside it")
+    ybot = c[1] - math.sqrt(radius ** 2 - w ** 2)        # the walls meet the circle here
+    left, right = (c[0] - w, ybot), (c[0] + w, ybot)
+    rel = x - c
+    rho = np.sqrt(np.sum(rel ** 2, axis=-1))
+    safe = np.where(rho > 0.0, rho, 1.0)
+    proj = c + radius * rel / safe[..., None]             # nearest point of the full circle
+    on_arc = ~((np.abs(proj[..., 0] - c[0]) < w) & (proj[..., 1] < top)) & (rho > 0.0)
+    d_arc = np.where(on_arc, np.abs(rho - radius),
+                     np.minimum(np.sqrt(np.sum((x - np.asarray(left)) ** 2, axis=-1)),
+                                np.sqrt(np.sum((x - np.asarray(right)) ** 2, axis=-1))))
+    d = np.minimum.reduce([d_arc,
+                           _segment_distance(x, left, (c[0] - w, top)),
+                           _segment_distance(x, right, (c[0] + w, top)),
+                           _segment_distance(x, (c[0] - w, top), (c[0] + w, top))])
+    inside = (rho <= radius) & ~((np.abs(x[..., 0] - c[0]) <= w) & (x[..., 1] <= top))
+    return np.where(inside, d, -d)
+
+
 def tanh_profile(psi_d: np.ndarray, eps_w: float) -> np.ndarray:
     """phi = (1 + tanh(psi_d / (2 eps_w))) / 2, i.e. Eq. initialCond with beta = 1/(2 eps_w)."""
     return 0.5 * (1.0 + np.tanh(psi_d / (2.0 * eps_w)))
@@ -216,10 +258,12 @@ class Config:
     params: Params = None
     vmax: float = 1.0
     description: str = ""
+    length: float = 1.0          # the domain is [0, length]^d
+    slot: Optional[tuple] = None  # (half width, top) of a slotted disc (§4.1)
 
     @property
     def h(self) -> float:
-        return 1.0 / self.n
+        return self.length / self.n
 
     @property
     def nelem(self) -> int:
@@ -238,10 +282,20 @@ class Config:
         planes = []
         for _ in range(self.ndims):
             if self.perturb > 0:
-                planes.append(perturbed_planes(self.n, self.perturb, rng))
+                planes.append(perturbed_planes(self.n, self.perturb, rng, hi=self.length))
             else:
-                planes.append(uniform_planes(self.n))
+                planes.append(uniform_planes(self.n, hi=self.length))
         return box_mesh(planes, [self.periodic] * self.ndims)
+
+    def distance(self, x: np.ndarray) -> np.ndarray:
+        """Signed distance of the initial shape (disc/sphere, or slotted disc)."""
+        if self.slot is None:
+            return signed_distance_ball(x, self.centre, self.radius)
+        return signed_distance_slotted_disc(x, self.centre, self.radius, *self.slot)
+
+    def initial_phi(self, x: np.ndarray) -> np.ndarray:
+        """Eq. initialCond at the points x[..., d] with beta = 1/(2 eps_w)."""
+        return tanh_profile(self.distance(x), self.params.eps_w)
 
     def hmin(self, mesh: Optional[BoxMesh] = None) -> float:
         mesh = mesh or self.mesh()
@@ -301,6 +355,45 @@ def _cfg_c5() -> Config:
                               "LeVeque deformation, 100 RK4 steps")
 
 
+ROTATION_CFL = {2: 0.05, 3: 0.05, 4: 0.05, 5: 0.03}
+
+
+def zalesak(n: int, order: int) -> Config:
+    """Zalesak's slotted disc (§4.1): r = 0.15 at (0.5, 0.75), slot |x - 0.5| <= 0.025,
+    y <= 0.85, rigid rotation (0.5 - y, x - 0.5) for one turn (t = 2 pi) on n x n quads;
+    dt is the CFL step rounded down so that a whole number of steps makes the turn."""
+    h = 1.0 / n
+    prm = default_params(2, order, h, vel_kind=VEL_ROTATION, vel_u0=(0.5, 0.5, 0.0))
+    cfl = ROTATION_CFL.get(order, 0.03)
+    vmax = math.sqrt(0.5)                               # at the corners of the square
+    steps = int(math.ceil(2.0 * math.pi / (cfl * h / vmax)))
+    return Config(f"zalesak2d_{n}x{n}_p{order}", 2, order, n, centre=(0.5, 0.75),
+                  radius=0.15, cfl=cfl, steps=steps, params=prm, vmax=vmax,
+                  slot=(0.025, 0.85),
+                  description=f"Zalesak slotted disc, {n}x{n} quads, p={order}, one rotation")
+
+
+def rudman(order: int, n: int = 200) -> Config:
+    """Rudman's slotted disc (§4.1): [0, 4]^2, r = 0.5 at (2, 2.75), slot |x - 2| <= 0.06,
+    y <= 2.65, rigid rotation (2 - y, x - 2) for one turn on n x n quads."""
+    L = 4.0
+    h = L / n
+    prm = default_params(2, order, h, vel_kind=VEL_ROTATION, vel_u0=(2.0, 2.0, 0.0))
+    cfl = ROTATION_CFL.get(order, 0.03)
+    vmax = 2.0 * math.sqrt(2.0)
+    steps = int(math.ceil(2.0 * math.pi / (cfl * h / vmax)))
+    return Config(f"rudman2d_{n}x{n}_p{order}", 2, order, n, centre=(2.0, 2.75),
+                  radius=0.5, cfl=cfl, steps=steps, params=prm, vmax=vmax, length=L,
+                  slot=(0.06, 2.65),
+                  description=f"Rudman slotted disc on [0,4]^2, {n}x{n} quads, p={order}, "
+                              "one rotation")
+
+
+def rotation_dt(cfg: Config) -> float:
+    """The step of a rotation workload: one turn (t = 2 pi) in cfg.steps steps."""
+    return 2.0 * math.pi / cfg.steps
+
+
 CONFIGS = {"C1": _cfg_c1, "C2": _cfg_c2, "C3": _cfg_c3, "C4": _cfg_c4, "C5": _cfg_c5}
 
 
@@ -316,10 +409,13 @@ def adjoint_target_centre(cfg: Config, seed: int = 0) -> np.ndarray:
 
 
 def small_case(ndims: int, order: int, shape: Sequence[int], *, vel_kind=VEL_UNIFORM,
-               vel_u0=(1.0, 0.5, 0.25), vel_period=8.0, perturb: float = 0.0,
+               vel_u0=None, vel_period=8.0, perturb: float = 0.0,
                periodic=True, seed: int = 3, shear: float = 0.0, **over):
     """A small mesh + parameter set for parity tests (non-cubic shapes give ragged
-    element chunks)."""
+    element chunks). vel_u0 defaults to (1, 0.5, 0.25) for the uniform field and to the
+    centre of the unit square for the rotation."""
+    if vel_u0 is None:
+        vel_u0 = (0.5, 0.5, 0.0) if vel_kind == VEL_ROTATION else (1.0, 0.5, 0.25)
     rng = np.random.default_rng(seed)
     planes = []
     for n in shape:
