@@ -147,9 +147,15 @@ def smeared_sign(disc, prm, psi0):
     return torch.tanh(psi0 / g)
 
 
-def precond_residual(disc, prm, psi, sgn):
-    """dpsi/dtau of the preconditioning system (§3.2)."""
+def precond_residual(disc, prm, psi, sgn, psi0=None):
+    """dpsi/dtau of the preconditioning system (§3.2). The smeared sign is ``sgn``, fixed at
+    the reset; with the printed form of the sign (sgn_mode 1, §2 text after Eq.
+    lsequation) it is tanh(psi0 / max(|grad psi|, delta_g)) with the gradient of the
+    current psi, and ``psi0`` must be given."""
     psif, q = corrected_gradient(disc, psi)
+    if getattr(prm, "sgn_mode", 0) == 1:
+        g = torch.clamp(torch.linalg.vector_norm(q, dim=-1), min=prm.delta_g)
+        sgn = torch.tanh(psi0 / g)
     nu = sensor(disc, prm, psi)
     g = -nu[:, None, None] * q
     gt = _transform_flux(disc, g)

@@ -5,9 +5,11 @@
 * Reset psi0 = phi - 1/2 at the start and every N physical steps (§2, Eq. after the psi
   transport equation; N = 1000 in §3.2), followed by a fixed number K of pseudo-time RK4
   iterations of the preconditioning system (the printed stop rule of §3.2 is garbled; a
-  fixed count inside the quoted 5-20 range is used). The optional LOGIT reset
-  psi0 = eps_w ln(phi/(1-phi)) inverts the tanh kernel of §2 (phi clamped to
-  [delta_phi, 1-delta_phi]).
+  fixed count inside the quoted 5-20 range is the default). The stop rule itself is the
+  option stop_mode 1: stop after the first iteration k whose RMS over all solution points
+  of (psi^k - psi^(k-1)) / dtau is <= 1/2 (the printed "psi_n^2" read as the iterate
+  psi^n), at most K iterations. The optional LOGIT reset psi0 = eps_w ln(phi/(1-phi))
+  inverts the tanh kernel of §2 (phi clamped to [delta_phi, 1-delta_phi]).
 * Error measures of §4: E_L1 = int |phi - phi_e|, E_r = E_L1 / int phi_e,
   E_m = (int phi - int phi_0) / int phi_e, integrals by the Gauss-Legendre quadrature of
   the solution points (|J| W).
@@ -33,8 +35,8 @@ class Oracle:
     def residual(self, phi, psi, t, amp=None):
         return res.physical_residual(self.disc, self.prm, phi, psi, t, amp)
 
-    def precond_residual(self, psi, sgn):
-        return res.precond_residual(self.disc, self.prm, psi, sgn)
+    def precond_residual(self, psi, sgn, psi0=None):
+        return res.precond_residual(self.disc, self.prm, psi, sgn, psi0)
 
     def sensor(self, psi):
         return res.sensor(self.disc, self.prm, psi)
@@ -47,16 +49,28 @@ class Oracle:
         return phi - 0.5
 
     def precondition(self, phi, iters=None):
-        """Reset + K pseudo-time RK4 iterations; returns (psi, sgn)."""
+        """Reset + pseudo-time RK4 iterations (K, or until the stop rule holds); returns
+        (psi, sgn), with psi0 in place of sgn under the printed form of the sign. The
+        number of iterations and the last stop-rule RMS are kept in last_iters and
+        last_rms."""
         prm = self.prm
         K = prm.precond_iters if iters is None else iters
         psi0 = self.reset_psi(phi)
-        sgn = res.smeared_sign(self.disc, prm, psi0)
+        current = getattr(prm, "sgn_mode", 0) == 1
+        sgn = None if current else res.smeared_sign(self.disc, prm, psi0)
+        rms_stop = getattr(prm, "stop_mode", 0) == 1
         psi = psi0
         dtau = prm.dtau
-        for _ in range(K):
-            psi = rk4(lambda y: self.precond_residual(y, sgn), psi, dtau)
-        return psi, sgn
+        self.last_iters, self.last_rms = 0, float("nan")
+        for k in range(K):
+            new = rk4(lambda y: self.precond_residual(y, sgn, psi0), psi, dtau)
+            self.last_iters = k + 1
+            if rms_stop:
+                self.last_rms = float(torch.sqrt(torch.mean(((new - psi) / dtau) ** 2)))
+            psi = new
+            if rms_stop and self.last_rms <= 0.5:
+                break
+        return psi, (psi0 if current else sgn)
 
     def step(self, phi, psi, t, dt, amp=None):
         def f(y, tt):

@@ -4,12 +4,17 @@ P12 sensor and viscosity ramp: closed forms of Eqs. resolutionIndicator and nu_s
     fields with a prescribed top-mode energy fraction.
 P13 eikonal fixed point and the sign of the source term.
 P14 the logit reset inverts the tanh kernel of §2 to the accuracy of float64.
+Options of the printed forms: the smeared sign with the current |grad psi| (§2, text after
+Eq. lsequation) against closed forms, and the RMS stop rule of §3.2 against its fixed point,
+a closed-form first iterate and the first-crossing property.
 """
 import math
 
 import numpy as np
 import pytest
 import torch
+
+import dataclasses
 
 import workloads as W
 from oracle import Oracle
@@ -124,3 +129,66 @@ def test_linear_reset_and_precondition_shape():
     # |phi - 1/2| > 0.25
     far = (phi - 0.5).abs() > 0.25
     assert bool(torch.all(torch.sign(psi[far]) == torch.sign((phi - 0.5)[far])))
+
+
+@pytest.mark.parametrize("d,p", [(2, 3), (3, 2)])
+def test_current_sign_closed_forms(d, p):
+    mesh, prm = W.small_case(d, p, (3,) * d, periodic=False, perturb=0.15)
+    cur = dataclasses.replace(prm, sgn_mode=W.SGN_CURRENT)
+    o, oc = Oracle(d, p, mesh, prm), Oracle(d, p, mesh, cur)
+    x = o.disc.xs
+    rng = np.random.default_rng(4)
+    psi0 = T(np.tanh(3 * (x[..., 0] - 0.45)) + 0.05 * rng.standard_normal(x.shape[:2]))
+    # at psi = psi0 the printed sign is the sign of the reset
+    R_reset = o.precond_residual(psi0, res.smeared_sign(o.disc, prm, psi0))
+    assert torch.equal(oc.precond_residual(psi0, None, psi0), R_reset)
+    # psi = 2(x - 1/2): no top modes (nu = 0), no jumps, |grad psi| = 2, so
+    # dpsi/dtau = tanh(psi0 / 2) (1 - 2) with psi0 over the CURRENT gradient
+    psi = T(2 * (x[..., 0] - 0.5))
+    R = oc.precond_residual(psi, None, psi0)
+    assert float((R + torch.tanh(psi0 / 2)).abs().max()) < 1e-12
+
+
+def _linear_case(slope):
+    """2D copy-boundary mesh and a phi whose linear reset is psi0 = slope (x - 1/2)."""
+    mesh, prm = W.small_case(2, 3, (4, 3), periodic=False, perturb=0.1)
+    prm = dataclasses.replace(prm, stop_mode=W.STOP_RMS, precond_iters=7)
+    o = Oracle(2, 3, mesh, prm)
+    x = o.disc.xs[..., 0]
+    return o, prm, T(slope * (x - 0.5) + 0.5), slope * (x - 0.5)
+
+
+def test_rms_stop_fixed_point():
+    # psi0 = x - 1/2 is a distance function: R_pc = 0, so the first iterate repeats psi0,
+    # the RMS is 0 and the rule stops after one iteration
+    o, prm, phi, psi0 = _linear_case(1.0)
+    psi, _ = o.precondition(phi)
+    assert o.last_iters == 1 and o.last_rms < 1e-12
+    assert float((psi - T(psi0)).abs().max()) < 1e-13
+
+
+def test_rms_stop_first_iterate():
+    # psi0 = 2(x - 1/2): dpsi/dtau = -tanh(psi0/2) at tau = 0 and |grad psi| moves by
+    # O(dtau) over one iteration, so RMS((psi^1 - psi^0)/dtau) = RMS(tanh(psi0/2)) (1 + O(dtau))
+    o, prm, phi, psi0 = _linear_case(2.0)
+    o.precondition(phi, iters=1)
+    want = math.sqrt(float(torch.mean(torch.tanh(T(psi0) / 2) ** 2)))
+    assert o.last_iters == 1
+    assert abs(o.last_rms - want) <= 20 * prm.dtau * want, (o.last_rms, want)
+
+
+@pytest.mark.parametrize("sgn_mode", [W.SGN_PSI0, W.SGN_CURRENT])
+def test_rms_stop_is_first_crossing(sgn_mode):
+    mesh, prm = W.small_case(2, 3, (6, 6), periodic=True)
+    prm = dataclasses.replace(prm, stop_mode=W.STOP_RMS, precond_iters=20, sgn_mode=sgn_mode)
+    o = Oracle(2, 3, mesh, prm)
+    phi = T(W.ic_phi(o.coords(), (0.5, 0.5), 0.3, 0.05))
+    psi, _ = o.precondition(phi)
+    k = o.last_iters
+    assert 1 < k < 20 and o.last_rms <= 0.5
+    # capped one short of k, the rule had not yet been met, and the iterates agree
+    psi_short, _ = o.precondition(phi, iters=k - 1)
+    assert o.last_iters == k - 1 and o.last_rms > 0.5
+    fixed = Oracle(2, 3, mesh, dataclasses.replace(prm, stop_mode=W.STOP_FIXED))
+    psi_k, _ = fixed.precondition(phi, iters=k)
+    assert torch.equal(psi_k, psi)

@@ -33,6 +33,10 @@ RESET_LINEAR = 0
 RESET_LOGIT = 1
 NORMAL_PSI = 0   # interface normal from the preconditioned level set psi (§2, the method)
 NORMAL_PHI = 1   # normal from phi itself: the unpreconditioned conservative phase field
+SGN_PSI0 = 0     # smeared sign with |grad psi0| of the reset (default reading)
+SGN_CURRENT = 1  # smeared sign with the current |grad psi| (the printed form)
+STOP_FIXED = 0   # a fixed number of pseudo-time iterations (default reading)
+STOP_RMS = 1     # the printed RMS stop rule (threshold 1/2, capped)
 
 
 # --------------------------------------------------------------------------------------
@@ -223,6 +227,8 @@ class Params:
     vel_period: float = 1.0
     vel_u0: tuple = (0.0, 0.0, 0.0)
     normal_mode: int = NORMAL_PSI
+    sgn_mode: int = SGN_PSI0
+    stop_mode: int = STOP_FIXED
 
 
 def default_params(ndims: int, order: int, h: float, *, eps_w: Optional[float] = None,
