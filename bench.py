@@ -185,14 +185,16 @@ def adjoint_leg(precision, steps, every):
 def accuracy_leg(cfg, mesh, phi0_np):
     """The vortex test to t = T (§4): E_L1 = int|phi(T) - phi(0)|, E_r = E_L1 / int phi(0)
     and E_m = (int phi(T) - int phi(0)) / int phi(0), FP64, for each form of
-    precond_variants."""
+    precond_variants; then the FP32 and BF16 forms with the default readings, each against
+    the FP64 run: "equal interface error" holds when |E_L1 - E_L1,64| <= 0.02 E_L1,64 and
+    int|phi - phi_64| <= 0.1 E_L1,64 at t = T."""
     import torch
     from paper_2006_10967_amd import Solver
     T = cfg.params.vel_period
     dt = cfg.dt(mesh)
     nsteps = int(round(T / dt))
     out = {"t_end": nsteps * dt, "steps": nsteps}
-    phi0 = None
+    ref = None
     for name, prm in precond_variants(cfg.params):
         s = Solver.from_box(mesh, cfg.order, prm, precision="fp64", device="cuda:0")
         phi0 = torch.as_tensor(phi0_np).to("cuda:0", s.dtype)
@@ -209,19 +211,47 @@ def accuracy_leg(cfg, mesh, phi0_np):
                      "wall_s": wall}
         log(f"[bench] {cfg.name} to t = T ({name}): E_L1 = {e_l1:.4e}, "
             f"E_m = {out[name]['E_m']:.2e}, {wall:.2f} s")
+        if ref is None:
+            ref = (s, phi0, phiT.clone(), e_l1, m0, wall)
+        else:
+            del s
+    s64, phi0, phi64, e64, m0, wall64 = ref
+    out["forms_default_readings"] = {}
+    for form in ("fp32", "bf16"):
+        s = Solver.from_box(mesh, cfg.order, cfg.params, precision=form, device="cuda:0")
+        s.set_state(phi0.to(s.dtype), None, 0.0, 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(dt, nsteps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        phiT = s.get_state(want_psi=False)[0].double()
+        e_l1 = s64.l1(phi0, phiT)
+        diff = s64.l1(phi64, phiT)
+        r = {"E_L1": e_l1, "E_r": e_l1 / m0, "E_m": (s64.mass(phiT) - m0) / m0,
+             "int_abs_diff_vs_fp64": diff, "wall_s": wall, "speedup_vs_fp64": wall64 / wall,
+             "equal_interface_error": bool(abs(e_l1 - e64) <= 0.02 * e64 and diff <= 0.1 * e64)}
+        out["forms_default_readings"][form] = r
+        log(f"[bench] {cfg.name} to t = T ({form}): E_L1 = {e_l1:.4e} (fp64 {e64:.4e}), "
+            f"int|phi-phi64| = {diff:.2e}, equal: {r['equal_interface_error']}, "
+            f"x{r['speedup_vs_fp64']:.2f}")
+        del s
     return out
 
 
 def precond_variants(prm):
     """The method with the default readings, the unpreconditioned form (normal from phi),
-    and the method given four times the pseudo-time per reset (K = 20 at twice the pseudo
+    the method given four times the pseudo-time per reset (K = 20 at twice the pseudo
     step, resets every 500 steps: inside the 5-20 iterations and 500-2000 steps the paper
-    quotes, the pseudo step just under its RK4 limit)."""
+    quotes, the pseudo step just under its RK4 limit), and the printed forms of the sign
+    (current |grad psi|) and of the stop rule (RMS <= 1/2, at most 20 iterations)."""
     import dataclasses
     return (("preconditioned", prm),
             ("unpreconditioned", dataclasses.replace(prm, normal_mode=1, reset_every=0)),
             ("preconditioned_K20_dtau2x_N500",
-             dataclasses.replace(prm, precond_iters=20, dtau=2 * prm.dtau, reset_every=500)))
+             dataclasses.replace(prm, precond_iters=20, dtau=2 * prm.dtau, reset_every=500)),
+            ("preconditioned_printed_sign_rms_stop",
+             dataclasses.replace(prm, sgn_mode=1, stop_mode=1, precond_iters=20)))
 
 
 def rotation_leg(orders=(2, 3, 4, 5)):
@@ -297,7 +327,7 @@ def main():
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: this build has no multi-GPU path "
+        print(f"bench.py measures one GPU: the library has no multi-GPU path "
               f"(--gpus {args.gpus} requested)", file=sys.stderr)
         sys.exit(2)
 

@@ -61,10 +61,21 @@ enum { PCPF_VEL_UNIFORM = 0, PCPF_VEL_ROTATION = 1,           /* analytic veloci
        PCPF_VEL_SINGLE_VORTEX = 2, PCPF_VEL_LEVEQUE3D = 3 };
 enum { PCPF_RESET_LINEAR = 0, PCPF_RESET_LOGIT = 1 };         /* psi reset transform */
 enum { PCPF_MODE_PHYS = 0, PCPF_MODE_PRECOND = 1 };           /* residual kind */
-enum { PCPF_REDUCE_MASS = 0, PCPF_REDUCE_L1 = 1 };            /* FP64 reductions */
+enum { PCPF_REDUCE_MASS = 0, PCPF_REDUCE_L1 = 1,              /* FP64 reductions */
+       PCPF_REDUCE_RMS = 2 };
 enum { PCPF_NORMAL_PSI = 0,  /* interface normal grad psi / |grad psi| (§2, the method) */
        PCPF_NORMAL_PHI = 1 };/* grad phi / |grad phi|: the unpreconditioned conservative phase
                                 field of §2 (psi is still advected but not used) */
+/* Smeared sign of the preconditioning equation (§2, Eq. lsequation and the text after it:
+ * tanh(psi0 / |grad psi|)). */
+enum { PCPF_SGN_PSI0 = 0,    /* |grad psi0| of the reset, once per reset (default; equals
+                                the printed form at the first pseudo stage) */
+       PCPF_SGN_CURRENT = 1 };/* |grad psi| of the current pseudo stage (the printed form) */
+/* Stop rule of the pseudo-time iterations (§3.2, after Eq. pseudotimesystem). */
+enum { PCPF_STOP_FIXED = 0,  /* exactly precond_iters iterations (default) */
+       PCPF_STOP_RMS = 1 };  /* stop after the first iteration k with
+                                sqrt(mean over all E N_u points of ((psi^k - psi^(k-1))/dtau)^2)
+                                <= 1/2, at most precond_iters iterations */
 
 /* Mesh and FR operators (host memory, float64, row-major). */
 typedef struct pcpf_mesh {
@@ -112,10 +123,12 @@ typedef struct pcpf_params {
     int32_t vel_kind;    /* PCPF_VEL_* */
     int32_t reset_mode;  /* PCPF_RESET_* */
     int32_t reset_every; /* reset + precondition before steps with index % N == 0 (0: never) */
-    int32_t precond_iters; /* pseudo-time RK4 iterations per reset (>= 0) */
+    int32_t precond_iters; /* pseudo-time RK4 iterations per reset (>= 0); the cap of
+                              PCPF_STOP_RMS */
     int32_t precision;   /* PCPF_FP64, PCPF_FP32 or PCPF_BF16 */
     int32_t normal_mode; /* PCPF_NORMAL_PSI (default) or PCPF_NORMAL_PHI */
-    int32_t reserved[2]; /* must be 0 */
+    int32_t sgn_mode;    /* PCPF_SGN_PSI0 (default) or PCPF_SGN_CURRENT */
+    int32_t stop_mode;   /* PCPF_STOP_FIXED (default) or PCPF_STOP_RMS */
 } pcpf_params;
 
 typedef struct pcpf_ctx pcpf_ctx;
@@ -179,9 +192,17 @@ pcpf_status pcpf_step(pcpf_ctx* ctx, double dt, int64_t nsteps);
 
 /* Reset psi from the current phi (psi0 = phi - 1/2, or eps_w ln(phi/(1-phi)) with the
  * LOGIT mode, always in float64), compute the smeared sign tanh(psi0/max(|grad psi0|,
- * delta_g)) and run iters pseudo-time RK4 iterations (iters < 0: params.precond_iters).
- * phi is not changed. */
+ * delta_g)) (PCPF_SGN_PSI0; PCPF_SGN_CURRENT keeps psi0 and takes |grad psi| at every
+ * pseudo stage) and run iters pseudo-time RK4 iterations (iters < 0:
+ * params.precond_iters), stopping early under PCPF_STOP_RMS. phi is not changed.
+ * PCPF_STOP_RMS reads one double back per iteration (a stream synchronisation). */
 pcpf_status pcpf_precondition(pcpf_ctx* ctx, int32_t iters);
+
+/* The last preconditioning (pcpf_precondition or a reset inside pcpf_step): the number of
+ * pseudo-time iterations it ran and, under PCPF_STOP_RMS, the RMS of (psi^k -
+ * psi^(k-1)) / dtau after the last of them (NaN under PCPF_STOP_FIXED). Either output may
+ * be NULL. ESTATE before the first preconditioning. */
+pcpf_status pcpf_precond_info(const pcpf_ctx* ctx, int32_t* iters, double* rms);
 
 /* One residual evaluation (the parity entry point). PCPF_MODE_PHYS: d/dt of (phi, psi)
  * at time t from d_phi, d_psi into d_rphi, d_rpsi. PCPF_MODE_PRECOND: d/dtau of psi from
@@ -191,7 +212,8 @@ pcpf_status pcpf_precondition(pcpf_ctx* ctx, int32_t iters);
 pcpf_status pcpf_residual(pcpf_ctx* ctx, const void* d_phi, const void* d_psi, double t,
                           int32_t mode, void* d_rphi, void* d_rpsi);
 
-/* Smeared sign of the last reset, [E][N_u] in the state type. ESTATE before a reset. */
+/* Smeared sign of the last reset, [E][N_u] in the state type (under PCPF_SGN_CURRENT:
+ * psi0, from which each pseudo stage forms the sign). ESTATE before a reset. */
 pcpf_status pcpf_get_sign(pcpf_ctx* ctx, void* d_sgn);
 
 /* Persson-Peraire element viscosity nu_s (§3.2, Eqs. resolutionIndicator and nu_s) of the
@@ -200,8 +222,11 @@ pcpf_status pcpf_sensor(pcpf_ctx* ctx, const void* d_psi, void* d_nu);
 
 /* FP64 reductions with the element quadrature |J| W (§4 error measures):
  * PCPF_REDUCE_MASS: integral of d_field (NULL: the stored phi);
- * PCPF_REDUCE_L1:   integral of |d_field - d_ref| (d_field NULL: the stored phi).
- * Deterministic two-pass reduction; synchronous (8 bytes device to host). */
+ * PCPF_REDUCE_L1:   integral of |d_field - d_ref| (d_field NULL: the stored phi);
+ * PCPF_REDUCE_RMS:  sqrt(sum over all E N_u points of (d_field - d_ref)^2 / (E N_u)),
+ *                   unweighted (the norm of the pseudo-time stop rule, §3.2).
+ * Deterministic two-pass reduction; synchronous (8 bytes device to host). EINVAL for an
+ * unknown kind or a missing d_ref. */
 pcpf_status pcpf_reduce(pcpf_ctx* ctx, int32_t what, const void* d_field,
                         const void* d_ref, double* out);
 

@@ -15,7 +15,9 @@ STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "EDEVICE", 3: "EUNSUPPORTED", 4: "ESTAT
 PCPF_FP64, PCPF_FP32, PCPF_BF16 = 0, 1, 2
 PCPF_MODE_PHYS, PCPF_MODE_PRECOND = 0, 1
 PCPF_NORMAL_PSI, PCPF_NORMAL_PHI = 0, 1
-PCPF_REDUCE_MASS, PCPF_REDUCE_L1 = 0, 1
+PCPF_REDUCE_MASS, PCPF_REDUCE_L1, PCPF_REDUCE_RMS = 0, 1, 2
+PCPF_SGN_PSI0, PCPF_SGN_CURRENT = 0, 1
+PCPF_STOP_FIXED, PCPF_STOP_RMS = 0, 1
 MAX_ORDER = 6
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -39,7 +41,7 @@ class PcpfParams(ctypes.Structure):
                 ("vel_kind", ctypes.c_int32), ("reset_mode", ctypes.c_int32),
                 ("reset_every", ctypes.c_int32), ("precond_iters", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("normal_mode", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("sgn_mode", ctypes.c_int32), ("stop_mode", ctypes.c_int32)]
 
 
 class PcpfError(RuntimeError):
@@ -83,6 +85,7 @@ def load() -> ctypes.CDLL:
         "pcpf_get_state": (st, [vp, vp, vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]),
         "pcpf_step": (st, [vp, dbl, i64]),
         "pcpf_precondition": (st, [vp, i32]),
+        "pcpf_precond_info": (st, [vp, ctypes.POINTER(i32), ctypes.POINTER(dbl)]),
         "pcpf_residual": (st, [vp, vp, vp, dbl, i32, vp, vp]),
         "pcpf_get_sign": (st, [vp, vp]),
         "pcpf_sensor": (st, [vp, vp, vp]),

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <string>
 #include <vector>
 
@@ -317,6 +318,9 @@ struct pcpf_ctx {
     void* pc_store_psi0_v = nullptr;
     std::vector<void*> pc_store_stage_v;
     bool pc_reset_hit = false;
+    // the last preconditioning: iterations run, final stop-rule RMS (NaN: not computed)
+    int32_t pc_iters = -1;
+    double pc_rms = 0.0;
     AdjLaunchers<double> A64;
     AdjLaunchers<float> A32;
     std::string err = "no error";
@@ -411,6 +415,7 @@ GFArgs<R> gf_args(const Ctx<R>& C, const R* u0, const R* u1, double t) {
     a.axis = c->axis ? 1 : 0;
     a.mf = c->prm.precision == PCPF_BF16 ? 1 : 0;
     a.nphi = c->prm.normal_mode == PCPF_NORMAL_PHI ? 1 : 0;
+    a.sgn_current = c->prm.sgn_mode == PCPF_SGN_CURRENT ? 1 : 0;
     return a;
 }
 
@@ -529,6 +534,10 @@ constexpr double RK_C[4] = {0.0, 0.5, 0.5, 1.0};
 // checkpointed recompute of the adjoint), psi0 and the input of every pseudo stage are kept:
 // store_stage[4*k + s] receives the psi input of stage s of iteration k.
 template <typename R>
+pcpf_status reduce_impl(const Ctx<R>& C, int what, const void* d_field, const void* d_ref,
+                        double* out);
+
+template <typename R>
 pcpf_status precondition_impl(const Ctx<R>& C, int iters, R* store_psi0 = nullptr,
                               R* const* store_stage = nullptr) {
     pcpf_ctx* c = C.c;
@@ -549,8 +558,12 @@ pcpf_status precondition_impl(const Ctx<R>& C, int iters, R* store_psi0 = nullpt
         a.E = c->mi.E;
         C.Lk().trace(1, a, c->stream);
     }
-    // smeared sign
-    {
+    // smeared sign; under PCPF_SGN_CURRENT the stages form it from psi0 and their own
+    // gradient, so psi0 is kept in its place
+    if (c->prm.sgn_mode == PCPF_SGN_CURRENT) {
+        HIPCHK(c, hipMemcpyAsync(C.template at<R>(c->L.sgn), psi, bytes,
+                                 hipMemcpyDeviceToDevice, c->stream));
+    } else {
         GFArgs<R> a = gf_args<R>(C, phi, psi, c->t);
         psi_only(a);
         a.out = C.template at<R>(c->L.sgn);
@@ -558,8 +571,14 @@ pcpf_status precondition_impl(const Ctx<R>& C, int iters, R* store_psi0 = nullpt
     }
     c->has_sign = true;
     c->has_psi = true;
+    c->pc_iters = 0;
+    c->pc_rms = std::numeric_limits<double>::quiet_NaN();
     const double dtau = c->prm.dtau;
+    const bool rms_stop = c->prm.stop_mode == PCPF_STOP_RMS;
+    R* prev = C.plane(c->L.res, 0);          // psi^(k-1) for the stop rule
     for (int it = 0; it < iters; ++it) {
+        if (rms_stop)
+            HIPCHK(c, hipMemcpyAsync(prev, psi, bytes, hipMemcpyDeviceToDevice, c->stream));
         if (store_stage)
             HIPCHK(c, hipMemcpyAsync(store_stage[4 * it], psi, bytes, hipMemcpyDeviceToDevice,
                                      c->stream));
@@ -578,6 +597,14 @@ pcpf_status precondition_impl(const Ctx<R>& C, int iters, R* store_psi0 = nullpt
             u.bcoef = (R)RK_B[s];
             u.ccoef = (R)(s == 3 ? dtau : RK_C[s + 1] * dtau);
             TIMED(c, PCPF_KT_PC_UPDATE, C.Lk().update(UP_RK, 1, u, c->stream, ev0_, ev1_));
+        }
+        c->pc_iters = it + 1;
+        if (rms_stop) {
+            double ss = 0.0;
+            pcpf_status st = reduce_impl<R>(C, PCPF_REDUCE_RMS, psi, prev, &ss);
+            if (st != PCPF_OK) return st;
+            c->pc_rms = ss / dtau;
+            if (c->pc_rms <= 0.5) break;
         }
     }
     c->trace_ok[1] = true;   // written by the last update (or by the trace of psi0)
@@ -724,6 +751,7 @@ pcpf_status reduce_impl(const Ctx<R>& C, int what, const void* d_field, const vo
     if (st != PCPF_OK) return st;
     HIPCHK(c, hipMemcpyAsync(out, red, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (what == PCPF_REDUCE_RMS) *out = std::sqrt(*out / (double)total);
     return PCPF_OK;
 }
 
@@ -1110,8 +1138,10 @@ pcpf_status check_params(const pcpf_params* p, std::string* err) {
         return fail(err, PCPF_EINVAL, "eps_w must be > 0 for the LOGIT reset");
     if (p->normal_mode != PCPF_NORMAL_PSI && p->normal_mode != PCPF_NORMAL_PHI)
         return fail(err, PCPF_EINVAL, "unknown normal_mode");
-    if (p->reserved[0] || p->reserved[1])
-        return fail(err, PCPF_EINVAL, "reserved fields must be 0");
+    if (p->sgn_mode != PCPF_SGN_PSI0 && p->sgn_mode != PCPF_SGN_CURRENT)
+        return fail(err, PCPF_EINVAL, "unknown sgn_mode");
+    if (p->stop_mode != PCPF_STOP_FIXED && p->stop_mode != PCPF_STOP_RMS)
+        return fail(err, PCPF_EINVAL, "unknown stop_mode");
     return PCPF_OK;
 }
 
@@ -1257,6 +1287,14 @@ pcpf_status pcpf_precondition(pcpf_ctx* c, int32_t iters) {
     return collect_times(c);
 }
 
+pcpf_status pcpf_precond_info(const pcpf_ctx* c, int32_t* iters, double* rms) {
+    if (!c) return fail(nullptr, PCPF_EINVAL, "precond_info: NULL context");
+    if (c->pc_iters < 0) return PCPF_ESTATE;
+    if (iters) *iters = c->pc_iters;
+    if (rms) *rms = c->pc_rms;
+    return PCPF_OK;
+}
+
 pcpf_status pcpf_residual(pcpf_ctx* c, const void* d_phi, const void* d_psi, double t,
                           int32_t mode, void* d_rphi, void* d_rpsi) {
     if (check_ctx(c) != PCPF_OK) return PCPF_EINVAL;
@@ -1290,9 +1328,10 @@ pcpf_status pcpf_reduce(pcpf_ctx* c, int32_t what, const void* d_field, const vo
                         double* out) {
     if (check_ctx(c) != PCPF_OK) return PCPF_EINVAL;
     if (!out) return fail(&c->err, PCPF_EINVAL, "out is NULL");
-    if (what != PCPF_REDUCE_MASS && what != PCPF_REDUCE_L1)
+    if (what != PCPF_REDUCE_MASS && what != PCPF_REDUCE_L1 && what != PCPF_REDUCE_RMS)
         return fail(&c->err, PCPF_EINVAL, "unknown reduction");
-    if (what == PCPF_REDUCE_L1 && !d_ref) return fail(&c->err, PCPF_EINVAL, "L1 needs d_ref");
+    if (what != PCPF_REDUCE_MASS && !d_ref)
+        return fail(&c->err, PCPF_EINVAL, "L1 and RMS need d_ref");
     if (!d_field && !c->has_state) return fail(&c->err, PCPF_ESTATE, "no state set");
     return DISPATCH(c, reduce_impl, what, d_field, d_ref, out);
 }
@@ -1343,6 +1382,9 @@ pcpf_status pcpf_forward_ckpt(pcpf_ctx* c, double dt, int64_t nsteps, int64_t ev
         return fail(&c->err, PCPF_EUNSUPPORTED, "no adjoint of the PCPF_BF16 form");
     if (c->prm.normal_mode == PCPF_NORMAL_PHI)
         return fail(&c->err, PCPF_EUNSUPPORTED, "no adjoint of the PCPF_NORMAL_PHI form");
+    if (c->prm.sgn_mode != PCPF_SGN_PSI0 || c->prm.stop_mode != PCPF_STOP_FIXED)
+        return fail(&c->err, PCPF_EUNSUPPORTED,
+                    "the adjoint differentiates the PCPF_SGN_PSI0 sign with PCPF_STOP_FIXED");
     if (!c->has_state) return fail(&c->err, PCPF_ESTATE, "no state set");
     size_t need = 0;
     if (pcpf_ckpt_bytes(c, nsteps, every, &need) != PCPF_OK || !std::isfinite(dt))

@@ -107,6 +107,8 @@ struct GFArgs {
                          // arithmetic and velocity from per-element 1D sin/cos tables
     int mf;              // line operators on the matrix cores, bf16 operands (float only)
     int nphi;            // interface normal from phi (the unpreconditioned form)
+    int sgn_current;     // GF_PRECOND: sgn holds psi0 and the sign is tanh(psi0 / |grad psi|)
+                         // of the current stage
 };
 
 // update kernel kinds
@@ -149,7 +151,7 @@ struct RDArgs {
     const double* w64;   // 1D quadrature weights in float64
     double* partial;
     int64_t E;
-    int kind;            // 0 mass, 1 L1
+    int kind;            // 0 mass, 1 L1, 2 unweighted sum of (field - ref)^2
 };
 
 // Launch table of one (precision, d, p) instantiation.

@@ -475,7 +475,15 @@ void k_grad_flux(GFArgs<R> a) {
                 R g2 = R(0);
 #pragma unroll
                 for (int i = 0; i < D; ++i) g2 += q[0][i] * q[0][i];
-                Sdet = det * gld(a.sgn + e0 * NU, tid) * (R(1) - M::sqrt_(g2));
+                const R g = M::sqrt_(g2);
+                R sg = gld(a.sgn + e0 * NU, tid);
+                if (a.sgn_current) {
+                    // the printed smeared sign: psi0 over the current |grad psi|
+                    R gd = g;
+                    if (!(gd > a.ph.delta_g)) gd = a.ph.delta_g;
+                    sg = M::tanh_(sg / gd);
+                }
+                Sdet = det * sg * (R(1) - g);
 #pragma unroll
                 for (int k = 0; k < D; ++k) {
                     R acc;
@@ -955,6 +963,11 @@ __global__ __launch_bounds__(REDUCE_THREADS) void k_reduce(RDArgs<R> a) {
             r /= N;
         }
         double f = (double)a.field[idx];
+        if (a.kind == 2) {
+            const double df = f - (double)a.ref[idx];
+            acc += df * df;
+            continue;
+        }
         if (a.kind == 1) f = ::fabs(f - (double)a.ref[idx]);
         acc += a.det64[e] * W * f;
     }

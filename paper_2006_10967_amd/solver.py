@@ -16,7 +16,7 @@ from ._lib import PcpfMesh, PcpfParams, check
 
 FP64, FP32, BF16 = _lib.PCPF_FP64, _lib.PCPF_FP32, _lib.PCPF_BF16
 MODE_PHYS, MODE_PRECOND = _lib.PCPF_MODE_PHYS, _lib.PCPF_MODE_PRECOND
-REDUCE_MASS, REDUCE_L1 = _lib.PCPF_REDUCE_MASS, _lib.PCPF_REDUCE_L1
+REDUCE_MASS, REDUCE_L1, REDUCE_RMS = _lib.PCPF_REDUCE_MASS, _lib.PCPF_REDUCE_L1, _lib.PCPF_REDUCE_RMS
 
 _PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16, FP64: FP64, FP32: FP32, BF16: BF16}
 _DTYPES = {FP64: torch.float64, FP32: torch.float32, BF16: torch.float32}
@@ -83,6 +83,8 @@ def make_params(prm, precision) -> PcpfParams:
     c.precond_iters = int(prm.precond_iters)
     c.precision = _PRECISIONS[precision]
     c.normal_mode = int(getattr(prm, "normal_mode", 0))
+    c.sgn_mode = int(getattr(prm, "sgn_mode", 0))
+    c.stop_mode = int(getattr(prm, "stop_mode", 0))
     return c
 
 
@@ -172,6 +174,13 @@ class Solver:
     def precondition(self, iters=-1):
         self._chk(self.lib.pcpf_precondition(self.ctx, int(iters)))
 
+    def precond_info(self):
+        """(iterations, stop-rule RMS) of the last preconditioning."""
+        n = ctypes.c_int32()
+        r = ctypes.c_double()
+        self._chk(self.lib.pcpf_precond_info(self.ctx, ctypes.byref(n), ctypes.byref(r)))
+        return n.value, r.value
+
     def residual(self, phi, psi, t=0.0, mode=MODE_PHYS):
         phi_t = self._field(phi) if phi is not None else None
         psi_t = self._field(psi)
@@ -215,6 +224,9 @@ class Solver:
 
     def l1(self, ref, field=None) -> float:
         return self.reduce(REDUCE_L1, field, ref)
+
+    def rms(self, field, ref) -> float:
+        return self.reduce(REDUCE_RMS, field, ref)
 
     # -- adjoint ------------------------------------------------------------------------
     def set_velocity_amplitude(self, amp: float):

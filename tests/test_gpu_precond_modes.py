@@ -1,0 +1,162 @@
+"""GPU parity of the printed forms of the preconditioning step against the FP64 oracle:
+the smeared sign with the current |grad psi| (§2, text after Eq. lsequation) and the RMS
+stop rule of §3.2, and the RMS reduction of the C ABI.
+
+Bars: residuals and preconditioned psi 1e-12 relative L_inf; the stop rule takes the same
+number of iterations as the oracle (the cases keep the RMS of every iteration at least
+1e-3 away from the threshold 1/2, far beyond the rounding of either side) and reports the
+same RMS to 1e-10; trajectories 1e-10.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import Oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _solver(mesh, p, prm, precision="fp64"):
+    from paper_2006_10967_amd import Solver
+    return Solver.from_box(mesh, p, prm, precision=precision)
+
+
+def _rel(a, b):
+    a = a.detach().double().cpu()
+    den = float(b.abs().max())
+    return float((a - b).abs().max()) / (den if den > 0 else 1.0)
+
+
+CUR_CASES = [("2d_p3_uniform", 2, 3, (9, 7), dict(vel_u0=(1.0, 0.5))),
+             ("2d_p4_copybc_perturbed", 2, 4, (6, 5), dict(periodic=False, perturb=0.2)),
+             ("3d_p3_ragged", 3, 3, (5, 4, 3), dict()),
+             ("3d_p2_copybc", 3, 2, (3, 4, 5), dict(periodic=False))]
+
+
+@pytest.mark.parametrize("cid,d,p,shape,kw", CUR_CASES, ids=[c[0] for c in CUR_CASES])
+def test_current_sign_precond_residual_parity(cid, d, p, shape, kw):
+    mesh, prm = W.small_case(d, p, shape, **kw)
+    prm = dataclasses.replace(prm, sgn_mode=W.SGN_CURRENT)
+    o = Oracle(d, p, mesh, prm)
+    s = _solver(mesh, p, prm)
+    rng = np.random.default_rng(17)
+    x = o.coords()
+    c = 0.5 + rng.uniform(-0.1, 0.1, d)
+    phi = torch.tensor(W.ic_phi(x, c, 0.27, 0.04))
+    s.set_state(phi)
+    s.precondition(0)
+    psi0 = o.reset_psi(phi)
+    # the stored field is psi0 itself, bit for bit
+    assert torch.equal(s.sign().cpu(), psi0)
+    for amp in (0.0, 1e-3, 1e-1):
+        field = psi0 + amp * torch.tensor(rng.standard_normal(psi0.shape))
+        R = o.precond_residual(field, None, psi0)
+        _, gR = s.residual(None, field, 0.0, mode=1)
+        assert _rel(gR, R) <= TOL, (cid, amp, _rel(gR, R))
+
+
+RMS_CASES = [
+    # (id, d, p, shape, eps_w of the IC, sign mode): stop after 3, 11, 10 and 8 iterations
+    ("2d_p3_psi0", 2, 3, (6, 6), 0.05, W.SGN_PSI0),
+    ("2d_p3_current", 2, 3, (6, 6), 0.04, W.SGN_CURRENT),
+    ("3d_p2_psi0", 3, 2, (4, 4, 4), 0.06, W.SGN_PSI0),
+    ("3d_p2_current", 3, 2, (4, 4, 4), 0.06, W.SGN_CURRENT),
+]
+
+
+@pytest.mark.parametrize("cid,d,p,shape,ew,sgn", RMS_CASES, ids=[c[0] for c in RMS_CASES])
+def test_rms_stop_rule_parity(cid, d, p, shape, ew, sgn):
+    mesh, prm = W.small_case(d, p, shape, periodic=True)
+    prm = dataclasses.replace(prm, stop_mode=W.STOP_RMS, precond_iters=20, sgn_mode=sgn)
+    o = Oracle(d, p, mesh, prm)
+    s = _solver(mesh, p, prm)
+    phi = torch.tensor(W.ic_phi(o.coords(), (0.5,) * d, 0.3, ew))
+    psi_o, _ = o.precondition(phi)
+    s.set_state(phi)
+    s.precondition()
+    k, rms = s.precond_info()
+    _, psi_g, _, _ = s.get_state()
+    print(f"[precond] {cid}: {k} iterations (oracle {o.last_iters}), RMS {rms:.6f} "
+          f"(oracle {o.last_rms:.6f}), psi {_rel(psi_g, psi_o):.2e}")
+    assert 1 < o.last_iters < 20
+    assert k == o.last_iters
+    assert abs(rms - o.last_rms) <= 1e-10 * o.last_rms
+    assert _rel(psi_g, psi_o) <= TOL
+
+
+def test_rms_stop_rule_reaches_the_cap():
+    """On the 16x16 p = 3 advection workload the RMS stays near 0.93 (the far field has
+    |grad psi0| ~ 0 and a source of magnitude 1): the rule runs to its cap."""
+    cfg = W.config("C1")
+    prm = dataclasses.replace(cfg.params, stop_mode=W.STOP_RMS, precond_iters=20)
+    mesh = cfg.mesh()
+    o = Oracle(2, 3, mesh, prm)
+    s = _solver(mesh, 3, prm)
+    phi = torch.tensor(W.ic_phi(o.coords(), cfg.centre, cfg.radius, prm.eps_w))
+    psi_o, _ = o.precondition(phi)
+    s.set_state(phi)
+    s.precondition()
+    k, rms = s.precond_info()
+    assert k == o.last_iters == 20
+    assert abs(rms - o.last_rms) <= 1e-10 * o.last_rms
+    assert _rel(s.get_state()[1], psi_o) <= TOL
+
+
+def test_fixed_mode_reports_iterations_without_rms():
+    from paper_2006_10967_amd import PcpfError
+    mesh, prm = W.small_case(2, 3, (4, 4))
+    s = _solver(mesh, 3, prm)
+    with pytest.raises(PcpfError) as ei:
+        s.precond_info()
+    assert ei.value.status == 4
+    s.set_state(torch.full((16, 16), 0.25, dtype=torch.float64))
+    s.precondition(3)
+    k, rms = s.precond_info()
+    assert k == 3 and np.isnan(rms)
+
+
+def test_rms_reduction():
+    mesh, prm = W.small_case(3, 3, (5, 4, 3))
+    s = _solver(mesh, 3, prm)
+    rng = np.random.default_rng(23)
+    a = torch.tensor(rng.standard_normal((60, 64)))
+    b = torch.tensor(rng.standard_normal((60, 64)))
+    want = float(np.sqrt(np.mean((a.numpy() - b.numpy()) ** 2)))
+    assert abs(s.rms(a, b) - want) <= 1e-14 * want
+    assert s.rms(a, a) == 0.0
+
+
+def test_printed_forms_trajectory_parity():
+    """Printed sign and RMS stop rule together over 120 steps with resets every 50."""
+    mesh, prm = W.small_case(2, 3, (6, 6), periodic=True, vel_u0=(0.8, -0.3))
+    prm = dataclasses.replace(prm, sgn_mode=W.SGN_CURRENT, stop_mode=W.STOP_RMS,
+                              precond_iters=20, reset_every=50)
+    o = Oracle(2, 3, mesh, prm)
+    s = _solver(mesh, 3, prm)
+    phi0 = torch.tensor(W.ic_phi(o.coords(), (0.5, 0.5), 0.3, 0.04))
+    dt = 0.1 / 6 / 0.85
+    phi_o, psi_o, _ = o.run(phi0, None, 0.0, dt, 120)
+    s.set_state(phi0)
+    s.step(dt, 120)
+    phi_g, psi_g, _, n = s.get_state()
+    print(f"[precond] printed forms, 120 steps: phi {_rel(phi_g, phi_o):.2e}, "
+          f"psi {_rel(psi_g, psi_o):.2e}, last preconditioning {s.precond_info()} "
+          f"(oracle {o.last_iters})")
+    assert n == 120 and s.precond_info()[0] == o.last_iters
+    assert _rel(phi_g, phi_o) <= 1e-10 and _rel(psi_g, psi_o) <= 1e-10
+
+
+@pytest.mark.parametrize("over", [dict(sgn_mode=W.SGN_CURRENT), dict(stop_mode=W.STOP_RMS)])
+def test_adjoint_refuses_printed_forms(over):
+    from paper_2006_10967_amd import PcpfError
+    mesh, prm = W.small_case(2, 3, (4, 4))
+    s = _solver(mesh, 3, dataclasses.replace(prm, **over))
+    s.set_state(torch.full((16, 16), 0.25, dtype=torch.float64))
+    with pytest.raises(PcpfError) as ei:
+        s.forward_ckpt(1e-3, 4, 2)
+    assert ei.value.status == 3
