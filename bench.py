@@ -140,7 +140,42 @@ def cpu_baseline(cfg, mesh, phi0_np, nsteps):
             "sample": f"full {cfg.n}x{cfg.n} p={cfg.order} mesh: {nsteps} RK4 steps "
                       f"({t_steps:.1f} s) after one reset + {cfg.params.precond_iters} "
                       f"pseudo iterations ({t_pc:.1f} s, not in value)",
-            "s_per_step": t_steps / nsteps}
+            "s_per_step": t_steps / nsteps,
+            "small_workload_full_run": small_workload_run()}
+
+
+def small_workload_run():
+    """The 16x16 p=3 advection workload run whole (reset + 10 pseudo iterations + 200 RK4
+    steps) by the FP64 oracle on the host cores and by the FP64 GPU path: seconds of
+    each, the mass error of each and the largest relative difference of the final phi."""
+    import torch
+    import workloads as W
+    from oracle import Oracle
+    from paper_2006_10967_amd import Solver
+    cfg = W.config("C1")
+    mesh = cfg.mesh()
+    dt = cfg.dt(mesh)
+    o = Oracle(cfg.ndims, cfg.order, mesh, cfg.params)
+    phi0 = torch.as_tensor(cfg.initial_phi(o.coords()), dtype=torch.float64)
+    t0 = time.perf_counter()
+    phi_o, _, _ = o.run(phi0, None, 0.0, dt, cfg.steps)
+    t_oracle = time.perf_counter() - t0
+    s = Solver.from_box(mesh, cfg.order, cfg.params, precision="fp64", device="cuda:0")
+    g0 = phi0.to("cuda:0")
+    s.set_state(g0)
+    s.step(dt, 5)                                   # warm-up (module load, first launches)
+    s.set_state(g0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(dt, cfg.steps)
+    torch.cuda.synchronize()
+    t_gpu = time.perf_counter() - t0
+    phi_g = s.get_state(want_psi=False)[0].cpu()
+    m0 = float(o.mass(phi0))
+    return {"workload": cfg.name, "steps": cfg.steps, "oracle_s": t_oracle, "gpu_s": t_gpu,
+            "E_m_oracle": float(o.mass_error(phi_o, phi0, phi0)),
+            "E_m_gpu": (s.mass() - m0) / m0,
+            "phi_rel_diff": float((phi_g - phi_o).abs().max() / phi_o.abs().max())}
 
 
 def adjoint_leg(precision, steps, every):
@@ -193,7 +228,9 @@ def accuracy_leg(cfg, mesh, phi0_np):
     T = cfg.params.vel_period
     dt = cfg.dt(mesh)
     nsteps = int(round(T / dt))
-    out = {"t_end": nsteps * dt, "steps": nsteps}
+    with open(os.path.join(ROOT, "tests", "golden", "paper_parameters.json")) as fh:
+        paper = json.load(fh)["vortex_E_L1"][f"p{cfg.order}"][2] if cfg.n == 128 else None
+    out = {"t_end": nsteps * dt, "steps": nsteps, "E_L1_paper": paper}
     ref = None
     for name, prm in precond_variants(cfg.params):
         s = Solver.from_box(mesh, cfg.order, prm, precision="fp64", device="cuda:0")
@@ -236,6 +273,40 @@ def accuracy_leg(cfg, mesh, phi0_np):
             f"int|phi-phi64| = {diff:.2e}, equal: {r['equal_interface_error']}, "
             f"x{r['speedup_vs_fp64']:.2f}")
         del s
+    return out
+
+
+def deformation_leg():
+    """The LeVeque deformation test on 64^3 hexes, p = 3, run to t = T = 3 (§4.3), FP64:
+    E_L1 = int|phi(T) - phi(0)| and E_m with the default readings and with the longer
+    preconditioning, next to the paper's E_L1 for this mesh and order (context)."""
+    import torch
+    import workloads as W
+    from paper_2006_10967_amd import Solver
+    cfg = W.config("C3")
+    mesh = cfg.mesh()
+    dt = cfg.dt(mesh)
+    nsteps = int(round(cfg.params.vel_period / dt))
+    with open(os.path.join(ROOT, "tests", "golden", "paper_parameters.json")) as fh:
+        paper = json.load(fh)["leveque_E_L1"]["p3"][1]
+    out = {"workload": cfg.name, "t_end": nsteps * dt, "steps": nsteps, "E_L1_paper": paper}
+    for name, prm in precond_variants(cfg.params)[::2]:
+        s = Solver.from_box(mesh, cfg.order, prm, precision="fp64", device="cuda:0")
+        phi0 = torch.as_tensor(cfg.initial_phi(s.solution_coords())).to("cuda:0", s.dtype)
+        s.set_state(phi0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(dt, nsteps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        m0 = s.mass(phi0)
+        e_l1 = s.l1(phi0)
+        out[name] = {"E_L1": e_l1, "E_m": (s.mass() - m0) / m0, "wall_s": wall,
+                     "dof_stage_per_s": cfg.dof * 4 * nsteps / wall}
+        log(f"[bench] {cfg.name} to t = T ({name}): E_L1 = {e_l1:.4e} (paper {paper:.2e}), "
+            f"E_m = {out[name]['E_m']:.1e}, {wall:.1f} s")
+        del s, phi0
+        torch.cuda.empty_cache()
     return out
 
 
@@ -316,12 +387,14 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-bf16", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=60)
+    ap.add_argument("--cpu-steps", type=int, default=200)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the run to t = T of the vortex workload (both normal forms)")
     ap.add_argument("--no-rotation", action="store_true",
                     help="skip the slotted-disc rotation tests (Zalesak, Rudman; one turn each)")
+    ap.add_argument("--deformation", action="store_true",
+                    help="also run the 64^3 p=3 LeVeque test to t = T (about a minute)")
     ap.add_argument("--adj-steps", type=int, default=512)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
@@ -421,6 +494,9 @@ def main():
 
     if not args.no_rotation:
         out["rotation"] = rotation_leg()
+
+    if args.deformation:
+        out["deformation"] = deformation_leg()
 
     if not args.no_adjoint:
         adj = {}
