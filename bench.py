@@ -314,9 +314,10 @@ def last_precond(s):
     """[iterations, stop-rule RMS] of the solver's last preconditioning (None if none ran)."""
     from paper_2006_10967_amd import PcpfError
     try:
-        return list(s.precond_info())
+        k, rms = s.precond_info()
     except PcpfError:
         return None
+    return [k, rms if math.isfinite(rms) else None]
 
 
 def precond_variants(prm):
