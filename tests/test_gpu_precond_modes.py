@@ -129,6 +129,11 @@ def test_rms_reduction():
     want = float(np.sqrt(np.mean((a.numpy() - b.numpy()) ** 2)))
     assert abs(s.rms(a, b) - want) <= 1e-14 * want
     assert s.rms(a, a) == 0.0
+    from paper_2006_10967_amd import REDUCE_RMS, PcpfError
+    for what, ref in ((REDUCE_RMS, None), (7, b)):
+        with pytest.raises(PcpfError) as ei:
+            s.reduce(what, a, ref)
+        assert ei.value.status == 1
 
 
 def test_printed_forms_trajectory_parity():

@@ -111,6 +111,17 @@ def test_create_rejects_invalid_input_before_device_work():
     bad.precision = 7
     st, _ = _create_status(MeshArgs(2, 3, mesh.x0, mesh.jac, mesh.nbr, _period(mesh)), bad)
     assert st == _lib.PCPF_EUNSUPPORTED
+    # unknown sign and stop modes
+    for field in ("sgn_mode", "stop_mode", "normal_mode"):
+        bad = make_params(prm, "fp64")
+        setattr(bad, field, 2)
+        st, msg = _create_status(MeshArgs(2, 3, mesh.x0, mesh.jac, mesh.nbr, _period(mesh)), bad)
+        assert st == _lib.PCPF_EINVAL and field in msg, (field, msg)
+    # an empty mesh
+    m0 = MeshArgs(2, 3, mesh.x0, mesh.jac, mesh.nbr, _period(mesh))
+    m0.c.nelem = 0
+    st, msg = _create_status(m0, good)
+    assert st == _lib.PCPF_EINVAL and "nelem" in msg
     # workspace too small / misaligned
     st, _ = _create_status(MeshArgs(2, 3, mesh.x0, mesh.jac, mesh.nbr, _period(mesh)), good, nbytes=16)
     assert st == _lib.PCPF_EINVAL
