@@ -1289,7 +1289,7 @@ pcpf_status pcpf_precondition(pcpf_ctx* c, int32_t iters) {
 
 pcpf_status pcpf_precond_info(const pcpf_ctx* c, int32_t* iters, double* rms) {
     if (!c) return fail(nullptr, PCPF_EINVAL, "precond_info: NULL context");
-    if (c->pc_iters < 0) return PCPF_ESTATE;
+    if (c->pc_iters < 0) return fail(nullptr, PCPF_ESTATE, "no preconditioning has run");
     if (iters) *iters = c->pc_iters;
     if (rms) *rms = c->pc_rms;
     return PCPF_OK;
