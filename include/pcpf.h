@@ -187,7 +187,9 @@ pcpf_status pcpf_get_state(pcpf_ctx* ctx, void* d_phi, void* d_psi, double* t,
 /* Advance nsteps classic RK4 steps of size dt (§3.1 last paragraph), with the reset +
  * preconditioning of §2/§3.2 before each step whose index is a multiple of reset_every.
  * Synchronises the stream once at the end to read the non-finite flag: ENONFINITE if any
- * value became NaN/Inf or |phi| > 10 (the state is kept for inspection). */
+ * value became NaN/Inf or |phi| > 10 (the state is kept for inspection). Under
+ * PCPF_STOP_RMS each pseudo-time iteration of a reset also reads its RMS back (one
+ * synchronisation per iteration). */
 pcpf_status pcpf_step(pcpf_ctx* ctx, double dt, int64_t nsteps);
 
 /* Reset psi from the current phi (psi0 = phi - 1/2, or eps_w ln(phi/(1-phi)) with the
