@@ -43,6 +43,25 @@ __device__ __forceinline__ void gst(T* base, uint32_t i, T v) {
     *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (uint32_t)sizeof(T)) = v;
 }
 
+// Element chunk of this block. Consecutive workgroups are placed round-robin on the 8
+// XCDs. When a state plane is small enough for the chunks of one XCD to stay in its L2 and
+// the shared cache between launches (at most 24 MiB; measured on the 2D and 3D meshes
+// from 65 k to 7 M points), the chunks are renumbered so that each XCD takes one
+// contiguous range: the faces its elements share (traces and fluxes pushed between
+// neighbours) and the registers one launch writes and the next reads then stay with that
+// XCD. Larger planes keep the plain order, whose concurrent blocks sweep one address
+// window. Either way a permutation: every chunk is processed exactly once.
+constexpr int64_t XCD_MAP_MAX_PLANE_BYTES = int64_t(24) << 20;
+
+template <typename R>
+__device__ __forceinline__ uint32_t block_chunk(int64_t points_per_plane) {
+    const uint32_t b = blockIdx.x;
+    if (points_per_plane * (int64_t)sizeof(R) > XCD_MAP_MAX_PLANE_BYTES) return b;
+    constexpr uint32_t X = 8;
+    const uint32_t g = gridDim.x, x = b % X, q = g / X, r = g % X;
+    return x * q + (x < r ? x : r) + b / X;
+}
+
 template <int N>
 __device__ __forceinline__ constexpr int st(int k) {
     return k == 0 ? 1 : (k == 1 ? N : N * N);

@@ -97,7 +97,7 @@ void k_grad_flux(GFArgs<R> a) {
     __shared__ R s_tr[MF ? V * D * EPB * NFA : 1];       // own + face traces (MF)
 
     const int tid = threadIdx.x;
-    const int64_t e0 = (int64_t)blockIdx.x * EPB;
+    const int64_t e0 = (int64_t)block_chunk<R>(a.E * NU) * EPB;
     const int nel = (int)((a.E - e0) < EPB ? (a.E - e0) : EPB);
     const bool pt = tid < nel * NU;
     const int le = tid / NU;
@@ -789,7 +789,7 @@ __global__ __launch_bounds__((Shape<D, P>::NT)) void k_update(UPArgs<R> a) {
     __shared__ R s_u[V][KIND == UP_RK ? EPB * NU : 1];
 
     const int tid = threadIdx.x;
-    const int64_t e0 = (int64_t)blockIdx.x * EPB;
+    const int64_t e0 = (int64_t)block_chunk<R>(a.E * NU) * EPB;
     const int nel = (int)((a.E - e0) < EPB ? (a.E - e0) : EPB);
     const bool pt = tid < nel * NU;
     const int le = tid / NU;
@@ -906,7 +906,7 @@ __global__ __launch_bounds__((Shape<D, P>::NT)) void k_trace(TRArgs<R> a) {
     __shared__ R s_lm[N];
     __shared__ R s_u[V][EPB * NU];
     const int tid = threadIdx.x;
-    const int64_t e0 = (int64_t)blockIdx.x * EPB;
+    const int64_t e0 = (int64_t)block_chunk<R>(a.E * NU) * EPB;
     const int nel = (int)((a.E - e0) < EPB ? (a.E - e0) : EPB);
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
