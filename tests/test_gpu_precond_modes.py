@@ -165,3 +165,25 @@ def test_adjoint_refuses_printed_forms(over):
     with pytest.raises(PcpfError) as ei:
         s.forward_ckpt(1e-3, 4, 2)
     assert ei.value.status == 3
+
+
+@pytest.mark.parametrize("cid,d,p,shape,ew,sgn", RMS_CASES[::2], ids=[c[0] for c in RMS_CASES[::2]])
+def test_rms_stop_rule_fp32(cid, d, p, shape, ew, sgn):
+    """The FP32 form takes the same decisions: its RMS differs from the FP64 oracle's by
+    the FP32 residual error (~1e-5 relative), far below the >= 1e-3 margins of these cases;
+    psi then agrees to the FP32 residual bar of the precision tests (2e-4)."""
+    mesh, prm = W.small_case(d, p, shape, periodic=True)
+    prm = dataclasses.replace(prm, stop_mode=W.STOP_RMS, precond_iters=20, sgn_mode=sgn)
+    o = Oracle(d, p, mesh, prm)
+    s = _solver(mesh, p, prm, precision="fp32")
+    phi = torch.tensor(W.ic_phi(o.coords(), (0.5,) * d, 0.3, ew))
+    psi_o, _ = o.precondition(phi)
+    s.set_state(phi.float())
+    s.precondition()
+    k, rms = s.precond_info()
+    _, psi_g, _, _ = s.get_state()
+    print(f"[precond] {cid} fp32: {k} iterations (oracle {o.last_iters}), RMS {rms:.6f}, "
+          f"psi {_rel(psi_g, psi_o):.2e}")
+    assert k == o.last_iters
+    assert abs(rms - o.last_rms) <= 1e-4 * o.last_rms
+    assert _rel(psi_g, psi_o) <= 2e-4
