@@ -697,19 +697,48 @@ void k_grad_flux(GFArgs<R> a) {
                     gst(a.P[v] + e0 * NU, tid, acc);
                 }
             }
-        } else if (pt) {
-            const R* DH = &s_ops[op_dh(N)];
+        } else {
+            // volume divergence of block point t (thread-point numbering)
+            auto e_point = [&](int t) {
+                const int l = t / NU, q = t - l * NU;
+                int m[D];
+                {
+                    int r = q;
 #pragma unroll
-            for (int v = 0; v < V; ++v) {
-                R acc = R(0);
-#pragma unroll
-                for (int k = 0; k < D; ++k) {
-                    const int b0 = le * NU + ip - mi[k] * st<N>(k);
-#pragma unroll
-                    for (int b = 0; b < N; ++b) acc += DH[mi[k] * N + b] * s_f[(v * D + k) * XST + b0 + b * st<N>(k)];
+                    for (int k = 0; k < D; ++k) {
+                        m[k] = r % N;
+                        r /= N;
+                    }
                 }
-                if constexpr (MODE == GF_PRECOND) acc -= Sdet;
-                gst(a.P[v] + e0 * NU, tid, acc);
+                const R* DH = &s_ops[op_dh(N)];
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    R acc = R(0);
+#pragma unroll
+                    for (int k = 0; k < D; ++k) {
+                        const int b0 = l * NU + q - m[k] * st<N>(k);
+#pragma unroll
+                        for (int b = 0; b < N; ++b)
+                            acc += DH[m[k] * N + b] * s_f[(v * D + k) * XST + b0 + b * st<N>(k)];
+                    }
+                    if constexpr (MODE == GF_PRECOND) acc -= Sdet;
+                    gst(a.P[v] + e0 * NU, t, acc);
+                }
+            };
+            // Physical mode with at most half of the waves carrying face units: the waves
+            // without one also take the divergence of the points of a wave with one, so
+            // that the face work and the divergence are spread over all the block's waves.
+            constexpr bool SHARE = MODE == GF_PHYS && 2 * S::NUNITS <= S::NW;
+            if constexpr (SHARE) {
+                if (wave >= S::NUNITS) {
+                    if (pt) e_point(tid);
+                    if (wave < 2 * S::NUNITS) {
+                        const int t2 = tid - 64 * S::NUNITS;
+                        if (t2 < nel * NU) e_point(t2);
+                    }
+                }
+            } else if (pt) {
+                e_point(tid);
             }
         }
     }
