@@ -395,6 +395,23 @@ def rudman(order: int, n: int = 200) -> Config:
                               "one rotation")
 
 
+def vortex(n: int, order: int) -> Config:
+    """The time-reversing single vortex of §4.2 on n x n quads (T = 8, circle r = 0.15 at
+    (0.5, 0.75)), run to t = T; CFL 0.05 (0.03 for p = 5) on |v|max = 1."""
+    h = 1.0 / n
+    prm = default_params(2, order, h, vel_kind=VEL_SINGLE_VORTEX, vel_period=8.0)
+    cfl = ROTATION_CFL.get(order, 0.03)
+    steps = int(math.ceil(8.0 / (cfl * h)))
+    return Config(f"vortex2d_{n}x{n}_p{order}", 2, order, n, centre=(0.5, 0.75), cfl=cfl,
+                  steps=steps, params=prm, vmax=1.0,
+                  description=f"single vortex T=8, {n}x{n} quads, p={order}, to t = T")
+
+
+def vortex_dt(cfg: Config) -> float:
+    """The step of a vortex run: t = T = 8 in cfg.steps steps."""
+    return cfg.params.vel_period / cfg.steps
+
+
 def rotation_dt(cfg: Config) -> float:
     """The step of a rotation workload: one turn (t = 2 pi) in cfg.steps steps."""
     return 2.0 * math.pi / cfg.steps
