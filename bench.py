@@ -341,6 +341,40 @@ def vortex_table_leg(sizes=(32, 64, 128), orders=(2, 3, 4, 5)):
     return out
 
 
+def leveque_table_leg(sizes=(32,), orders=(2, 3, 4, 5)):
+    """The LeVeque deformation test of §4.3 to t = T on n^3 hexes (FP64), default readings
+    and the longer preconditioning, next to the paper's E_L1 (context)."""
+    import torch
+    import workloads as W
+    from paper_2006_10967_amd import Solver
+    with open(os.path.join(ROOT, "tests", "golden", "paper_parameters.json")) as fh:
+        gold = json.load(fh)["leveque_E_L1"]
+    out = {}
+    for n in sizes:
+        col = {32: 0, 64: 1, 128: 2}[n]
+        for p in orders:
+            cfg = W.leveque(n, p)
+            mesh = cfg.mesh()
+            dt = W.vortex_dt(cfg)
+            res = {"steps": cfg.steps, "E_L1_paper": gold[f"p{p}"][col]}
+            for name, prm in precond_variants(cfg.params)[::2]:
+                s = Solver.from_box(mesh, p, prm, precision="fp64", device="cuda:0")
+                phi0 = torch.as_tensor(cfg.initial_phi(s.solution_coords())).to("cuda:0", s.dtype)
+                s.set_state(phi0)
+                t0 = time.perf_counter()
+                s.step(dt, cfg.steps)
+                torch.cuda.synchronize()
+                m0 = s.mass(phi0)
+                res[name] = {"E_L1": s.l1(phi0), "E_m": (s.mass() - m0) / m0,
+                             "wall_s": time.perf_counter() - t0}
+                del s
+            out[cfg.name] = res
+            log(f"[bench] {cfg.name} to t = T: E_L1 {res['preconditioned']['E_L1']:.3e} "
+                f"(K20: {res['preconditioned_K20_dtau2x_N500']['E_L1']:.3e}; "
+                f"paper {res['E_L1_paper']:.2e})")
+    return out
+
+
 def last_precond(s):
     """[iterations, stop-rule RMS] of the solver's last preconditioning (None if none ran)."""
     from paper_2006_10967_amd import PcpfError
@@ -439,6 +473,8 @@ def main():
                     help="also run the 64^3 p=3 LeVeque test to t = T (about a minute)")
     ap.add_argument("--vortex-table", action="store_true",
                     help="also run the single vortex to t = T on 32^2..128^2, p = 2..5")
+    ap.add_argument("--leveque-table", action="store_true",
+                    help="also run the 3D deformation to t = T on 32^3, p = 2..5")
     ap.add_argument("--adj-steps", type=int, default=512)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
@@ -544,6 +580,9 @@ def main():
 
     if args.vortex_table:
         out["vortex_table"] = vortex_table_leg()
+
+    if args.leveque_table:
+        out["leveque_table"] = leveque_table_leg()
 
     if not args.no_adjoint:
         adj = {}

@@ -407,8 +407,24 @@ def vortex(n: int, order: int) -> Config:
                   description=f"single vortex T=8, {n}x{n} quads, p={order}, to t = T")
 
 
+LEVEQUE_CFL = {2: 0.05, 3: 0.05, 4: 0.03, 5: 0.02}
+
+
+def leveque(n: int, order: int) -> Config:
+    """The LeVeque 3D deformation test of §4.3 on n^3 hexes (T = 3, sphere r = 0.15 at
+    (0.35, 0.35, 0.35)), run to t = T; CFL 0.05 / 0.05 / 0.03 / 0.02 for p = 2..5 on
+    |v|max = 2."""
+    h = 1.0 / n
+    prm = default_params(3, order, h, vel_kind=VEL_LEVEQUE3D, vel_period=3.0)
+    cfl = LEVEQUE_CFL.get(order, 0.02)
+    steps = int(math.ceil(3.0 / (cfl * h / 2.0)))
+    return Config(f"deform3d_{n}cube_p{order}", 3, order, n, centre=(0.35, 0.35, 0.35),
+                  cfl=cfl, steps=steps, params=prm, vmax=2.0,
+                  description=f"LeVeque deformation T=3, {n}^3 hexes, p={order}, to t = T")
+
+
 def vortex_dt(cfg: Config) -> float:
-    """The step of a vortex run: t = T = 8 in cfg.steps steps."""
+    """The step of a run to t = T (vortex or deformation) in cfg.steps steps."""
     return cfg.params.vel_period / cfg.steps
 
 
