@@ -438,6 +438,26 @@ def rotation_leg(orders=(2, 3, 4, 5)):
                 f"(paper {paper:.2e}), E_m = {res[name]['E_m']:.1e}, {wall:.2f} s")
             del s
         out[cfg.name] = res
+    # long-time behaviour (§4.1, the slot corners over several turns): Zalesak 100^2 p4,
+    # E_r after each of four turns
+    cfg = W.zalesak(100, 4)
+    mesh = cfg.mesh()
+    dt = W.rotation_dt(cfg)
+    multi = {}
+    for name, prm in precond_variants(cfg.params)[::2]:
+        s = Solver.from_box(mesh, cfg.order, prm, precision="fp64", device="cuda:0")
+        phi0 = torch.as_tensor(cfg.initial_phi(s.solution_coords())).to("cuda:0", s.dtype)
+        s.set_state(phi0)
+        m0 = s.mass(phi0)
+        per_turn = []
+        for _ in range(4):
+            s.step(dt, cfg.steps)
+            per_turn.append({"E_r": s.l1(phi0) / m0, "E_m": (s.mass() - m0) / m0})
+        multi[name] = per_turn
+        log(f"[bench] {cfg.name} four turns ({name}): E_r "
+            + " ".join(f"{x['E_r']:.3e}" for x in per_turn))
+        del s
+    out["zalesak2d_100x100_p4_four_turns"] = multi
     return out
 
 
