@@ -158,12 +158,14 @@ void k_grad_flux(GFArgs<R> a) {
             r_det = gld(gb, el * G + D + 2 * D * D);
         }
     }
-    // velocity-table inputs: x0_k, J_kk and the reference position of each table entry
+    // velocity-table inputs: x0_k, J_kk and the reference position of each table entry.
+    // Entries are taken from the last wave down: the face units of phase C sit in the
+    // first waves, so the sin/cos work lands on the waves that have no face unit.
     R r_tx[I_TB];
     if constexpr (TAB) {
 #pragma unroll
         for (int j = 0; j < I_TB; ++j) {
-            const int it = tid + j * NT;
+            const int it = (NT - 1 - tid) + j * NT;
             r_tx[j] = R(0);
             if (trig && it < nel * D * NTB) {
                 const int el = it / (D * NTB), r = it - el * (D * NTB), k = r / NTB, jj = r - k * NTB;
@@ -224,7 +226,7 @@ void k_grad_flux(GFArgs<R> a) {
         if (trig) {
 #pragma unroll
             for (int j = 0; j < I_TB; ++j) {
-                const int it = tid + j * NT;
+                const int it = (NT - 1 - tid) + j * NT;
                 if (it < nel * D * NTB) {
                     R sn, cs;
                     M::sincospi_(r_tx[j], &sn, &cs);
