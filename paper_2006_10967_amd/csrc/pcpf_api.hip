@@ -253,7 +253,7 @@ pcpf_status check_geometry(const pcpf_mesh* m, const MeshInfo& mi, std::string* 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t un, us, acc, P, Fp, Fm, Tp, sgn, geo, det64, w64, nbr, ops, flag, partial, red, res;
+    size_t un, us, acc, P, Fp, Fm, Tp, sgn, geo, vtab, det64, w64, nbr, ops, flag, partial, red, res;
     size_t total;
 };
 
@@ -279,6 +279,7 @@ Layout layout(const MeshInfo& mi, int precision) {
     L.Tp = take(face);
     L.sgn = take(E * mi.nu * r);
     L.geo = take(E * geo * r);
+    L.vtab = take(E * mi.d * (mi.n + 2) * 2 * r);   // velocity tables (axis-aligned meshes)
     L.det64 = take(E * 8);
     L.w64 = take(mi.n * 8);
     L.nbr = take(E * 2 * mi.d * 4);
@@ -409,6 +410,7 @@ GFArgs<R> gf_args(const Ctx<R>& C, const R* u0, const R* u1, double t) {
     a.nbr = C.template at<int32_t>(c->L.nbr);
     a.ops = C.template at<R>(c->L.ops);
     a.sgn = C.template at<R>(c->L.sgn);
+    a.vtab = C.template at<R>(c->L.vtab);
     a.out = nullptr;
     a.E = c->mi.E;
     a.ph = phys<R>(c->prm, t);
@@ -755,6 +757,10 @@ pcpf_status reduce_impl(const Ctx<R>& C, int what, const void* d_field, const vo
     return PCPF_OK;
 }
 
+// sin(pi x) and cos(pi x) on the host: x reduced exactly to [-1, 1], then sin / cos
+double sinpi_host(double x) { return std::sin(M_PI * (x - 2.0 * std::nearbyint(0.5 * x))); }
+double cospi_host(double x) { return std::cos(M_PI * (x - 2.0 * std::nearbyint(0.5 * x))); }
+
 template <typename R>
 pcpf_status upload(pcpf_ctx* c, const pcpf_mesh* m) {
     const MeshInfo& mi = c->mi;
@@ -795,9 +801,26 @@ pcpf_status upload(pcpf_ctx* c, const pcpf_mesh* m) {
         ops[op_xi(n) + a] = (R)m->nodes[a];
         ops[op_w(n) + a] = (R)m->weights[a];
     }
+    // sin and cos of pi x_k at the n nodes and at both ends (xi = -1, +1) of every element
+    // axis, for the trigonometric velocity fields on axis-aligned meshes (time-independent)
+    const int ntb = n + 2;
+    const bool trig = c->prm.vel_kind == PCPF_VEL_SINGLE_VORTEX || c->prm.vel_kind == PCPF_VEL_LEVEQUE3D;
+    std::vector<R> vtab(trig ? (size_t)E * d * ntb * 2 : 0);
+    for (int64_t e = 0; trig && e < E; ++e)
+        for (int k = 0; k < d; ++k)
+            for (int j = 0; j < ntb; ++j) {
+                const double xr = j < n ? m->nodes[j] : (j == n ? -1.0 : 1.0);
+                const double x = m->x0[e * d + k] + m->jac[(e * d + k) * d + k] * (xr + 1.0);
+                const size_t o = (((size_t)e * d + k) * ntb + j) * 2;
+                vtab[o] = (R)sinpi_host(x);
+                vtab[o + 1] = (R)cospi_host(x);
+            }
     Ctx<R> C{c};
     HIPCHK(c, hipMemcpyAsync(C.template at<R>(c->L.geo), geo.data(), geo.size() * sizeof(R),
                              hipMemcpyHostToDevice, c->stream));
+    if (trig)
+        HIPCHK(c, hipMemcpyAsync(C.template at<R>(c->L.vtab), vtab.data(), vtab.size() * sizeof(R),
+                                 hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(C.template at<double>(c->L.det64), det64.data(), E * 8,
                              hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(C.template at<double>(c->L.w64), m->weights, n * 8,

@@ -121,7 +121,7 @@ void k_grad_flux(GFArgs<R> a) {
     constexpr int I_NBR = (EPB * 2 * D + NT - 1) / NT;
     constexpr int I_U = (EPB * NU + NT - 1) / NT;
     constexpr int I_NB = (EPB * NPF + NT - 1) / NT;
-    constexpr int I_TB = TAB ? (EPB * D * NTB + NT - 1) / NT : 1;
+    constexpr int I_TB = TAB ? (EPB * D * NTB * 2 + NT - 1) / NT : 1;
     R r_ops[I_OPS], r_geo[I_GEO], r_u[V][I_U];
     int32_t r_nbr[I_NBR];
 #pragma unroll
@@ -158,21 +158,14 @@ void k_grad_flux(GFArgs<R> a) {
             r_det = gld(gb, el * G + D + 2 * D * D);
         }
     }
-    // velocity-table inputs: x0_k, J_kk and the reference position of each table entry.
-    // Entries are taken from the last wave down: the face units of phase C sit in the
-    // first waves, so the sin/cos work lands on the waves that have no face unit.
-    R r_tx[I_TB];
+    // velocity tables of the block's elements (sin and cos of pi x_k at the line positions
+    // of every axis; stored with the geometry, they depend on the mesh only)
+    R r_vt[I_TB];
     if constexpr (TAB) {
 #pragma unroll
         for (int j = 0; j < I_TB; ++j) {
-            const int it = (NT - 1 - tid) + j * NT;
-            r_tx[j] = R(0);
-            if (trig && it < nel * D * NTB) {
-                const int el = it / (D * NTB), r = it - el * (D * NTB), k = r / NTB, jj = r - k * NTB;
-                const R* gb = a.geo + e0 * G;
-                const R xi = jj < N ? gld(a.ops + op_xi(N), jj) : (jj == N ? R(-1) : R(1));
-                r_tx[j] = gld(gb, el * G + k) + gld(gb, el * G + D + k * D + k) * (xi + R(1));
-            }
+            const int it = tid + j * NT;
+            r_vt[j] = (trig && it < nel * D * NTB * 2) ? gld(a.vtab + e0 * D * NTB * 2, it) : R(0);
         }
     }
     // neighbour traces on the + faces, pushed here by the neighbours (boundary + face
@@ -222,18 +215,10 @@ void k_grad_flux(GFArgs<R> a) {
         }
     }
     if constexpr (TAB) {
-        // one sincospi per line position of each axis
         if (trig) {
 #pragma unroll
-            for (int j = 0; j < I_TB; ++j) {
-                const int it = (NT - 1 - tid) + j * NT;
-                if (it < nel * D * NTB) {
-                    R sn, cs;
-                    M::sincospi_(r_tx[j], &sn, &cs);
-                    s_vt[2 * it] = sn;
-                    s_vt[2 * it + 1] = cs;
-                }
-            }
+            for (int j = 0; j < I_TB; ++j)
+                if (tid + j * NT < nel * D * NTB * 2) s_vt[tid + j * NT] = r_vt[j];
         }
     }
     // does any - face of the block lie on a boundary (face 2k of an element, no neighbour)?
