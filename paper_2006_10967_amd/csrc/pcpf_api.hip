@@ -757,9 +757,8 @@ pcpf_status reduce_impl(const Ctx<R>& C, int what, const void* d_field, const vo
     return PCPF_OK;
 }
 
-// sin(pi x) and cos(pi x) on the host: x reduced exactly to [-1, 1], then sin / cos
+// sin(pi x) on the host: x reduced exactly to [-1, 1], then sin
 double sinpi_host(double x) { return std::sin(M_PI * (x - 2.0 * std::nearbyint(0.5 * x))); }
-double cospi_host(double x) { return std::cos(M_PI * (x - 2.0 * std::nearbyint(0.5 * x))); }
 
 template <typename R>
 pcpf_status upload(pcpf_ctx* c, const pcpf_mesh* m) {
@@ -801,8 +800,9 @@ pcpf_status upload(pcpf_ctx* c, const pcpf_mesh* m) {
         ops[op_xi(n) + a] = (R)m->nodes[a];
         ops[op_w(n) + a] = (R)m->weights[a];
     }
-    // sin and cos of pi x_k at the n nodes and at both ends (xi = -1, +1) of every element
-    // axis, for the trigonometric velocity fields on axis-aligned meshes (time-independent)
+    // sin^2(pi x_k) and sin(2 pi x_k) at the n nodes and at both ends (xi = -1, +1) of every
+    // element axis: the factors of the trigonometric velocity fields on axis-aligned meshes
+    // (time-independent)
     const int ntb = n + 2;
     const bool trig = c->prm.vel_kind == PCPF_VEL_SINGLE_VORTEX || c->prm.vel_kind == PCPF_VEL_LEVEQUE3D;
     std::vector<R> vtab(trig ? (size_t)E * d * ntb * 2 : 0);
@@ -812,8 +812,9 @@ pcpf_status upload(pcpf_ctx* c, const pcpf_mesh* m) {
                 const double xr = j < n ? m->nodes[j] : (j == n ? -1.0 : 1.0);
                 const double x = m->x0[e * d + k] + m->jac[(e * d + k) * d + k] * (xr + 1.0);
                 const size_t o = (((size_t)e * d + k) * ntb + j) * 2;
-                vtab[o] = (R)sinpi_host(x);
-                vtab[o + 1] = (R)cospi_host(x);
+                const double sx = sinpi_host(x);
+                vtab[o] = (R)(sx * sx);
+                vtab[o + 1] = (R)sinpi_host(2.0 * x);
             }
     Ctx<R> C{c};
     HIPCHK(c, hipMemcpyAsync(C.template at<R>(c->L.geo), geo.data(), geo.size() * sizeof(R),

@@ -156,30 +156,29 @@ __device__ __forceinline__ R visc_ramp(R e_all, R e_top, R s0, R kappa, R nu_max
     return R(0.5) * nu_max * (R(1) + Math<R>::sinpi_((s - s0) / (R(2) * kappa)));
 }
 
-// Velocity from the per-element (sin, cos)(pi x_k) tables of an axis-aligned element:
-// vt[(k * NTB + pos_k) * 2 + {0, 1}], pos_k the node index along k, or N / N + 1 for the
-// xi_k = -1 / +1 end of the element.
+// Velocity from the per-element tables of an axis-aligned element:
+// vt[(k * NTB + pos_k) * 2 + {0, 1}] = (sin^2(pi x_k), sin(2 pi x_k)), pos_k the node index
+// along k, or N / N + 1 for the xi_k = -1 / +1 end of the element.
 template <typename R, int D, int NTB>
 __device__ __forceinline__ void velocity_tab(const Phys<R>& ph, const R* vt, const int (&pos)[D],
                                              R (&v)[D]) {
     const R A = ph.ampg;
-    R s[3], c[3];
+    R q[3], t[3];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        s[k] = vt[(k * NTB + pos[k]) * 2];
-        c[k] = vt[(k * NTB + pos[k]) * 2 + 1];
+        q[k] = vt[(k * NTB + pos[k]) * 2];
+        t[k] = vt[(k * NTB + pos[k]) * 2 + 1];
     }
     if (ph.vel_kind == PCPF_VEL_SINGLE_VORTEX) {
-        v[0] = A * (-(s[0] * s[0]) * (R(2) * s[1] * c[1]));
-        v[1] = A * ((R(2) * s[0] * c[0]) * (s[1] * s[1]));
+        v[0] = A * (-q[0] * t[1]);
+        v[1] = A * (t[0] * q[1]);
 #pragma unroll
         for (int k = 2; k < D; ++k) v[k] = R(0);
     } else {
         if (D == 3) {
-            const R s2x = R(2) * s[0] * c[0], s2y = R(2) * s[1] * c[1], s2z = R(2) * s[2] * c[2];
-            v[0] = A * (R(2) * (s[0] * s[0]) * s2y * s2z);
-            v[1] = A * (-s2x * (s[1] * s[1]) * s2z);
-            v[D - 1] = A * (-s2x * s2y * (s[2] * s[2]));
+            v[0] = A * (R(2) * q[0] * t[1] * t[2]);
+            v[1] = A * (-t[0] * q[1] * t[2]);
+            v[D - 1] = A * (-t[0] * t[1] * q[2]);
         } else {
 #pragma unroll
             for (int k = 0; k < D; ++k) v[k] = R(0);

@@ -100,8 +100,9 @@ struct GFArgs {
     const int32_t* nbr;  // [E][2D]
     const R* ops;
     const R* sgn;        // smeared sign (precond)
-    const R* vtab;       // sin, cos(pi x_k) at the n nodes and both ends of every element
-                         // axis, [E][D][n + 2][2] (axis-aligned trigonometric fields)
+    const R* vtab;       // sin^2(pi x_k), sin(2 pi x_k) at the n nodes and both ends of
+                         // every element axis, [E][D][n + 2][2] (axis-aligned
+                         // trigonometric fields)
     R* out;              // sign (GF_SIGN) or nu (GF_SENSOR)
     int64_t E;
     Phys<R> ph;

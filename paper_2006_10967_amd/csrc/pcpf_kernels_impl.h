@@ -45,7 +45,7 @@ using namespace dev;
 //   GF_SENSOR   psi only: the element viscosity nu_e.
 // AXIS: every element is axis-aligned (diagonal J): the metric terms reduce to one
 // product per component, face normals are +-e_k, and trigonometric velocity fields come
-// from per-element tables of sin/cos(pi x_k) at the n node positions and both ends.
+// from per-element tables of sin^2(pi x_k), sin(2 pi x_k) at the n nodes and both ends.
 // Phases: A loads (state, operators, geometry, neighbour traces, face normals, velocity
 // tables) | B corrected gradient q and fluxes f~ at solution points -> LDS | C common
 // fluxes on owned face points -> global, and P = sum_k DH_k f~_k -> global.
@@ -158,8 +158,8 @@ void k_grad_flux(GFArgs<R> a) {
             r_det = gld(gb, el * G + D + 2 * D * D);
         }
     }
-    // velocity tables of the block's elements (sin and cos of pi x_k at the line positions
-    // of every axis; stored with the geometry, they depend on the mesh only)
+    // velocity tables of the block's elements (sin^2(pi x_k) and sin(2 pi x_k) at the line
+    // positions of every axis; stored with the geometry, they depend on the mesh only)
     R r_vt[I_TB];
     if constexpr (TAB) {
 #pragma unroll
