@@ -48,7 +48,8 @@ typedef enum pcpf_status {
     PCPF_EDEVICE = 2,       /* a HIP runtime call failed; pcpf_last_error has its message */
     PCPF_EUNSUPPORTED = 3,  /* valid but not built (e.g. order above the compiled range) */
     PCPF_ESTATE = 4,        /* call out of order (no state set, ...) */
-    PCPF_ENONFINITE = 5     /* the state became non-finite or |phi| > 10; state kept */
+    PCPF_ENONFINITE = 5,    /* the state became non-finite or |phi| > 10; state kept */
+    PCPF_ENOMEM = 6         /* a host allocation failed (the library caught the exception) */
 } pcpf_status;
 
 /* Precision of the form. PCPF_FP64: everything in float64. PCPF_FP32: float32 state and

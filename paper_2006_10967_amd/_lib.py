@@ -9,9 +9,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("PCPF_LIBRARY") or os.path.join(HERE, "libpcpf.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "pcpf.h")
 
-PCPF_OK, PCPF_EINVAL, PCPF_EDEVICE, PCPF_EUNSUPPORTED, PCPF_ESTATE, PCPF_ENONFINITE = range(6)
+(PCPF_OK, PCPF_EINVAL, PCPF_EDEVICE, PCPF_EUNSUPPORTED, PCPF_ESTATE, PCPF_ENONFINITE,
+ PCPF_ENOMEM) = range(7)
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "EDEVICE", 3: "EUNSUPPORTED", 4: "ESTATE",
-                5: "ENONFINITE"}
+                5: "ENONFINITE", 6: "ENOMEM"}
 PCPF_FP64, PCPF_FP32, PCPF_BF16 = 0, 1, 2
 PCPF_MODE_PHYS, PCPF_MODE_PRECOND = 0, 1
 PCPF_NORMAL_PSI, PCPF_NORMAL_PHI = 0, 1

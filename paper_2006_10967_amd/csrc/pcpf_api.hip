@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -22,6 +23,11 @@ pcpf_status fail(std::string* dst, pcpf_status st, const std::string& msg) {
     g_err = msg;
     return st;
 }
+
+// Status of an entry point that caught an exception (a failed host allocation: every
+// other failure is reported by status). The message fits the strings' inline buffer, so
+// setting it allocates nothing.
+pcpf_status out_of_memory(pcpf_ctx* c) noexcept;
 
 // ------------------------------------------------------------------------------------
 // 1D Gauss-Legendre element (host, float64)
@@ -73,7 +79,7 @@ int pcpf_abi_version(void) { return PCPF_ABI_VERSION; }
 
 pcpf_status pcpf_line_operators(int32_t order, double* nodes, double* weights, double* deriv,
                                 double* lminus, double* lplus, double* cminus, double* cplus,
-                                double* vinv) {
+                                double* vinv) try {
     if (order < 1 || order > PCPF_MAX_ORDER)
         return fail(nullptr, PCPF_EINVAL, "pcpf_line_operators: order out of range");
     if (!nodes || !weights || !deriv || !lminus || !lplus || !cminus || !cplus || !vinv)
@@ -122,6 +128,8 @@ pcpf_status pcpf_line_operators(int32_t order, double* nodes, double* weights, d
         }
     }
     return PCPF_OK;
+} catch (...) {
+    return out_of_memory(nullptr);
 }
 
 }  // extern "C"
@@ -1169,6 +1177,13 @@ pcpf_status check_params(const pcpf_params* p, std::string* err) {
     return PCPF_OK;
 }
 
+pcpf_status out_of_memory(pcpf_ctx* c) noexcept {
+    static const char kMsg[] = "out of memory";
+    if (c) c->err = kMsg;
+    g_err = kMsg;
+    return PCPF_ENOMEM;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1177,7 +1192,7 @@ const char* pcpf_last_error(const pcpf_ctx* ctx) {
     return ctx ? ctx->err.c_str() : g_err.c_str();
 }
 
-pcpf_status pcpf_solution_coords(const pcpf_mesh* m, double* xs) {
+pcpf_status pcpf_solution_coords(const pcpf_mesh* m, double* xs) try {
     MeshInfo mi;
     pcpf_status st = check_mesh(m, &mi, nullptr);
     if (st != PCPF_OK) return st;
@@ -1194,9 +1209,11 @@ pcpf_status pcpf_solution_coords(const pcpf_mesh* m, double* xs) {
                       xs + (e * mi.nu + i) * mi.d);
         }
     return PCPF_OK;
+} catch (...) {
+    return out_of_memory(nullptr);
 }
 
-pcpf_status pcpf_workspace_bytes(const pcpf_mesh* m, const pcpf_params* p, size_t* nbytes) {
+pcpf_status pcpf_workspace_bytes(const pcpf_mesh* m, const pcpf_params* p, size_t* nbytes) try {
     MeshInfo mi;
     pcpf_status st = check_mesh(m, &mi, nullptr);
     if (st != PCPF_OK) return st;
@@ -1205,10 +1222,12 @@ pcpf_status pcpf_workspace_bytes(const pcpf_mesh* m, const pcpf_params* p, size_
     if (!nbytes) return fail(nullptr, PCPF_EINVAL, "nbytes is NULL");
     *nbytes = layout(mi, p->precision).total;
     return PCPF_OK;
+} catch (...) {
+    return out_of_memory(nullptr);
 }
 
 pcpf_status pcpf_create(const pcpf_mesh* m, const pcpf_params* p, void* d_ws, size_t ws_bytes,
-                        void* stream, pcpf_ctx** out) {
+                        void* stream, pcpf_ctx** out) try {
     if (!out) return fail(nullptr, PCPF_EINVAL, "out is NULL");
     *out = nullptr;
     MeshInfo mi;
@@ -1223,7 +1242,8 @@ pcpf_status pcpf_create(const pcpf_mesh* m, const pcpf_params* p, void* d_ws, si
         return fail(nullptr, PCPF_EINVAL, "workspace missing or smaller than pcpf_workspace_bytes");
     if (reinterpret_cast<uintptr_t>(d_ws) % 256 != 0)
         return fail(nullptr, PCPF_EINVAL, "workspace must be 256-byte aligned");
-    pcpf_ctx* c = new pcpf_ctx();
+    std::unique_ptr<pcpf_ctx> hold(new pcpf_ctx());
+    pcpf_ctx* c = hold.get();
     c->mi = mi;
     c->prm = *p;
     c->stream = static_cast<hipStream_t>(stream);
@@ -1237,31 +1257,31 @@ pcpf_status pcpf_create(const pcpf_mesh* m, const pcpf_params* p, void* d_ws, si
     bool ok = p->precision != PCPF_FP64
                   ? (get_launchers<float>(mi.d, mi.p, &c->L32) && get_adj_launchers<float>(mi.d, mi.p, &c->A32))
                   : (get_launchers<double>(mi.d, mi.p, &c->L64) && get_adj_launchers<double>(mi.d, mi.p, &c->A64));
-    if (!ok) {
-        delete c;
-        return fail(nullptr, PCPF_EUNSUPPORTED, "no kernels built for this (d, p)");
-    }
+    if (!ok) return fail(nullptr, PCPF_EUNSUPPORTED, "no kernels built for this (d, p)");
     st = p->precision != PCPF_FP64 ? upload<float>(c, m) : upload<double>(c, m);
     if (st != PCPF_OK) {
         g_err = c->err;
-        delete c;
         return st;
     }
-    *out = c;
+    *out = hold.release();
     return PCPF_OK;
+} catch (...) {
+    return out_of_memory(nullptr);
 }
 
 void pcpf_destroy(pcpf_ctx* c) { delete c; }
 
-pcpf_status pcpf_sizes(const pcpf_ctx* c, int64_t* nelem, int32_t* nupts) {
+pcpf_status pcpf_sizes(const pcpf_ctx* c, int64_t* nelem, int32_t* nupts) try {
     if (!c) return fail(nullptr, PCPF_EINVAL, "ctx is NULL");
     if (nelem) *nelem = c->mi.E;
     if (nupts) *nupts = c->mi.nu;
     return PCPF_OK;
+} catch (...) {
+    return out_of_memory(nullptr);
 }
 
 pcpf_status pcpf_set_state(pcpf_ctx* c, const void* d_phi, const void* d_psi, double t,
-                           int64_t step) {
+                           int64_t step) try {
     if (check_ctx(c) != PCPF_OK) return PCPF_EINVAL;
     if (!d_phi) return fail(&c->err, PCPF_EINVAL, "d_phi is NULL");
     if (step < 0) return fail(&c->err, PCPF_EINVAL, "step must be >= 0");
@@ -1276,9 +1296,11 @@ pcpf_status pcpf_set_state(pcpf_ctx* c, const void* d_phi, const void* d_psi, do
     c->has_psi = d_psi != nullptr;
     c->trace_ok[0] = c->trace_ok[1] = false;
     return PCPF_OK;
+} catch (...) {
+    return out_of_memory(c);
 }
 
-pcpf_status pcpf_get_state(pcpf_ctx* c, void* d_phi, void* d_psi, double* t, int64_t* step) {
+pcpf_status pcpf_get_state(pcpf_ctx* c, void* d_phi, void* d_psi, double* t, int64_t* step) try {
     if (check_ctx(c) != PCPF_OK) return PCPF_EINVAL;
     if (!c->has_state) return fail(&c->err, PCPF_ESTATE, "no state set");
     const size_t bytes = (size_t)c->mi.E * c->mi.nu * (c->prm.precision != PCPF_FP64 ? 4 : 8);
@@ -1292,16 +1314,20 @@ pcpf_status pcpf_get_state(pcpf_ctx* c, void* d_phi, void* d_psi, double* t, int
     if (t) *t = c->t;
     if (step) *step = c->step;
     return PCPF_OK;
+} catch (...) {
+    return out_of_memory(c);
 }
 
-pcpf_status pcpf_step(pcpf_ctx* c, double dt, int64_t nsteps) {
+pcpf_status pcpf_step(pcpf_ctx* c, double dt, int64_t nsteps) try {
     if (check_ctx(c) != PCPF_OK) return PCPF_EINVAL;
     if (!c->has_state) return fail(&c->err, PCPF_ESTATE, "no state set");
     if (!std::isfinite(dt) || nsteps < 0) return fail(&c->err, PCPF_EINVAL, "bad dt or nsteps");
     return DISPATCH(c, step_impl, dt, nsteps);
+} catch (...) {
+    return out_of_memory(c);
 }
 
-pcpf_status pcpf_precondition(pcpf_ctx* c, int32_t iters) {
+pcpf_status pcpf_precondition(pcpf_ctx* c, int32_t iters) try {
     if (check_ctx(c) != PCPF_OK) return PCPF_EINVAL;
     if (!c->has_state) return fail(&c->err, PCPF_ESTATE, "no state set");
     const int k = iters < 0 ? c->prm.precond_iters : iters;
@@ -1309,18 +1335,22 @@ pcpf_status pcpf_precondition(pcpf_ctx* c, int32_t iters) {
     if (st != PCPF_OK || !c->timing) return st;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return collect_times(c);
+} catch (...) {
+    return out_of_memory(c);
 }
 
-pcpf_status pcpf_precond_info(const pcpf_ctx* c, int32_t* iters, double* rms) {
+pcpf_status pcpf_precond_info(const pcpf_ctx* c, int32_t* iters, double* rms) try {
     if (!c) return fail(nullptr, PCPF_EINVAL, "precond_info: NULL context");
     if (c->pc_iters < 0) return fail(nullptr, PCPF_ESTATE, "no preconditioning has run");
     if (iters) *iters = c->pc_iters;
     if (rms) *rms = c->pc_rms;
     return PCPF_OK;
+} catch (...) {
+    return out_of_memory(nullptr);
 }
 
 pcpf_status pcpf_residual(pcpf_ctx* c, const void* d_phi, const void* d_psi, double t,
-                          int32_t mode, void* d_rphi, void* d_rpsi) {
+                          int32_t mode, void* d_rphi, void* d_rpsi) try {
     if (check_ctx(c) != PCPF_OK) return PCPF_EINVAL;
     if (mode != PCPF_MODE_PHYS && mode != PCPF_MODE_PRECOND)
         return fail(&c->err, PCPF_EINVAL, "unknown residual mode");
@@ -1331,25 +1361,31 @@ pcpf_status pcpf_residual(pcpf_ctx* c, const void* d_phi, const void* d_psi, dou
     if (d_rpsi == d_psi || d_rpsi == d_phi || (d_rphi && (d_rphi == d_phi || d_rphi == d_psi)))
         return fail(&c->err, PCPF_EINVAL, "residual outputs may not alias inputs");
     return DISPATCH(c, residual_impl, d_phi, d_psi, t, mode, d_rphi, d_rpsi);
+} catch (...) {
+    return out_of_memory(c);
 }
 
-pcpf_status pcpf_get_sign(pcpf_ctx* c, void* d_sgn) {
+pcpf_status pcpf_get_sign(pcpf_ctx* c, void* d_sgn) try {
     if (check_ctx(c) != PCPF_OK) return PCPF_EINVAL;
     if (!c->has_sign) return fail(&c->err, PCPF_ESTATE, "no reset has run");
     if (!d_sgn) return fail(&c->err, PCPF_EINVAL, "d_sgn is NULL");
     const size_t bytes = (size_t)c->mi.E * c->mi.nu * (c->prm.precision != PCPF_FP64 ? 4 : 8);
     HIPCHK(c, hipMemcpyAsync(d_sgn, c->ws + c->L.sgn, bytes, hipMemcpyDeviceToDevice, c->stream));
     return PCPF_OK;
+} catch (...) {
+    return out_of_memory(c);
 }
 
-pcpf_status pcpf_sensor(pcpf_ctx* c, const void* d_psi, void* d_nu) {
+pcpf_status pcpf_sensor(pcpf_ctx* c, const void* d_psi, void* d_nu) try {
     if (check_ctx(c) != PCPF_OK) return PCPF_EINVAL;
     if (!d_psi || !d_nu) return fail(&c->err, PCPF_EINVAL, "sensor: NULL pointer");
     return DISPATCH(c, sensor_impl, d_psi, d_nu);
+} catch (...) {
+    return out_of_memory(c);
 }
 
 pcpf_status pcpf_reduce(pcpf_ctx* c, int32_t what, const void* d_field, const void* d_ref,
-                        double* out) {
+                        double* out) try {
     if (check_ctx(c) != PCPF_OK) return PCPF_EINVAL;
     if (!out) return fail(&c->err, PCPF_EINVAL, "out is NULL");
     if (what != PCPF_REDUCE_MASS && what != PCPF_REDUCE_L1 && what != PCPF_REDUCE_RMS)
@@ -1358,9 +1394,11 @@ pcpf_status pcpf_reduce(pcpf_ctx* c, int32_t what, const void* d_field, const vo
         return fail(&c->err, PCPF_EINVAL, "L1 and RMS need d_ref");
     if (!d_field && !c->has_state) return fail(&c->err, PCPF_ESTATE, "no state set");
     return DISPATCH(c, reduce_impl, what, d_field, d_ref, out);
+} catch (...) {
+    return out_of_memory(c);
 }
 
-pcpf_status pcpf_set_timing(pcpf_ctx* c, int32_t on) {
+pcpf_status pcpf_set_timing(pcpf_ctx* c, int32_t on) try {
     if (check_ctx(c) != PCPF_OK) return PCPF_EINVAL;
     if (c->ev_used) {
         HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1369,9 +1407,11 @@ pcpf_status pcpf_set_timing(pcpf_ctx* c, int32_t on) {
     }
     c->timing = on != 0;
     return PCPF_OK;
+} catch (...) {
+    return out_of_memory(c);
 }
 
-pcpf_status pcpf_kernel_times(pcpf_ctx* c, double* ms, int64_t* launches, int32_t reset) {
+pcpf_status pcpf_kernel_times(pcpf_ctx* c, double* ms, int64_t* launches, int32_t reset) try {
     if (check_ctx(c) != PCPF_OK) return PCPF_EINVAL;
     for (int k = 0; k < PCPF_KT_COUNT; ++k) {
         if (ms) ms[k] = c->kt_ms[k];
@@ -1382,25 +1422,31 @@ pcpf_status pcpf_kernel_times(pcpf_ctx* c, double* ms, int64_t* launches, int32_
         }
     }
     return PCPF_OK;
+} catch (...) {
+    return out_of_memory(c);
 }
 
-pcpf_status pcpf_set_velocity_amplitude(pcpf_ctx* c, double amp) {
+pcpf_status pcpf_set_velocity_amplitude(pcpf_ctx* c, double amp) try {
     if (check_ctx(c) != PCPF_OK) return PCPF_EINVAL;
     if (!std::isfinite(amp)) return fail(&c->err, PCPF_EINVAL, "amplitude must be finite");
     c->prm.vel_amp = amp;
     return PCPF_OK;
+} catch (...) {
+    return out_of_memory(c);
 }
 
-pcpf_status pcpf_ckpt_bytes(const pcpf_ctx* c, int64_t nsteps, int64_t every, size_t* nbytes) {
+pcpf_status pcpf_ckpt_bytes(const pcpf_ctx* c, int64_t nsteps, int64_t every, size_t* nbytes) try {
     if (!c || !nbytes) return fail(nullptr, PCPF_EINVAL, "ckpt_bytes: NULL argument");
     if (nsteps < 1 || every < 1) return fail(nullptr, PCPF_EINVAL, "nsteps and every must be >= 1");
     const size_t r = c->prm.precision != PCPF_FP64 ? 4 : 8;
     *nbytes = (size_t)((nsteps + every - 1) / every) * 2 * (size_t)c->mi.E * c->mi.nu * r;
     return PCPF_OK;
+} catch (...) {
+    return out_of_memory(nullptr);
 }
 
 pcpf_status pcpf_forward_ckpt(pcpf_ctx* c, double dt, int64_t nsteps, int64_t every, void* d_ckpt,
-                              size_t ckpt_bytes) {
+                              size_t ckpt_bytes) try {
     if (check_ctx(c) != PCPF_OK) return PCPF_EINVAL;
     if (c->prm.precision == PCPF_BF16)
         return fail(&c->err, PCPF_EUNSUPPORTED, "no adjoint of the PCPF_BF16 form");
@@ -1420,18 +1466,22 @@ pcpf_status pcpf_forward_ckpt(pcpf_ctx* c, double dt, int64_t nsteps, int64_t ev
     if (N > 0 && !c->has_psi && c->step % N != 0 && nsteps > 1)
         return fail(&c->err, PCPF_EINVAL, "a forced reset off the reset schedule is not supported");
     return DISPATCH(c, forward_ckpt_impl, dt, nsteps, every, d_ckpt);
+} catch (...) {
+    return out_of_memory(c);
 }
 
-pcpf_status pcpf_adjoint_bytes(const pcpf_ctx* c, int64_t every, size_t* nbytes) {
+pcpf_status pcpf_adjoint_bytes(const pcpf_ctx* c, int64_t every, size_t* nbytes) try {
     if (!c || !nbytes) return fail(nullptr, PCPF_EINVAL, "adjoint_bytes: NULL argument");
     if (every < 1) return fail(nullptr, PCPF_EINVAL, "every must be >= 1");
     *nbytes = adj_layout(c, every).total;
     return PCPF_OK;
+} catch (...) {
+    return out_of_memory(nullptr);
 }
 
 pcpf_status pcpf_adjoint(pcpf_ctx* c, const void* d_ckpt, void* d_scratch, size_t scratch_bytes,
                          const void* d_gphi, const void* d_gpsi, void* d_gphi0, void* d_gpsi0,
-                         double* g_amp) {
+                         double* g_amp) try {
     if (check_ctx(c) != PCPF_OK) return PCPF_EINVAL;
     if (!c->ck_valid) return fail(&c->err, PCPF_ESTATE, "no checkpointed forward run");
     if (!d_ckpt || !d_gphi || !d_gphi0) return fail(&c->err, PCPF_EINVAL, "adjoint: NULL argument");
@@ -1440,6 +1490,8 @@ pcpf_status pcpf_adjoint(pcpf_ctx* c, const void* d_ckpt, void* d_scratch, size_
     if (reinterpret_cast<uintptr_t>(d_scratch) % 256 != 0)
         return fail(&c->err, PCPF_EINVAL, "adjoint scratch must be 256-byte aligned");
     return DISPATCH(c, adjoint_impl, d_ckpt, d_scratch, d_gphi, d_gpsi, d_gphi0, d_gpsi0, g_amp);
+} catch (...) {
+    return out_of_memory(c);
 }
 
 }  // extern "C"

@@ -24,6 +24,25 @@ def test_exports_every_declared_symbol():
     assert lib.pcpf_abi_version() == 1
 
 
+def test_binding_constants_match_the_header():
+    """Every PCPF_* constant that the binding defines has the header's value."""
+    import os
+    import re
+    hdr = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                            "include", "pcpf.h")).read()
+    values = {m.group(1): int(m.group(2))
+              for m in re.finditer(r"\b(PCPF_[A-Z0-9_]+)\s*=\s*(\d+)", hdr)}
+    assert "PCPF_ENOMEM" in values
+    checked = 0
+    for name in dir(_lib):
+        if name.startswith("PCPF_") and name in values:
+            assert getattr(_lib, name) == values[name], name
+            checked += 1
+    assert checked >= 20
+    assert set(_lib.STATUS_NAMES) == {v for k, v in values.items()
+                                      if k == "PCPF_OK" or re.fullmatch(r"PCPF_E[A-Z]+", k)}
+
+
 @pytest.mark.parametrize("p", range(1, 7))
 def test_line_operators_match_oracle_basis(p):
     ops = P.line_operators(p)
