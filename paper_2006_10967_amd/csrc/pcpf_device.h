@@ -38,6 +38,14 @@ template <typename T>
 __device__ __forceinline__ T gld(const T* base, uint32_t i) {
     return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + i * (uint32_t)sizeof(T));
 }
+// Load of element min(i, n - 1) (n >= 1): an unconditional load that stays inside the n
+// valid elements, for lanes whose value is then discarded. Without a branch around each
+// load, the scalar loads of all base pointers can be issued together ahead of the vector
+// loads instead of one after another.
+template <typename T>
+__device__ __forceinline__ T gld_in(const T* base, int i, int n) {
+    return gld(base, (uint32_t)(i < n ? i : n - 1));
+}
 template <typename T>
 __device__ __forceinline__ void gst(T* base, uint32_t i, T v) {
     *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (uint32_t)sizeof(T)) = v;
@@ -144,6 +152,26 @@ __device__ __forceinline__ void velocity_lin(const Phys<R>& ph, const R (&x)[D],
 #pragma unroll
         for (int k = 0; k < D; ++k) v[k] = A * ph.u0[k];
     }
+}
+
+// max(sqrt(x), g) for x >= 0 and g > 0: the flux multiplier max(gamma, |v|) of §2. The root is
+// taken only where x > g^2, which keeps its argument away from the tiny and huge ranges a
+// general square root has to rescale. There the hardware reciprocal-root estimate y is
+// refined by one coupled Newton step for the pair (sqrt(x), 1/(2 sqrt(x))), started from
+// (x y, y / 2), and one correction by the residual x - s^2 (within an ulp or two of the
+// rounded root). NaN gives g, as max(sqrt(NaN), g) does.
+__device__ __forceinline__ double max_sqrt(double x, double g) {
+    if (!(x > g * g)) return g;
+    const double y = __builtin_amdgcn_rsq(x);
+    double s = x * y, h = 0.5 * y;
+    const double r = __builtin_fma(-s, h, 0.5);
+    s = __builtin_fma(s, r, s);
+    h = __builtin_fma(h, r, h);
+    const double d = __builtin_fma(-s, s, x);
+    return __builtin_fma(d, h, s);
+}
+__device__ __forceinline__ float max_sqrt(float x, float g) {
+    return (x > g * g) ? __builtin_amdgcn_sqrtf(x) : g;
 }
 
 template <typename R>

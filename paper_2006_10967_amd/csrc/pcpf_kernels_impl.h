@@ -127,24 +127,24 @@ void k_grad_flux(GFArgs<R> a) {
 #pragma unroll
     for (int j = 0; j < I_OPS; ++j) {
         const int i = tid + j * NT;
-        r_ops[j] = (i < NOPS) ? gld(a.ops, i) : R(0);
+        r_ops[j] = gld_in(a.ops, i, NOPS);
     }
 #pragma unroll
     for (int j = 0; j < I_GEO; ++j) {
         const int i = tid + j * NT;
-        r_geo[j] = (i < nel * G) ? gld(a.geo + e0 * G, i) : R(0);
+        r_geo[j] = gld_in(a.geo + e0 * G, i, nel * G);
     }
 #pragma unroll
     for (int j = 0; j < I_NBR; ++j) {
         const int i = tid + j * NT;
-        r_nbr[j] = (i < nel * 2 * D) ? gld(a.nbr + e0 * 2 * D, i) : -1;
+        r_nbr[j] = gld_in(a.nbr + e0 * 2 * D, i, nel * 2 * D);
     }
 #pragma unroll
     for (int v = 0; v < V; ++v)
 #pragma unroll
         for (int j = 0; j < I_U; ++j) {
             const int i = tid + j * NT;
-            r_u[v][j] = (i < nel * NU) ? gld(a.u[v] + e0 * NU, i) : R(0);
+            r_u[v][j] = gld_in(a.u[v] + e0 * NU, i, nel * NU);
         }
     // + face normal inputs (row k of J^-1 and |J|) of this thread's (element, face)
     R r_ji[FLUX ? D : 1], r_det = R(1);
@@ -158,16 +158,6 @@ void k_grad_flux(GFArgs<R> a) {
             r_det = gld(gb, el * G + D + 2 * D * D);
         }
     }
-    // velocity tables of the block's elements (sin^2(pi x_k) and sin(2 pi x_k) at the line
-    // positions of every axis; stored with the geometry, they depend on the mesh only)
-    R r_vt[I_TB];
-    if constexpr (TAB) {
-#pragma unroll
-        for (int j = 0; j < I_TB; ++j) {
-            const int it = tid + j * NT;
-            r_vt[j] = (trig && it < nel * D * NTB * 2) ? gld(a.vtab + e0 * D * NTB * 2, it) : R(0);
-        }
-    }
     // neighbour traces on the + faces, pushed here by the neighbours (boundary + face
     // slots are zeroed when the context is created and never written)
     R r_nb[GRAD ? I_NB : 1][V];
@@ -176,7 +166,17 @@ void k_grad_flux(GFArgs<R> a) {
         for (int j = 0; j < I_NB; ++j) {
             const int it = tid + j * NT;
 #pragma unroll
-            for (int v = 0; v < V; ++v) r_nb[j][v] = (it < nel * NPF) ? gld(a.Tp[v] + e0 * NPF, it) : R(0);
+            for (int v = 0; v < V; ++v) r_nb[j][v] = gld_in(a.Tp[v] + e0 * NPF, it, nel * NPF);
+        }
+    }
+    // velocity tables of the block's elements (sin^2(pi x_k) and sin(2 pi x_k) at the line
+    // positions of every axis; stored with the geometry, they depend on the mesh only)
+    R r_vt[I_TB];
+    if constexpr (TAB) {
+#pragma unroll
+        for (int j = 0; j < I_TB; ++j) {
+            const int it = tid + j * NT;
+            r_vt[j] = trig ? gld_in(a.vtab + e0 * D * NTB * 2, it, nel * D * NTB * 2) : R(0);
         }
     }
     // registers -> LDS
@@ -426,8 +426,7 @@ void k_grad_flux(GFArgs<R> a) {
                     v2 += vel[i] * vel[i];
                     g2 += q[NV][i] * q[NV][i];
                 }
-                R mm = M::sqrt_(v2);
-                if (!(mm > a.ph.gamma)) mm = a.ph.gamma;
+                const R mm = max_sqrt(v2, a.ph.gamma);
                 const R rn = M::rsqrt_(g2 + a.ph.delta_n * a.ph.delta_n);
                 const R phi = s_u[0][tid], psi = s_u[1][tid];
                 const R sharp = a.ph.gamma * phi * (R(1) - phi) * rn;
@@ -593,8 +592,7 @@ void k_grad_flux(GFArgs<R> a) {
                         vn += vel[i] * nrm[i];
                     }
                 }
-                R mm = M::sqrt_(v2);
-                if (!(mm > a.ph.gamma)) mm = a.ph.gamma;
+                const R mm = max_sqrt(v2, a.ph.gamma);
                 const R rn = M::rsqrt_(g2 + a.ph.delta_n * a.ph.delta_n);
                 const R pL = uL[0], pR = uR[0], sL = uL[1], sR = uR[1];
                 const R fvn = mm * (a.ph.eps * qn[0] - a.ph.gamma * pL * (R(1) - pL) * qn[NV] * rn);
@@ -819,29 +817,26 @@ __global__ __launch_bounds__((Shape<D, P>::NT)) void k_update(UPArgs<R> a) {
     int32_t r_own[S::UPW];
     if constexpr (KIND == UP_RK) load_owners<D, P, S::UPW>(r_own, a.nbr, e0, nel, wave, lane);
     R rP[V], rU[V], rA[V];
-    R det = R(1);
     const uint32_t so = e0 * NU;     // first state value of the block (per plane)
-    if (pt) {
-        det = gld(a.geo + e0 * G, le * G + D + 2 * D * D);
+    // lanes past the block's points load its last point (values unused)
+    const int tp = pt ? tid : nel * NU - 1;
+    const R det = gld(a.geo + e0 * G, (tp / NU) * G + D + 2 * D * D);
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
-            rP[v] = gld(a.P[v] + so, tid);
-            if constexpr (KIND == UP_RK) {
-                rU[v] = gld(a.un[v] + so, tid);
-                rA[v] = a.first ? R(0) : gld(a.acc[v] + so, tid);
-            }
+    for (int v = 0; v < V; ++v) {
+        rP[v] = gld(a.P[v] + so, tp);
+        if constexpr (KIND == UP_RK) {
+            rU[v] = gld(a.un[v] + so, tp);
+            rA[v] = a.first ? R(0) : gld(a.acc[v] + so, tp);
         }
     }
-    R r_c[3] = {R(0), R(0), R(0)};
-    if (tid < N) {
-        r_c[0] = gld(a.ops + op_cm(N), tid);
-        r_c[1] = gld(a.ops + op_cp(N), tid);
-        r_c[2] = gld(a.ops + op_lm(N), tid);
-    }
+    R r_c[3];
+    r_c[0] = gld_in(a.ops + op_cm(N), tid, N);
+    r_c[1] = gld_in(a.ops + op_cp(N), tid, N);
+    r_c[2] = gld_in(a.ops + op_lm(N), tid, N);
     R r_F[I_F][V];
 #pragma unroll
     for (int j = 0; j < I_F; ++j) {
-        const int it = tid + j * NT;
+        const int it = (tid + j * NT < nel * NFE) ? tid + j * NT : nel * NFE - 1;
         const int el = it / NFE;
         const int r = it - el * NFE;
         const int f = r / NFA;
@@ -849,9 +844,7 @@ __global__ __launch_bounds__((Shape<D, P>::NT)) void k_update(UPArgs<R> a) {
         const int k = f >> 1, s = f & 1;
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            R F = R(0);
-            if (it < nel * NFE) F = gld((s ? a.Fp[v] : a.Fm[v]) + e0 * D * NFA, (el * D + k) * NFA + t);
-            r_F[j][v] = F;
+            r_F[j][v] = gld((s ? a.Fp[v] : a.Fm[v]) + e0 * D * NFA, (el * D + k) * NFA + t);
         }
     }
     if (tid < N) {
