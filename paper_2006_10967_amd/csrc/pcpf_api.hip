@@ -318,6 +318,7 @@ struct pcpf_ctx {
     bool has_state = false, has_psi = false, has_sign = false;
     bool trace_ok[2] = {false, false};
     bool axis = false;     // every element axis-aligned (diagonal J)
+    bool bnd_minus = false;  // some - face (face 2k) has no neighbour
     // checkpointed forward run recorded by pcpf_forward_ckpt (read by pcpf_adjoint)
     bool ck_valid = false, ck_has_psi0 = false;
     int64_t ck_step0 = 0, ck_nsteps = 0, ck_every = 1;
@@ -426,6 +427,7 @@ GFArgs<R> gf_args(const Ctx<R>& C, const R* u0, const R* u1, double t) {
     a.mf = c->prm.precision == PCPF_BF16 ? 1 : 0;
     a.nphi = c->prm.normal_mode == PCPF_NORMAL_PHI ? 1 : 0;
     a.sgn_current = c->prm.sgn_mode == PCPF_SGN_CURRENT ? 1 : 0;
+    a.bnd_minus = c->bnd_minus ? 1 : 0;
     return a;
 }
 
@@ -1254,6 +1256,9 @@ pcpf_status pcpf_create(const pcpf_mesh* m, const pcpf_params* p, void* d_ws, si
         for (int i = 0; i < mi.d; ++i)
             for (int j = 0; j < mi.d; ++j)
                 if (i != j && m->jac[(e * mi.d + i) * mi.d + j] != 0.0) c->axis = false;
+    for (int64_t e = 0; e < mi.E && !c->bnd_minus; ++e)
+        for (int k = 0; k < mi.d; ++k)
+            if (m->nbr[e * 2 * mi.d + 2 * k] < 0) c->bnd_minus = true;
     bool ok = p->precision != PCPF_FP64
                   ? (get_launchers<float>(mi.d, mi.p, &c->L32) && get_adj_launchers<float>(mi.d, mi.p, &c->A32))
                   : (get_launchers<double>(mi.d, mi.p, &c->L64) && get_adj_launchers<double>(mi.d, mi.p, &c->A64));

@@ -112,6 +112,8 @@ struct GFArgs {
     int nphi;            // interface normal from phi (the unpreconditioned form)
     int sgn_current;     // GF_PRECOND: sgn holds psi0 and the sign is tanh(psi0 / |grad psi|)
                          // of the current stage
+    int bnd_minus;       // some - face of the mesh lies on a boundary (its flux is computed
+                         // by the element itself)
 };
 
 // update kernel kinds

@@ -221,14 +221,7 @@ void k_grad_flux(GFArgs<R> a) {
                 if (tid + j * NT < nel * D * NTB * 2) s_vt[tid + j * NT] = r_vt[j];
         }
     }
-    // does any - face of the block lie on a boundary (face 2k of an element, no neighbour)?
-    int my_bnd = 0;
-#pragma unroll
-    for (int j = 0; j < I_NBR; ++j) {
-        const int i = tid + j * NT;
-        if (i < nel * 2 * D && (i & 1) == 0 && r_nbr[j] < 0) my_bnd = 1;
-    }
-    const int has_bnd = __syncthreads_or(my_bnd);
+    __syncthreads();
 
     // ---- sensor (§3.2): modal coefficients by one 1D transform per direction -----------
     if constexpr (SENS) {
@@ -646,7 +639,9 @@ void k_grad_flux(GFArgs<R> a) {
             }
         };
         face_pass(std::integral_constant<int, 1>{});
-        if (has_bnd) face_pass(std::integral_constant<int, 0>{});
+        // - faces on a boundary (face 2k without a neighbour) exist only on meshes with
+        // walls; the pass skips every point whose face has a neighbour
+        if (a.bnd_minus) face_pass(std::integral_constant<int, 0>{});
 
         // ---- E: volume part of Step 6, P = sum_k DH_k f~_k (- |J| S) ---------------------
         if constexpr (MF) {
