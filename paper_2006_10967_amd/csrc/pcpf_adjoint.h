@@ -62,6 +62,9 @@ template <typename R>
 bool get_adj_launchers(int d, int p, AdjLaunchers<R>* out);
 template <typename R>
 void launch_axpby(R* out, const R* x, const R* y, R alpha, R beta, int64_t n, hipStream_t s);
+// ya[i] = yb[i], rb[i] = alpha yb[i] for i < n (ya, rb, yb each hold both variables)
+template <typename R>
+void launch_rev_seed(R* ya, R* rb, const R* yb, R alpha, int64_t n, hipStream_t s);
 template <typename R>
 void launch_reset_adj(R* phib, const R* psi0b, const R* phi, int64_t n, int mode, double eps_w,
                       double dphi, hipStream_t s);

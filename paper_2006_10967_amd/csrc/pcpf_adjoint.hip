@@ -789,6 +789,18 @@ __global__ void k_axpby(R* out, const R* x, const R* y, R alpha, R beta, int64_t
     if (i < n) out[i] = alpha * x[i] + (y ? beta * y[i] : R(0));
 }
 
+// Start of a reverse step, both variables in one pass: ya <- yb (the running adjoint of u_n)
+// and rb <- alpha yb (the adjoint of the last stage's residual), as a copy and an axpby.
+template <typename R>
+__global__ void k_rev_seed(R* ya, R* rb, const R* yb, R alpha, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const R y = yb[i];
+        ya[i] = y;
+        rb[i] = alpha * y + R(0);
+    }
+}
+
 // adjoint of the reset psi0 = phi - 1/2 (LINEAR) or eps_w ln(c / (1 - c)) (LOGIT):
 // phi^ += psi0^ dpsi0/dphi
 template <typename R>
@@ -888,6 +900,14 @@ void launch_axpby(R* out, const R* x, const R* y, R alpha, R beta, int64_t n, hi
 }
 template void launch_axpby<double>(double*, const double*, const double*, double, double, int64_t, hipStream_t);
 template void launch_axpby<float>(float*, const float*, const float*, float, float, int64_t, hipStream_t);
+
+template <typename R>
+void launch_rev_seed(R* ya, R* rb, const R* yb, R alpha, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL((k_rev_seed<R>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ya, rb,
+                       yb, alpha, n);
+}
+template void launch_rev_seed<double>(double*, double*, const double*, double, int64_t, hipStream_t);
+template void launch_rev_seed<float>(float*, float*, const float*, float, int64_t, hipStream_t);
 
 template <typename R>
 void launch_reset_adj(R* phib, const R* psi0b, const R* phi, int64_t n, int mode, double eps_w,

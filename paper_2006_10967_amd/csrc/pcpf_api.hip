@@ -450,6 +450,7 @@ UPArgs<R> up_args(const Ctx<R>& C) {
         a.Fp[v] = C.fplane(c->L.Fp, v);
         a.Fm[v] = C.fplane(c->L.Fm, v);
         a.un[v] = C.plane(c->L.un, v);
+        a.uo[v] = nullptr;
         a.acc[v] = C.plane(c->L.acc, v);
         a.us[v] = C.plane(c->L.us, v);
         a.res[v] = nullptr;
@@ -624,12 +625,18 @@ pcpf_status precondition_impl(const Ctx<R>& C, int iters, R* store_psi0 = nullpt
 }
 
 // One classic RK4 step of the stored state. With y_store set (the checkpointed recompute),
-// the input of stage s is kept in y_store[2*s + v].
+// the input of stage s is kept in y_store[2*s + v]; y_next, if set, receives u_{n+1} from the
+// last stage as well (the stage-0 input of the next recomputed step), and y0_filled says that
+// y_store[0..1] was filled that way by the previous step. A reset at this step changes psi
+// before stage 0, so then stage 0's input is copied in any case.
 template <typename R>
-pcpf_status step_one(const Ctx<R>& C, double dt, R* const* y_store) {
+pcpf_status step_one(const Ctx<R>& C, double dt, R* const* y_store, R* const* y_next = nullptr,
+                     bool y0_filled = false) {
     pcpf_ctx* c = C.c;
     const int N = c->prm.reset_every;
+    bool reset = false;
     if (!c->has_psi || (N > 0 && c->step % N == 0)) {
+        reset = true;
         pcpf_status st = precondition_impl<R>(
             C, c->prm.precond_iters, static_cast<R*>(c->pc_store_psi0_v),
             c->pc_store_stage_v.empty() ? nullptr
@@ -639,7 +646,7 @@ pcpf_status step_one(const Ctx<R>& C, double dt, R* const* y_store) {
     }
     pcpf_status st = refresh_traces<R>(C);
     if (st != PCPF_OK) return st;
-    if (y_store) {
+    if (y_store && (reset || !y0_filled)) {
         const size_t bytes = (size_t)c->mi.E * c->mi.nu * sizeof(R);
         for (int v = 0; v < 2; ++v)
             HIPCHK(c, hipMemcpyAsync(y_store[v], C.plane(c->L.un, v), bytes,
@@ -655,6 +662,10 @@ pcpf_status step_one(const Ctx<R>& C, double dt, R* const* y_store) {
         if (y_store && s < 3) {
             u.us[0] = y_store[2 * (s + 1)];
             u.us[1] = y_store[2 * (s + 1) + 1];
+        }
+        if (y_next && s == 3) {
+            u.uo[0] = y_next[0];
+            u.uo[1] = y_next[1];
         }
         u.first = s == 0;
         u.last = s == 3;
@@ -1055,8 +1066,10 @@ pcpf_status adjoint_impl(const Ctx<R>& C, const void* d_ckpt, void* d_scratch,
             R* ys[8];
             for (int s = 0; s < 4; ++s)
                 for (int v = 0; v < 2; ++v) ys[2 * s + v] = at(A.seg) + ((size_t)i * 4 + s) * 2 * S + v * S;
+            // the next step's stage-0 slot, written by this step's last stage
+            R* yn[2] = {at(A.seg) + (size_t)(i + 1) * 4 * 2 * S, at(A.seg) + (size_t)(i + 1) * 4 * 2 * S + S};
             c->pc_reset_hit = false;
-            pcpf_status st = step_one<R>(C, dt, ys);
+            pcpf_status st = step_one<R>(C, dt, ys, i + 1 < nloc ? yn : nullptr, i > 0);
             if (st != PCPF_OK) return st;
             if (c->pc_reset_hit) {
                 if (reset_local >= 0)
@@ -1069,8 +1082,8 @@ pcpf_status adjoint_impl(const Ctx<R>& C, const void* d_ckpt, void* d_scratch,
         // reverse sweep over the segment
         for (int64_t i = nloc - 1; i >= 0; --i) {
             const double tn = c->ck_t0 + (double)(seg_start + i) * dt;
-            HIPCHK(c, hipMemcpyAsync(ya[0], yb[0], 2 * Sb, hipMemcpyDeviceToDevice, c->stream));
-            for (int v = 0; v < 2; ++v) launch_axpby<R>(rb[v], yb[v], nullptr, (R)(dt * RK_B[3]), R(0), (int64_t)S, c->stream);
+            // both planes of ya, rb and yb are contiguous (the swaps below exchange whole pairs)
+            launch_rev_seed<R>(ya[0], rb[0], yb[0], (R)(dt * RK_B[3]), 2 * (int64_t)S, c->stream);
             for (int s = 3; s >= 0; --s) {
                 R* Y[2] = {at(A.seg) + ((size_t)i * 4 + s) * 2 * S, at(A.seg) + ((size_t)i * 4 + s) * 2 * S + S};
                 pcpf_status st = adj_stage<R>(C, AD_PHYS, Y, rb, tn + RK_C[s] * dt, ub, tb, gp, nullptr,

@@ -18,6 +18,7 @@ struct Math<double> {
     __device__ static double sinpi_(double x) { return ::sinpi(x); }
     __device__ static double fabs_(double x) { return ::fabs(x); }
     __device__ static double rsqrt_(double x) { return ::rsqrt(x); }
+    __device__ static double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
 };
 template <>
 struct Math<float> {
@@ -28,6 +29,7 @@ struct Math<float> {
     __device__ static float sinpi_(float x) { return ::sinpif(x); }
     __device__ static float fabs_(float x) { return ::fabsf(x); }
     __device__ static float rsqrt_(float x) { return ::rsqrtf(x); }
+    __device__ static float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 };
 
 // Global accesses: a wave-uniform base pointer plus an unsigned 32-bit byte offset per

@@ -125,6 +125,7 @@ struct UPArgs {
     const R* Fp[2];
     const R* Fm[2];
     R* un[2];            // u_n (read; written on the last stage)
+    R* uo[2];            // null, or a second destination of u_{n+1} on the last stage
     R* acc[2];           // RK accumulator
     R* us[2];            // next stage input (written on stages 0-2)
     R* res[2];           // residual output (UP_RESID)

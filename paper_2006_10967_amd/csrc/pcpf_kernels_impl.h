@@ -878,14 +878,18 @@ __global__ __launch_bounds__((Shape<D, P>::NT)) void k_update(UPArgs<R> a) {
             if constexpr (KIND == UP_RESID) {
                 gst(a.res[v] + so, tid, res);
             } else {
+                // explicit fused multiply-adds: one rounding per register update, whatever
+                // the surrounding code lets the compiler contract
+                using M = Math<R>;
                 R nx;
                 if (!a.last) {
-                    gst(a.acc[v] + so, tid, rA[v] + a.bcoef * res);
-                    nx = rU[v] + a.ccoef * res;
+                    gst(a.acc[v] + so, tid, M::fma_(a.bcoef, res, rA[v]));
+                    nx = M::fma_(a.ccoef, res, rU[v]);
                     gst(a.us[v] + so, tid, nx);
                 } else {
-                    nx = rU[v] + a.ccoef * (rA[v] + a.bcoef * res);
+                    nx = M::fma_(a.ccoef, M::fma_(a.bcoef, res, rA[v]), rU[v]);
                     gst(a.un[v] + so, tid, nx);
+                    if (a.uo[0]) gst(a.uo[v] + so, tid, nx);
                 }
                 s_u[v][tid] = nx;
                 const R lim = (v == 0 && V == 2) ? R(10) : R(1e30);
