@@ -11,6 +11,8 @@ template <typename R>
 struct AJPush {
     const R* rbar[2];    // R^ of the stage (per variable, [E][NU])
     R* gp[2];            // out: flux adjoints pushed into the owners' + face slots
+    const R* u[2];       // stage input Y
+    R* Tp[2];            // out: forward - face traces of Y pushed into the owners' + face slots
     const R* geo;
     const int32_t* nbr;
     const R* ops;

@@ -8,10 +8,10 @@
 // other way round. The forward quantities of the stage (gradients, fluxes) are recomputed
 // from Y, never stored.
 //
-// Per stage: k_trace (forward traces of Y) -> k_adj_push (lifting adjoint of every - face
-// pushed to the owner of the face) -> k_adj_main (forward recompute + VJPs; trace adjoints
-// pushed to the neighbours' - face slots) -> k_adj_finish (adds the pushed trace adjoints
-// and performs the reverse RK4 combine).
+// Per stage: k_adj_push (lifting adjoint of every - face and the forward trace of Y on it,
+// both pushed to the owner of the face) -> k_adj_main (forward recompute + VJPs; trace
+// adjoints pushed to the neighbours' - face slots) -> k_adj_finish (adds the pushed trace
+// adjoints and performs the reverse RK4 combine).
 #include <cmath>
 
 #include "pcpf_adjoint.h"
@@ -25,7 +25,9 @@ using namespace dev;
 // ------------------------------------------------------------------------------------
 // k_adj_push: F~^ of the - faces. The residual of element e contains cm * F~_slot / |J|
 // with F~_slot = -F~_owner on faces that have an owner, so the owner's flux receives
-// sum_a cm[a] R^(line a) / |J_e|.
+// sum_a cm[a] R^(line a) / |J_e|. The same face points also carry the forward trace
+// sum_a lm[a] Y(line a) that the owner's gradient reads (what the forward update pushes),
+// so it is pushed here as well, in the same order of summation.
 // ------------------------------------------------------------------------------------
 template <typename R, int D, int P, int V>
 __global__ __launch_bounds__((AShape<D, P>::NT)) void k_adj_push(AJPush<R> a) {
@@ -35,7 +37,9 @@ __global__ __launch_bounds__((AShape<D, P>::NT)) void k_adj_push(AJPush<R> a) {
     constexpr int I_T = (EPB * NMF + NT - 1) / NT;
     constexpr int I_U = (EPB * NU + NT - 1) / NT;
     __shared__ R s_cm[N];
+    __shared__ R s_lm[N];
     __shared__ R s_r[V][EPB * NU];
+    __shared__ R s_y[V][EPB * NU];
     __shared__ R s_det[EPB];
     const int tid = threadIdx.x;
     const int64_t e0 = (int64_t)blockIdx.x * EPB;
@@ -47,23 +51,31 @@ __global__ __launch_bounds__((AShape<D, P>::NT)) void k_adj_push(AJPush<R> a) {
         const int el = it / NMF, k = (it - el * NMF) / NFA;
         r_own[j] = (it < nel * NMF) ? a.nbr[(e0 + el) * 2 * D + 2 * k] : -1;
     }
-    R r_r[V][I_U];
+    R r_r[V][I_U], r_y[V][I_U];
 #pragma unroll
     for (int v = 0; v < V; ++v)
 #pragma unroll
         for (int j = 0; j < I_U; ++j) {
             const int i = tid + j * NT;
             r_r[v][j] = (i < nel * NU) ? a.rbar[v][e0 * NU + i] : R(0);
+            r_y[v][j] = (i < nel * NU) ? a.u[v][e0 * NU + i] : R(0);
         }
     const R r_c = (tid < N) ? a.ops[op_cm(N) + tid] : R(0);
+    const R r_l = (tid < N) ? a.ops[op_lm(N) + tid] : R(0);
     const R r_d = (tid < nel) ? a.geo[(e0 + tid) * G + D + 2 * D * D] : R(1);
-    if (tid < N) s_cm[tid] = r_c;
+    if (tid < N) {
+        s_cm[tid] = r_c;
+        s_lm[tid] = r_l;
+    }
     if (tid < nel) s_det[tid] = r_d;
 #pragma unroll
     for (int v = 0; v < V; ++v)
 #pragma unroll
         for (int j = 0; j < I_U; ++j)
-            if (tid + j * NT < nel * NU) s_r[v][tid + j * NT] = r_r[v][j];
+            if (tid + j * NT < nel * NU) {
+                s_r[v][tid + j * NT] = r_r[v][j];
+                s_y[v][tid + j * NT] = r_y[v][j];
+            }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < I_T; ++j) {
@@ -74,10 +86,14 @@ __global__ __launch_bounds__((AShape<D, P>::NT)) void k_adj_push(AJPush<R> a) {
         const R rd = R(1) / s_det[el];
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            R acc = R(0);
+            R acc = R(0), tr = R(0);
 #pragma unroll
-            for (int q = 0; q < N; ++q) acc += s_cm[q] * s_r[v][base + q * st<N>(k)];
+            for (int q = 0; q < N; ++q) {
+                acc += s_cm[q] * s_r[v][base + q * st<N>(k)];
+                tr += s_lm[q] * s_y[v][base + q * st<N>(k)];
+            }
             a.gp[v][((int64_t)r_own[j] * D + k) * NFA + t] = acc * rd;
+            a.Tp[v][((int64_t)r_own[j] * D + k) * NFA + t] = tr;
         }
     }
 }

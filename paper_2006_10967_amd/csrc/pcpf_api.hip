@@ -919,12 +919,16 @@ pcpf_status adj_stage(const Ctx<R>& C, int mode, R* const* Y, R* const* rb, doub
     tr.nbr = C.template at<int32_t>(c->L.nbr);
     tr.ops = C.template at<R>(c->L.ops);
     tr.E = c->mi.E;
-    C.Lk().trace(nvar, tr, c->stream);
-    if (mode != AD_SIGN) {
+    if (mode == AD_SIGN) {
+        C.Lk().trace(nvar, tr, c->stream);
+    } else {
+        // the lifting-adjoint push also pushes the forward traces of Y
         AJPush<R> p{};
         for (int v = 0; v < nvar; ++v) {
             p.rbar[v] = rb[v];
             p.gp[v] = gp[v];
+            p.u[v] = Y[v];
+            p.Tp[v] = tr.Tp[v];
         }
         p.geo = C.template at<R>(c->L.geo);
         p.nbr = tr.nbr;
