@@ -17,6 +17,12 @@ struct AJPush {
     const int32_t* nbr;
     const R* ops;
     int64_t E;
+    // start of a reverse step (seed_yb set): R^ is not read but formed as seed_alpha * yb
+    // and written to seed_rb, and seed_ya receives a copy of yb
+    const R* seed_yb[2];
+    R* seed_ya[2];
+    R* seed_rb[2];
+    R seed_alpha;
 };
 
 template <typename R>
@@ -50,6 +56,12 @@ struct AJFinish {
     const R* ops;
     int64_t E;
     R c_prev, c_cur;
+    // optional: the push of the next (earlier) stage, whose R^ is rnext, run after the
+    // combine (ynext set; rnext must be set then)
+    const R* ynext[2];   // that stage's input Y
+    R* gp[2];
+    R* Tp[2];
+    const R* geo;
 };
 
 template <typename R>
@@ -62,11 +74,6 @@ struct AdjLaunchers {
 
 template <typename R>
 bool get_adj_launchers(int d, int p, AdjLaunchers<R>* out);
-template <typename R>
-void launch_axpby(R* out, const R* x, const R* y, R alpha, R beta, int64_t n, hipStream_t s);
-// ya[i] = yb[i], rb[i] = alpha yb[i] for i < n (ya, rb, yb each hold both variables)
-template <typename R>
-void launch_rev_seed(R* ya, R* rb, const R* yb, R alpha, int64_t n, hipStream_t s);
 template <typename R>
 void launch_reset_adj(R* phib, const R* psi0b, const R* phi, int64_t n, int mode, double eps_w,
                       double dphi, hipStream_t s);

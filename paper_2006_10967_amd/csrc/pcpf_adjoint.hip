@@ -23,18 +23,63 @@ namespace {
 using namespace dev;
 
 // ------------------------------------------------------------------------------------
-// k_adj_push: F~^ of the - faces. The residual of element e contains cm * F~_slot / |J|
-// with F~_slot = -F~_owner on faces that have an owner, so the owner's flux receives
-// sum_a cm[a] R^(line a) / |J_e|. The same face points also carry the forward trace
-// sum_a lm[a] Y(line a) that the owner's gradient reads (what the forward update pushes),
-// so it is pushed here as well, in the same order of summation.
+// Push of one stage: F~^ of the - faces. The residual of element e contains
+// cm * F~_slot / |J| with F~_slot = -F~_owner on faces that have an owner, so the owner's
+// flux receives sum_a cm[a] R^(line a) / |J_e|. The same face points also carry the forward
+// trace sum_a lm[a] Y(line a) that the owner's gradient reads (what the forward update
+// pushes), so it is pushed here as well, in the same order of summation. Shared by
+// k_adj_push and the tail of k_adj_finish: s_r / s_y hold R^ and Y of the block's elements.
 // ------------------------------------------------------------------------------------
+template <typename R, int D, int P, int V>
+__device__ __forceinline__ void owners_of_minus_faces(int32_t* r_own, const int32_t* nbr, int64_t e0,
+                                                      int nel, int tid) {
+    using S = AShape<D, P>;
+    constexpr int NMF = D * S::NFA;
+    constexpr int I_T = (S::EPB * NMF + S::NT - 1) / S::NT;
+#pragma unroll
+    for (int j = 0; j < I_T; ++j) {
+        const int it = tid + j * S::NT;
+        const int el = it / NMF, k = (it - el * NMF) / S::NFA;
+        r_own[j] = (it < nel * NMF) ? nbr[(e0 + el) * 2 * D + 2 * k] : -1;
+    }
+}
+
+template <typename R, int D, int P, int V>
+__device__ __forceinline__ void push_minus_faces(const R* s_cm, const R* s_lm, const R* const* s_r,
+                                                 const R* const* s_y, const R* s_det,
+                                                 const int32_t* r_own, R* const* gp, R* const* Tp,
+                                                 int nel, int tid) {
+    using S = AShape<D, P>;
+    constexpr int N = S::N, NU = S::NU, NFA = S::NFA;
+    constexpr int NMF = D * NFA;
+    constexpr int I_T = (S::EPB * NMF + S::NT - 1) / S::NT;
+#pragma unroll
+    for (int j = 0; j < I_T; ++j) {
+        const int it = tid + j * S::NT;
+        if (it >= nel * NMF || r_own[j] < 0) continue;
+        const int el = it / NMF, r = it - el * NMF, k = r / NFA, t = r - k * NFA;
+        const int base = el * NU + face_base<D, N>(k, t);
+        const R rd = R(1) / s_det[el];
+        using M = Math<R>;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            R acc = R(0), tr = R(0);
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+                acc = M::fma_(s_cm[q], s_r[v][base + q * st<N>(k)], acc);
+                tr = M::fma_(s_lm[q], s_y[v][base + q * st<N>(k)], tr);
+            }
+            gp[v][((int64_t)r_own[j] * D + k) * NFA + t] = acc * rd;
+            Tp[v][((int64_t)r_own[j] * D + k) * NFA + t] = tr;
+        }
+    }
+}
+
 template <typename R, int D, int P, int V>
 __global__ __launch_bounds__((AShape<D, P>::NT)) void k_adj_push(AJPush<R> a) {
     using S = AShape<D, P>;
     constexpr int N = S::N, NU = S::NU, NFA = S::NFA, EPB = S::EPB, NT = S::NT, G = S::GEO;
-    constexpr int NMF = D * NFA;
-    constexpr int I_T = (EPB * NMF + NT - 1) / NT;
+    constexpr int I_T = (EPB * D * NFA + NT - 1) / NT;
     constexpr int I_U = (EPB * NU + NT - 1) / NT;
     __shared__ R s_cm[N];
     __shared__ R s_lm[N];
@@ -45,21 +90,35 @@ __global__ __launch_bounds__((AShape<D, P>::NT)) void k_adj_push(AJPush<R> a) {
     const int64_t e0 = (int64_t)blockIdx.x * EPB;
     const int nel = (int)((a.E - e0) < EPB ? (a.E - e0) : EPB);
     int32_t r_own[I_T];
-#pragma unroll
-    for (int j = 0; j < I_T; ++j) {
-        const int it = tid + j * NT;
-        const int el = it / NMF, k = (it - el * NMF) / NFA;
-        r_own[j] = (it < nel * NMF) ? a.nbr[(e0 + el) * 2 * D + 2 * k] : -1;
-    }
+    owners_of_minus_faces<R, D, P, V>(r_own, a.nbr, e0, nel, tid);
+    const bool seed = a.seed_yb[0] != nullptr;
     R r_r[V][I_U], r_y[V][I_U];
 #pragma unroll
     for (int v = 0; v < V; ++v)
 #pragma unroll
         for (int j = 0; j < I_U; ++j) {
             const int i = tid + j * NT;
-            r_r[v][j] = (i < nel * NU) ? a.rbar[v][e0 * NU + i] : R(0);
+            if (seed) {
+                r_r[v][j] = (i < nel * NU) ? a.seed_yb[v][e0 * NU + i] : R(0);
+            } else {
+                r_r[v][j] = (i < nel * NU) ? a.rbar[v][e0 * NU + i] : R(0);
+            }
             r_y[v][j] = (i < nel * NU) ? a.u[v][e0 * NU + i] : R(0);
         }
+    if (seed) {
+        // ya <- yb, R^ = alpha yb + 0 (as the axpby of the plain sweep)
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+#pragma unroll
+            for (int j = 0; j < I_U; ++j) {
+                const int i = tid + j * NT;
+                if (i < nel * NU) {
+                    a.seed_ya[v][e0 * NU + i] = r_r[v][j];
+                    r_r[v][j] = a.seed_alpha * r_r[v][j] + R(0);
+                    a.seed_rb[v][e0 * NU + i] = r_r[v][j];
+                }
+            }
+    }
     const R r_c = (tid < N) ? a.ops[op_cm(N) + tid] : R(0);
     const R r_l = (tid < N) ? a.ops[op_lm(N) + tid] : R(0);
     const R r_d = (tid < nel) ? a.geo[(e0 + tid) * G + D + 2 * D * D] : R(1);
@@ -77,25 +136,14 @@ __global__ __launch_bounds__((AShape<D, P>::NT)) void k_adj_push(AJPush<R> a) {
                 s_y[v][tid + j * NT] = r_y[v][j];
             }
     __syncthreads();
+    const R* sr[V];
+    const R* sy[V];
 #pragma unroll
-    for (int j = 0; j < I_T; ++j) {
-        const int it = tid + j * NT;
-        if (it >= nel * NMF || r_own[j] < 0) continue;
-        const int el = it / NMF, r = it - el * NMF, k = r / NFA, t = r - k * NFA;
-        const int base = el * NU + face_base<D, N>(k, t);
-        const R rd = R(1) / s_det[el];
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-            R acc = R(0), tr = R(0);
-#pragma unroll
-            for (int q = 0; q < N; ++q) {
-                acc += s_cm[q] * s_r[v][base + q * st<N>(k)];
-                tr += s_lm[q] * s_y[v][base + q * st<N>(k)];
-            }
-            a.gp[v][((int64_t)r_own[j] * D + k) * NFA + t] = acc * rd;
-            a.Tp[v][((int64_t)r_own[j] * D + k) * NFA + t] = tr;
-        }
+    for (int v = 0; v < V; ++v) {
+        sr[v] = s_r[v];
+        sy[v] = s_y[v];
     }
+    push_minus_faces<R, D, P, V>(s_cm, s_lm, sr, sy, s_det, r_own, a.gp, a.Tp, nel, tid);
 }
 
 // ------------------------------------------------------------------------------------
@@ -752,13 +800,19 @@ __global__ __launch_bounds__((AShape<D, P>::NT)) void k_adj_main(AJMain<R> a) {
 template <typename R, int D, int P, int V>
 __global__ __launch_bounds__((AShape<D, P>::NT)) void k_adj_finish(AJFinish<R> a) {
     using S = AShape<D, P>;
-    constexpr int N = S::N, NU = S::NU, NFA = S::NFA, EPB = S::EPB, NT = S::NT;
+    constexpr int N = S::N, NU = S::NU, NFA = S::NFA, EPB = S::EPB, NT = S::NT, G = S::GEO;
+    constexpr int I_T = (EPB * D * NFA + NT - 1) / NT;
     __shared__ R s_lm[N];
+    __shared__ R s_cm[N];
     __shared__ int s_nbr[EPB * 2 * D];
+    __shared__ R s_r[V][EPB * NU];
+    __shared__ R s_y[V][EPB * NU];
+    __shared__ R s_det[EPB];
     const int tid = threadIdx.x;
     const int64_t e0 = (int64_t)blockIdx.x * EPB;
     const int nel = (int)((a.E - e0) < EPB ? (a.E - e0) : EPB);
     const bool pt = tid < nel * NU;
+    const bool push = a.ynext[0] != nullptr;
     const int le = tid / NU;
     const int ip = tid - le * NU;
     const int64_t idx = (e0 + le) * NU + ip;
@@ -769,53 +823,70 @@ __global__ __launch_bounds__((AShape<D, P>::NT)) void k_adj_finish(AJFinish<R> a
         const int i = tid + j * NT;
         r_n[j] = (i < nel * 2 * D) ? a.nbr[e0 * 2 * D + i] : -1;
     }
+    // inputs of the next stage's push
+    int32_t r_own[I_T];
+    R r_y[V];
+    if (push) {
+        owners_of_minus_faces<R, D, P, V>(r_own, a.nbr, e0, nel, tid);
+#pragma unroll
+        for (int v = 0; v < V; ++v) r_y[v] = pt ? a.ynext[v][idx] : R(0);
+        const R r_c = (tid < N) ? a.ops[op_cm(N) + tid] : R(0);
+        const R r_d = (tid < nel) ? a.geo[(e0 + tid) * G + D + 2 * D * D] : R(1);
+        if (tid < N) s_cm[tid] = r_c;
+        if (tid < nel) s_det[tid] = r_d;
+    }
     if (tid < N) s_lm[tid] = r_l;
 #pragma unroll
     for (int j = 0; j < (EPB * 2 * D + NT - 1) / NT; ++j)
         if (tid + j * NT < nel * 2 * D) s_nbr[tid + j * NT] = r_n[j];
     __syncthreads();
-    if (!pt) return;
-    int mi[D];
-    {
-        int r = ip;
+    if (pt) {
+        int mi[D];
+        {
+            int r = ip;
 #pragma unroll
-        for (int k = 0; k < D; ++k) {
-            mi[k] = r % N;
-            r /= N;
+            for (int k = 0; k < D; ++k) {
+                mi[k] = r % N;
+                r /= N;
+            }
+        }
+        // explicit fused multiply-adds: the rounding does not depend on what the surrounding
+        // code lets the compiler contract
+        using M = Math<R>;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            R y = a.ub[v][idx];
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                if (s_nbr[le * 2 * D + 2 * k] < 0) continue;
+                const int tk = tang_index<D, N>(k, mi);
+                y = M::fma_(s_lm[mi[k]], a.tb[v][((e0 + le) * D + k) * NFA + tk], y);
+            }
+            if (a.ya[v]) a.ya[v][idx] += y;
+            if (a.rnext[v]) {
+                const R rn = M::fma_(a.c_cur, y, a.c_prev * a.yb[v][idx]);
+                a.rnext[v][idx] = rn;
+                if (push) {
+                    s_r[v][tid] = rn;
+                    s_y[v][tid] = r_y[v];
+                }
+            }
         }
     }
+    if (!push) return;
+    // the push of the next stage: its R^ is rnext of this block's own points
+    __syncthreads();
+    const R* sr[V];
+    const R* sy[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-        R y = a.ub[v][idx];
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            if (s_nbr[le * 2 * D + 2 * k] < 0) continue;
-            const int tk = tang_index<D, N>(k, mi);
-            y += s_lm[mi[k]] * a.tb[v][((e0 + le) * D + k) * NFA + tk];
-        }
-        if (a.ya[v]) a.ya[v][idx] += y;
-        if (a.rnext[v]) a.rnext[v][idx] = a.c_prev * a.yb[v][idx] + a.c_cur * y;
+        sr[v] = s_r[v];
+        sy[v] = s_y[v];
     }
+    push_minus_faces<R, D, P, V>(s_cm, s_lm, sr, sy, s_det, r_own, a.gp, a.Tp, nel, tid);
 }
 
 // elementwise helpers of the reverse sweep
-template <typename R>
-__global__ void k_axpby(R* out, const R* x, const R* y, R alpha, R beta, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = alpha * x[i] + (y ? beta * y[i] : R(0));
-}
-
-// Start of a reverse step, both variables in one pass: ya <- yb (the running adjoint of u_n)
-// and rb <- alpha yb (the adjoint of the last stage's residual), as a copy and an axpby.
-template <typename R>
-__global__ void k_rev_seed(R* ya, R* rb, const R* yb, R alpha, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) {
-        const R y = yb[i];
-        ya[i] = y;
-        rb[i] = alpha * y + R(0);
-    }
-}
 
 // adjoint of the reset psi0 = phi - 1/2 (LINEAR) or eps_w ln(c / (1 - c)) (LOGIT):
 // phi^ += psi0^ dpsi0/dphi
@@ -909,21 +980,6 @@ bool get_adj_launchers(int d, int p, AdjLaunchers<R>* L) {
 template bool get_adj_launchers<double>(int, int, AdjLaunchers<double>*);
 template bool get_adj_launchers<float>(int, int, AdjLaunchers<float>*);
 
-template <typename R>
-void launch_axpby(R* out, const R* x, const R* y, R alpha, R beta, int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL((k_axpby<R>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, x, y,
-                       alpha, beta, n);
-}
-template void launch_axpby<double>(double*, const double*, const double*, double, double, int64_t, hipStream_t);
-template void launch_axpby<float>(float*, const float*, const float*, float, float, int64_t, hipStream_t);
-
-template <typename R>
-void launch_rev_seed(R* ya, R* rb, const R* yb, R alpha, int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL((k_rev_seed<R>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ya, rb,
-                       yb, alpha, n);
-}
-template void launch_rev_seed<double>(double*, double*, const double*, double, int64_t, hipStream_t);
-template void launch_rev_seed<float>(float*, float*, const float*, float, int64_t, hipStream_t);
 
 template <typename R>
 void launch_reset_adj(R* phib, const R* psi0b, const R* phi, int64_t n, int mode, double eps_w,

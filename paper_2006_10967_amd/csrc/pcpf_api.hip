@@ -902,12 +902,26 @@ const AdjLaunchers<double>& adj_launchers<double>(const pcpf_ctx* c) { return c-
 template <>
 const AdjLaunchers<float>& adj_launchers<float>(const pcpf_ctx* c) { return c->A32; }
 
+// Reverse-sweep options of one stage: where its push (lifting adjoint and forward traces of
+// Y, to the faces' owners) runs, and whether the stage starts a reverse step.
+template <typename R>
+struct AdjStageOpt {
+    bool push = true;                 // launch the push first (false: the previous stage's
+                                      // finish has done it)
+    const R* const* seed_yb = nullptr;  // start of a reverse step: ya <- yb, R^ = alpha yb
+    R* const* seed_ya = nullptr;
+    double seed_alpha = 0.0;
+    R* const* ynext = nullptr;        // the next stage's input: its push runs at the end of
+                                      // this stage's finish (rnext must be set)
+};
+
 // One stage of the reverse sweep: Y^ = (dR/dY)^T R^ for the stage input Y (nvar planes);
 // then ya += Y^ and rnext = c_prev yb + c_cur Y^ (either may be null).
 template <typename R>
 pcpf_status adj_stage(const Ctx<R>& C, int mode, R* const* Y, R* const* rb, double t, R* const* ub,
                       R* const* tb, R* const* gp, R* sb, R* const* ya, R* const* rnext,
-                      R* const* yb, double c_prev, double c_cur, double* apart) {
+                      R* const* yb, double c_prev, double c_cur, double* apart,
+                      const AdjStageOpt<R>& opt = AdjStageOpt<R>()) {
     pcpf_ctx* c = C.c;
     const int nvar = mode == AD_PHYS ? 2 : 1;
     const AdjLaunchers<R>& AL = adj_launchers<R>(c);
@@ -921,7 +935,7 @@ pcpf_status adj_stage(const Ctx<R>& C, int mode, R* const* Y, R* const* rb, doub
     tr.E = c->mi.E;
     if (mode == AD_SIGN) {
         C.Lk().trace(nvar, tr, c->stream);
-    } else {
+    } else if (opt.push) {
         // the lifting-adjoint push also pushes the forward traces of Y
         AJPush<R> p{};
         for (int v = 0; v < nvar; ++v) {
@@ -929,7 +943,13 @@ pcpf_status adj_stage(const Ctx<R>& C, int mode, R* const* Y, R* const* rb, doub
             p.gp[v] = gp[v];
             p.u[v] = Y[v];
             p.Tp[v] = tr.Tp[v];
+            if (opt.seed_yb) {
+                p.seed_yb[v] = opt.seed_yb[v];
+                p.seed_ya[v] = opt.seed_ya[v];
+                p.seed_rb[v] = rb[v];
+            }
         }
+        p.seed_alpha = (R)opt.seed_alpha;
         p.geo = C.template at<R>(c->L.geo);
         p.nbr = tr.nbr;
         p.ops = tr.ops;
@@ -969,6 +989,14 @@ pcpf_status adj_stage(const Ctx<R>& C, int mode, R* const* Y, R* const* rb, doub
     f.E = c->mi.E;
     f.c_prev = (R)c_prev;
     f.c_cur = (R)c_cur;
+    if (opt.ynext) {
+        for (int v = 0; v < nvar; ++v) {
+            f.ynext[v] = opt.ynext[v];
+            f.gp[v] = gp[v];
+            f.Tp[v] = tr.Tp[v];
+        }
+        f.geo = C.template at<R>(c->L.geo);
+    }
     AL.finish(nvar, f, c->stream);
     return launch_status<R>(c);
 }
@@ -1086,14 +1114,27 @@ pcpf_status adjoint_impl(const Ctx<R>& C, const void* d_ckpt, void* d_scratch,
         // reverse sweep over the segment
         for (int64_t i = nloc - 1; i >= 0; --i) {
             const double tn = c->ck_t0 + (double)(seg_start + i) * dt;
-            // both planes of ya, rb and yb are contiguous (the swaps below exchange whole pairs)
-            launch_rev_seed<R>(ya[0], rb[0], yb[0], (R)(dt * RK_B[3]), 2 * (int64_t)S, c->stream);
+            // stage 4's push also seeds the step (ya <- yb, rb <- dt b_4 yb); each later
+            // stage's push runs at the end of the previous stage's finish
             for (int s = 3; s >= 0; --s) {
                 R* Y[2] = {at(A.seg) + ((size_t)i * 4 + s) * 2 * S, at(A.seg) + ((size_t)i * 4 + s) * 2 * S + S};
+                R* Yn[2] = {nullptr, nullptr};
+                if (s > 0) {
+                    Yn[0] = at(A.seg) + ((size_t)i * 4 + s - 1) * 2 * S;
+                    Yn[1] = Yn[0] + S;
+                }
+                AdjStageOpt<R> opt;
+                opt.push = s == 3;
+                if (s == 3) {
+                    opt.seed_yb = yb;
+                    opt.seed_ya = ya;
+                    opt.seed_alpha = dt * RK_B[3];
+                }
+                opt.ynext = s > 0 ? Yn : nullptr;
                 pcpf_status st = adj_stage<R>(C, AD_PHYS, Y, rb, tn + RK_C[s] * dt, ub, tb, gp, nullptr,
                                               ya, s > 0 ? rb : nullptr, yb,
                                               s > 0 ? dt * RK_B[s - 1] : 0.0, s > 0 ? dt * RK_C[s] : 0.0,
-                                              apart);
+                                              apart, opt);
                 if (st != PCPF_OK) return st;
             }
             std::swap(yb[0], ya[0]);
@@ -1105,8 +1146,6 @@ pcpf_status adjoint_impl(const Ctx<R>& C, const void* d_ckpt, void* d_scratch,
                 HIPCHK(c, hipMemsetAsync(sb, 0, Sb, c->stream));
                 R* pbv[1] = {pb};
                 for (int k = K - 1; k >= 0; --k) {
-                    HIPCHK(c, hipMemcpyAsync(pa, pb, Sb, hipMemcpyDeviceToDevice, c->stream));
-                    launch_axpby<R>(prb, pb, nullptr, (R)(dtau * RK_B[3]), R(0), (int64_t)S, c->stream);
                     R* pav[1] = {pa};
                     R* prv[1] = {prb};
                     R* ubv[1] = {ub[0]};
@@ -1115,10 +1154,19 @@ pcpf_status adjoint_impl(const Ctx<R>& C, const void* d_ckpt, void* d_scratch,
                     pbv[0] = pb;
                     for (int s = 3; s >= 0; --s) {
                         R* Y[1] = {pre_stage[(size_t)k * 4 + s]};
+                        R* Yn[1] = {s > 0 ? pre_stage[(size_t)k * 4 + s - 1] : nullptr};
+                        AdjStageOpt<R> opt;
+                        opt.push = s == 3;
+                        if (s == 3) {
+                            opt.seed_yb = pbv;
+                            opt.seed_ya = pav;
+                            opt.seed_alpha = dtau * RK_B[3];
+                        }
+                        opt.ynext = s > 0 ? Yn : nullptr;
                         pcpf_status st = adj_stage<R>(C, AD_PRECOND, Y, prv, c->t, ubv, tbv, gpv, sb, pav,
                                                       s > 0 ? prv : nullptr, pbv,
                                                       s > 0 ? dtau * RK_B[s - 1] : 0.0,
-                                                      s > 0 ? dtau * RK_C[s] : 0.0, apart);
+                                                      s > 0 ? dtau * RK_C[s] : 0.0, apart, opt);
                         if (st != PCPF_OK) return st;
                     }
                     std::swap(pb, pa);
