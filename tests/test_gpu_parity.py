@@ -59,6 +59,10 @@ CASES = [
     ("3d_p2_copybc", 3, 2, (3, 4, 5), dict(periodic=False, vel_u0=(0.3, 0.2, -0.5))),
     ("3d_p1", 3, 1, (6, 5, 4), dict(vel_u0=(0.3, 0.2, -0.5))),
     ("3d_p5", 3, 5, (3, 2, 3), dict(vel_kind=W.VEL_LEVEQUE3D, vel_period=3.0)),
+    # walls in some directions only: most - faces have a neighbour, some lie on a wall
+    ("2d_p4_mixed_bc", 2, 4, (9, 7), dict(periodic=(True, False), vel_u0=(0.7, -0.3))),
+    ("3d_p3_mixed_bc", 3, 3, (4, 5, 3), dict(periodic=(False, True, False),
+                                             vel_u0=(0.3, -0.4, 0.2))),
 ]
 
 
@@ -79,7 +83,8 @@ def test_physical_residual_parity(cid, d, p, shape, kw, kind):
 
 PC_CASES = [c for c in CASES if c[0] in ("2d_p3_uniform", "2d_p4_vortex_ragged",
                                          "2d_p3_copybc_rotation", "3d_p3_leveque_ragged",
-                                         "3d_p4_perturbed", "3d_p2_copybc", "2d_single_element")]
+                                         "3d_p4_perturbed", "3d_p2_copybc", "2d_single_element",
+                                         "3d_p3_mixed_bc")]
 
 
 @pytest.mark.parametrize("cid,d,p,shape,kw", PC_CASES, ids=[c[0] for c in PC_CASES])
@@ -145,6 +150,24 @@ def test_trajectory_parity_advection_200_steps():
     assert abs(s.mass() - m0) / m0 <= 1e-12
     assert abs(m0 - float(o.mass(phi0))) <= 1e-14 * abs(m0)
     assert abs(s.l1(phi0) - float(o.l1(phi_g.cpu(), phi0))) <= 1e-13
+
+
+def test_trajectory_parity_mixed_walls():
+    """Periodic in x, walls in y (9x7 quads, p=4): reset + 3 pseudo iterations, then 30 RK4
+    steps with a reset at step 20; phi and psi match the oracle to 1e-10."""
+    mesh, prm = W.small_case(2, 4, (9, 7), periodic=(True, False), vel_u0=(0.7, -0.3),
+                             precond_iters=3, reset_every=20)
+    o = Oracle(2, 4, mesh, prm)
+    s = _solver(mesh, 4, prm)
+    x = o.coords()
+    phi0 = torch.tensor(W.ic_phi(x, np.array([0.45, 0.5]), 0.25, 0.05))
+    dt = 0.005          # dt |v| / h = 0.034, half the RK4 limit at p = 4
+    phi_o, psi_o, _ = o.run(phi0, None, 0.0, dt, 30)
+    s.set_state(phi0)
+    s.step(dt, 30)
+    phi_g, psi_g, _, _ = s.get_state()
+    assert _rel(phi_g, phi_o) <= 1e-10
+    assert _rel(psi_g, psi_o) <= 1e-10
 
 
 def test_full_size_vortex_residual():
