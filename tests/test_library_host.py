@@ -24,6 +24,22 @@ def test_exports_every_declared_symbol():
     assert lib.pcpf_abi_version() == 1
 
 
+def test_missing_library_fails_loudly(tmp_path):
+    """There is no fallback: without the built library the binding raises instead of
+    computing anything (checked in a fresh process, since the path is read at import)."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, PCPF_LIBRARY=str(tmp_path / "absent" / "libpcpf.so"))
+    code = ("from paper_2006_10967_amd import _lib\n"
+            "try:\n    _lib.load()\nexcept ImportError as e:\n    print('raised:', e)\n")
+    r = subprocess.run([sys.executable, "-c", code], env=env, cwd=root, capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
+    assert "raised:" in r.stdout and "missing" in r.stdout, r.stdout
+
+
 def test_binding_constants_match_the_header():
     """Every PCPF_* constant that the binding defines has the header's value."""
     import os
