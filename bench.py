@@ -1,18 +1,33 @@
 #!/usr/bin/env python3
 """Throughput of the FR-PCPF RK4 step on one MI355X.
 
-Workload: 2D unit square, 128x128 affine quads, p = 4 (25 Gauss-Legendre points per
-element, 409 600 DOF), time-reversing single-vortex velocity (T = 8), tanh circle r = 0.15
-at (0.5, 0.75), CFL 0.05, reset + 10 pseudo-time iterations of the preconditioner before
-every step whose index is a multiple of 1000 (the timed region starts at step 0, so it
-contains one). A step is one classic RK4 step of the whole path (4 x [grad_flux + update]
-plus the scheduled reset/preconditioning). Inputs are resident in device memory before
-the timed region starts.
+Headline workload: the 3D deformation test of §4.3 on the unit cube, 96^3 affine hexes whose
+interior grid planes are shifted by U(-0.2h, 0.2h) (seed 1), p = 4 (125 Gauss-Legendre
+points per element, 110 592 000 DOF), LeVeque field with T = 3, sphere r = 0.15 at
+(0.35, 0.35, 0.35), CFL 0.03 on the smallest spacing. It is the largest of the benchmark
+configurations that fits one GPU, and the one the BF16 form is quoted on.
 
-Prints ONE JSON line: value = DOF-stage updates per second of the FP64 form (E*N_u*4*K /
-wall time of K steps), with the FP32 form, the per-kernel roofline (HIP events around
-every launch of a second, identical timed region), and the CPU oracle on a bounded sample
-of the same workload.
+A step is one classic RK4 step of the whole path: 4 x [grad_flux + update]. The reset
+and the preconditioning (10 pseudo-time RK4 iterations) run before step 0; the timed
+region starts after them and after the warm-up steps, so it holds K plain steps (a reset
+lands inside only if the region crosses a multiple of the reset interval, 1000). The reset
++ preconditioning is timed on its own and reported beside. Inputs are resident in device
+memory before the timed region starts.
+
+Prints ONE JSON line:
+  value        DOF-stage updates per second of the FP64 form, E N_u 4 K / wall time;
+  forms        the FP32 and BF16 forms on the same workload: rate, speed-up, and after
+               100 steps from the same initial state the interface L1 difference
+               int|phi_form - phi_64| and the mass drift of each form;
+  roofline     the RK stage (grad_flux + update, HIP events around every launch of a
+               second timed region) against HBM: algorithmic bytes per stage
+               (5 V N_u + 2 V N_f words per element) over the stage's kernel time, with
+               the two-launch implementation's bytes and the counter-measured bytes beside;
+  legs         the same measurements on the 64^3 p = 3 deformation workload and the
+               128^2 p = 4 single-vortex workload (cache-resident), and the adjoint
+               workload (64^2 p = 3, checkpoints every 32 of 512 steps);
+  cpu_baseline the FP64 oracle on the host cores on an 8^3 sub-mesh of the same kind
+               (the full mesh does not fit a bounded CPU run).
 """
 from __future__ import annotations
 
@@ -32,31 +47,39 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "DOF-stage updates/s FP64 vs FP32/BF16 at equal interface L1 error; adjoint s/step"
 UNIT = "DOF-stage updates/s"
 PROFILES = os.path.join(ROOT, "profiles")
+WORD = {"fp64": 8, "fp32": 4, "bf16": 4}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_bytes(d, p, word, kind):
-    """Algorithmic bytes per element of one launch (inputs read + outputs written once)."""
+def sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def stage_words(d, p):
+    """Words per element of one RK stage.
+
+    alg:  5 V N_u + 2 V N_f (read the stage input and u_n, read and write the accumulator,
+          write the next stage input; write and read the face traces and common fluxes);
+    impl: what the two launches of a stage read and write, averaged over the four stages
+          (the accumulator is not read on stage 1 nor written on stage 4): grad_flux reads
+          u and the pushed traces and writes the partial divergence and the common fluxes
+          of its + faces (its own slot and the neighbour's); update reads those, u_n and the
+          accumulator and writes the accumulator, the next stage input and its - face traces.
+    """
     n = p + 1
-    nu, nfa = n ** d, n ** (d - 1)
     V = 2
+    nu, nfa = n ** d, n ** (d - 1)
+    nf = 2 * d * nfa
+    npf = d * nfa
     geo = d + 2 * d * d + 1
-    if kind == "grad_flux":
-        words = V * nu + V * d * nfa + geo + V * nu + V * d * nfa
-    else:  # update, averaged over the four stages (acc is not read on stage 1, not written on 4)
-        words = V * nu + 2 * V * d * nfa + 1 + V * nu + 0.75 * V * nu + 0.75 * V * nu + V * nu \
-            + V * d * nfa
-    return words * word
-
-
-def step_alg_bytes_per_dof(d, p, word):
-    """B_alg per DOF-stage: RK4 registers (5 V N_u) + two face exchanges (2 V N_f)."""
-    n = p + 1
-    nu, nf = n ** d, 2 * d * n ** (d - 1)
-    return (5 * 2 * nu + 2 * 2 * nf) * word / nu
+    alg = 5 * V * nu + 2 * V * nf
+    gf = V * nu + V * npf + geo + V * nu + 2 * V * npf
+    up = V * nu + 2 * V * npf + 1 + V * nu + 0.75 * V * nu + 0.75 * V * nu + V * nu + V * npf
+    return {"alg": alg, "impl": gf + up, "grad_flux": gf, "update": up}
 
 
 def kernel_source_hash():
@@ -68,62 +91,191 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def make_solver(cfg, mesh, precision):
+def make_solver(cfg, mesh, precision, prm=None):
     from paper_2006_10967_amd import Solver
-    return Solver.from_box(mesh, cfg.order, cfg.params, precision=precision, device="cuda:0")
+    return Solver.from_box(mesh, cfg.order, prm or cfg.params, precision=precision,
+                           device="cuda:0")
 
 
-def run_form(cfg, mesh, precision, steps, warmup, phi0_np):
+def initial_state(cfg, mesh):
+    import workloads as W
+    from paper_2006_10967_amd import MeshArgs
+    period = [float(mesh.period[k]) if mesh.periodic[k] else 0.0 for k in range(cfg.ndims)]
+    x = MeshArgs(cfg.ndims, cfg.order, mesh.x0, mesh.jac, mesh.nbr, period).solution_coords()
+    return W.ic_phi(x, cfg.centre, cfg.radius, cfg.params.eps_w)
+
+
+def run_form(cfg, mesh, phi0_np, precision, K, Wm, acc_steps):
+    """One form on one workload: the timed K-step region, a second K-step region with HIP
+    events around every launch, the reset + preconditioning alone, and a separate
+    acc_steps-step run from the initial state whose final phi is returned (on the device,
+    in float64) for the interface comparison."""
     import torch
     s = make_solver(cfg, mesh, precision)
     dt = cfg.dt(mesh)
     phi0 = torch.as_tensor(phi0_np).to("cuda:0", s.dtype)
-    # warm-up (includes a reset + preconditioning at step 0)
+    # reset + preconditioning (step 0 is on the schedule), then the warm-up steps
     s.set_state(phi0, None, 0.0, 0)
-    s.step(dt, warmup)
-    # timed region: K steps from step 0 (one reset + preconditioning inside)
-    s.set_state(phi0, None, 0.0, 0)
-    torch.cuda.synchronize()
+    s.step(dt, 1 + Wm)
+    sync()
     t0 = time.perf_counter()
-    s.step(dt, steps)
-    torch.cuda.synchronize()
+    s.step(dt, K)
+    sync()
     wall = time.perf_counter() - t0
-    phi_end = s.get_state(want_psi=False)[0].clone()
-    # the same region again with HIP events around every launch (per-kernel durations)
-    s.set_state(phi0, None, 0.0, 0)
+    # the next K steps with per-launch events (kernel durations)
     s.kernel_times(reset=True)
     s.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s.step(dt, steps)
-    torch.cuda.synchronize()
-    wall_ev = time.perf_counter() - t0
+    sync()
+    s.step(dt, K)
+    sync()
     s.set_timing(False)
     kt = s.kernel_times(reset=True)
-    # preconditioning alone (reset + K pseudo iterations)
-    torch.cuda.synchronize()
+    # the reset + preconditioning alone
+    sync()
     t0 = time.perf_counter()
     s.precondition()
-    torch.cuda.synchronize()
+    sync()
     pc_ms = (time.perf_counter() - t0) * 1e3
-    return s, wall, wall_ev, kt, pc_ms, phi_end
+    # accuracy run
+    phi_acc = None
+    if acc_steps > 0:
+        s.set_state(phi0, None, 0.0, 0)
+        s.step(dt, acc_steps)
+        phi_acc = s.get_state(want_psi=False)[0].double()
+    mass_fn = s.mass
+    res = {"wall": wall, "kt": kt, "pc_ms": pc_ms}
+    return s, res, phi_acc, mass_fn
 
 
-def cpu_baseline(cfg, mesh, phi0_np, nsteps):
-    """The FP64 CPU oracle (test infrastructure) on a bounded sample of the same workload:
-    one reset + preconditioning and nsteps RK4 steps of the full mesh."""
+def load_traffic(workload, precision, hsh):
+    """Counter-measured HBM bytes per launch of grad_flux and update on a workload,
+    recorded in profiles/traffic_<workload>.json for the kernel sources of hash hsh (else
+    None)."""
+    try:
+        with open(os.path.join(PROFILES, f"traffic_{workload}.json")) as fh:
+            data = json.load(fh)
+    except OSError:
+        return None
+    if data.get("kernel_source_hash") != hsh:
+        return None
+    per = data.get("per_launch_bytes", {})
+    if isinstance(per.get(precision), dict):
+        per = per[precision]
+    elif precision != "fp64":
+        return None
+    if "grad_flux" not in per or "update" not in per:
+        return None
+    return {"grad_flux": per["grad_flux"], "update": per["update"],
+            "stage": per["grad_flux"] + per["update"]}
+
+
+def workload_leg(name, forms, K, Wm, acc_steps, hsh):
+    """Rates, roofline and interface comparison of the given forms on one workload."""
     import torch
+    import workloads as W
+    cfg = W.config(name)
+    mesh = cfg.mesh()
+    phi0 = initial_state(cfg, mesh)
+    words = stage_words(cfg.ndims, cfg.order)
+    log(f"[bench] {cfg.name}: E={cfg.nelem} N_u={cfg.nupts} DOF={cfg.dof} K={K} warmup={Wm}")
+    out = {"workload": cfg.name, "description": cfg.description, "elements": cfg.nelem,
+           "order": cfg.order, "dof": cfg.dof, "dt": cfg.dt(mesh),
+           "reset_every": cfg.params.reset_every, "precond_iters": cfg.params.precond_iters,
+           "forms": {}}
+    ref = None
+    for form in forms:
+        s, r, phi_acc, _ = run_form(cfg, mesh, phi0, form, K, Wm, acc_steps)
+        rate = cfg.dof * 4 * K / r["wall"]
+        word = WORD[form]
+        gf_ms, gf_n = r["kt"]["grad_flux"]
+        up_ms, up_n = r["kt"]["update"]
+        gf_us = gf_ms / gf_n * 1e3
+        up_us = up_ms / up_n * 1e3
+        stage_us = gf_us + up_us
+        alg = words["alg"] * word * cfg.nelem
+        impl = words["impl"] * word * cfg.nelem
+        achieved = alg / (stage_us * 1e-6) / 1e9
+        traffic = load_traffic(cfg.name, form, hsh)
+        f = {"value": rate, "ms_per_step": r["wall"] * 1e3 / K,
+             "precondition_ms": r["pc_ms"],
+             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                          "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                          "traffic": traffic["stage"] if traffic else None,
+                          "kernel": "RK stage: grad_flux + update",
+                          "alg_bytes_per_stage": alg, "impl_bytes_per_stage": impl,
+                          "stage_us": stage_us},
+             "kernels": {"grad_flux": {"avg_us": gf_us, "launches": gf_n,
+                                       "impl_bytes": words["grad_flux"] * word * cfg.nelem,
+                                       "counter_bytes": traffic["grad_flux"] if traffic else None},
+                         "update": {"avg_us": up_us, "launches": up_n,
+                                    "impl_bytes": words["update"] * word * cfg.nelem,
+                                    "counter_bytes": traffic["update"] if traffic else None}}}
+        for k in ("grad_flux", "update"):
+            kk = f["kernels"][k]
+            kk["impl_GBs"] = kk["impl_bytes"] / (kk["avg_us"] * 1e3)
+            if kk["counter_bytes"]:
+                kk["counter_GBs"] = kk["counter_bytes"] / (kk["avg_us"] * 1e3)
+        if traffic:
+            f["roofline"]["traffic_over_alg"] = traffic["stage"] / alg
+        if phi_acc is not None:
+            m0 = s.mass(torch.as_tensor(phi0).to("cuda:0", s.dtype))
+            if ref is None:
+                ref = (s, phi_acc, m0)
+                f["after_steps"] = {"steps": acc_steps, "mass_drift": (s.mass(phi_acc.to(s.dtype)) - m0) / m0}
+            else:
+                s64, phi64, m64 = ref
+                l1 = s64.l1(phi64, phi_acc)
+                f["after_steps"] = {"steps": acc_steps,
+                                    "interface_l1_vs_fp64": l1,
+                                    "interface_l1_vs_fp64_rel": l1 / m64,
+                                    "mass_drift": (s64.mass(phi_acc) - m64) / m64}
+        if ref is not None and form != forms[0]:
+            f["speedup_vs_fp64"] = rate / out["forms"][forms[0]]["value"]
+        out["forms"][form] = f
+        log(f"[bench] {cfg.name} {form}: {f['ms_per_step']:.4f} ms/step, {rate:.4e} DOF-stage/s, "
+            f"stage {stage_us:.1f} us (grad_flux {gf_us:.1f} + update {up_us:.1f}), "
+            f"{achieved:.0f} GB/s alg ({achieved / HBM_PEAK_GBS:.3f} of HBM), "
+            f"reset+precond {r['pc_ms']:.2f} ms"
+            + (f", int|phi-phi64| {f['after_steps'].get('interface_l1_vs_fp64', 0):.2e}" if phi_acc is not None else ""))
+        if ref is None or s is not ref[0]:
+            del s
+        torch.cuda.empty_cache()
+    del ref
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(name, target_s=12.0):
+    """The FP64 CPU oracle (test infrastructure), untuned, on all visible host cores, on a
+    bounded sample of the workload: the same kind of mesh, order, field and IC on 8^3
+    elements (3D) or the full mesh (2D); one reset + preconditioning (timed, not in the
+    value), then as many RK4 steps as fit about target_s seconds."""
+    import torch
+    import workloads as W
+    from dataclasses import replace
     from oracle import Oracle
-    cores = min(16, len(os.sched_getaffinity(0)))
+    cores = len(os.sched_getaffinity(0))
     torch.set_num_threads(cores)
+    cfg = W.config(name)
+    if cfg.ndims == 3:
+        n = 8
+        h = 1.0 / n
+        prm = W.default_params(3, cfg.order, h, vel_kind=cfg.params.vel_kind,
+                               vel_period=cfg.params.vel_period)
+        cfg = replace(cfg, n=n, params=prm)
+    mesh = cfg.mesh()
     o = Oracle(cfg.ndims, cfg.order, mesh, cfg.params)
-    phi = torch.as_tensor(phi0_np, dtype=torch.float64)
+    phi = torch.as_tensor(cfg.initial_phi(o.coords()), dtype=torch.float64)
     t0 = time.perf_counter()
     psi, _ = o.precondition(phi)
     t_pc = time.perf_counter() - t0
     dt = cfg.dt(mesh)
     t0 = time.perf_counter()
-    t = 0.0
+    phi, psi = o.step(phi, psi, 0.0, dt)
+    t1 = time.perf_counter() - t0
+    nsteps = max(1, min(500, int(target_s / max(t1, 1e-6))))
+    t0 = time.perf_counter()
+    t = dt
     for _ in range(nsteps):
         phi, psi = o.step(phi, psi, t, dt)
         t += dt
@@ -135,13 +287,15 @@ def cpu_baseline(cfg, mesh, phi0_np, nsteps):
             cpu = next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
     except (OSError, StopIteration):
         pass
+    mesh_s = f"{cfg.n}^3" if cfg.ndims == 3 else f"{cfg.n}x{cfg.n}"
     return {"value": rate, "unit": UNIT, "cores": torch.get_num_threads(), "kind": "oracle",
             "cpu": cpu,
-            "sample": f"full {cfg.n}x{cfg.n} p={cfg.order} mesh: {nsteps} RK4 steps "
-                      f"({t_steps:.1f} s) after one reset + {cfg.params.precond_iters} "
-                      f"pseudo iterations ({t_pc:.1f} s, not in value)",
-            "s_per_step": t_steps / nsteps,
-            "small_workload_full_run": small_workload_run()}
+            "sample": f"{mesh_s} p={cfg.order} mesh ({cfg.dof} DOF) of the workload's kind "
+                      f"(same order, field, IC{', plane perturbation' if cfg.perturb else ''}): "
+                      f"{nsteps} RK4 steps ({t_steps:.1f} s) after one reset + "
+                      f"{cfg.params.precond_iters} pseudo iterations ({t_pc:.1f} s, not in "
+                      f"value)",
+            "s_per_step": t_steps / nsteps}
 
 
 def small_workload_run():
@@ -461,41 +615,71 @@ def rotation_leg(orders=(2, 3, 4, 5)):
     return out
 
 
-def load_traffic(workload, kernel, hsh):
-    """Counter-measured HBM bytes per launch of a kernel on a workload, recorded in
-    profiles/traffic_<workload>.json for the kernel sources of hash hsh (else None)."""
-    try:
-        with open(os.path.join(PROFILES, f"traffic_{workload}.json")) as fh:
-            data = json.load(fh)
-    except OSError:
-        return None
-    if data.get("kernel_source_hash") != hsh:
-        return None
-    return data.get("per_launch_bytes", {}).get(kernel)
+def pseudo_sweep_leg():
+    """The single vortex on 128^2 quads, p = 4, to t = T (FP64) with the pseudo-time per
+    reset swept: K iterations at the default pseudo step for K = 0, 5, 10, 20, 40, resets
+    every 1000 steps; E_L1 = int|phi(T) - phi(0)| of each."""
+    import dataclasses
+    import torch
+    import workloads as W
+    cfg = W.config("C2")
+    mesh = cfg.mesh()
+    dt = cfg.dt(mesh)
+    nsteps = int(round(cfg.params.vel_period / dt))
+    phi0_np = initial_state(cfg, mesh)
+    out = {"workload": cfg.name, "steps": nsteps, "dtau": cfg.params.dtau}
+    for K in (0, 5, 10, 20, 40):
+        prm = dataclasses.replace(cfg.params, precond_iters=K)
+        s = make_solver(cfg, mesh, "fp64", prm)
+        phi0 = torch.as_tensor(phi0_np).to("cuda:0", s.dtype)
+        s.set_state(phi0)
+        s.step(dt, nsteps)
+        m0 = s.mass(phi0)
+        e = s.l1(phi0)
+        out[f"K{K}"] = {"pseudo_time_over_h": K * cfg.params.dtau / cfg.h, "E_L1": e,
+                        "E_m": (s.mass() - m0) / m0}
+        log(f"[bench] pseudo sweep K={K} (K dtau = {K * cfg.params.dtau / cfg.h:.3f} h): "
+            f"E_L1 = {e:.3e}")
+        del s
+    return out
+
+
+LEG_MIN_STEPS = {"C3": 50, "C2": 1000, "C1": 200, "C4": 200}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--config", default="C2")
-    ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--no-bf16", action="store_true")
+    ap.add_argument("--steps", type=int, default=20,
+                    help="timed RK4 steps of the headline workload")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="C5",
+                    help="headline workload (C1..C5; default C5, the 96^3 p=4 perturbed mesh)")
+    ap.add_argument("--forms", default="fp64,fp32,bf16")
+    ap.add_argument("--acc-steps", type=int, default=100,
+                    help="steps of the per-form interface comparison run (0: skip)")
+    ap.add_argument("--legs", default="C3,C2",
+                    help="further workloads measured the same way (comma list, '' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=200)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target length of the oracle's timed step loop")
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--no-accuracy", action="store_true",
-                    help="skip the run to t = T of the vortex workload (both normal forms)")
-    ap.add_argument("--no-rotation", action="store_true",
-                    help="skip the slotted-disc rotation tests (Zalesak, Rudman; one turn each)")
-    ap.add_argument("--deformation", action="store_true",
-                    help="also run the 64^3 p=3 LeVeque test to t = T (about a minute)")
-    ap.add_argument("--vortex-table", action="store_true",
-                    help="also run the single vortex to t = T on 32^2..128^2, p = 2..5")
-    ap.add_argument("--leveque-table", action="store_true",
-                    help="also run the 3D deformation to t = T on 32^3, p = 2..5")
+    ap.add_argument("--no-small-run", action="store_true",
+                    help="skip the 16x16 p=3 workload run whole on the oracle and the GPU")
     ap.add_argument("--adj-steps", type=int, default=512)
+    ap.add_argument("--accuracy", action="store_true",
+                    help="the 128^2 p=4 vortex to t = T: E_L1 of the method's variants and "
+                         "the equal-interface-error protocol of the FP32 and BF16 forms")
+    ap.add_argument("--rotation", action="store_true",
+                    help="the slotted-disc rotation tests (Zalesak, Rudman; one turn each)")
+    ap.add_argument("--deformation", action="store_true",
+                    help="the 64^3 p=3 LeVeque test to t = T (about a minute)")
+    ap.add_argument("--vortex-table", action="store_true",
+                    help="the single vortex to t = T on 32^2..128^2, p = 2..5")
+    ap.add_argument("--leveque-table", action="store_true",
+                    help="the 3D deformation to t = T on 32^3, p = 2..5")
+    ap.add_argument("--pseudo-sweep", action="store_true",
+                    help="the 128^2 p=4 vortex to t = T with K = 0..40 pseudo iterations")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -504,105 +688,51 @@ def main():
               f"(--gpus {args.gpus} requested)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import workloads as W
-    from paper_2006_10967_amd import MeshArgs
-
-    cfg = W.config(args.config)
-    mesh = cfg.mesh()
-    period = [float(mesh.period[k]) if mesh.periodic[k] else 0.0 for k in range(cfg.ndims)]
-    coords = MeshArgs(cfg.ndims, cfg.order, mesh.x0, mesh.jac, mesh.nbr, period).solution_coords()
-    phi0 = W.ic_phi(coords, cfg.centre, cfg.radius, cfg.params.eps_w)
-    K, Wm = args.steps, args.warmup
-    log(f"[bench] {cfg.name}: E={cfg.nelem} N_u={cfg.nupts} DOF={cfg.dof} steps={K} warmup={Wm}")
 
     if args.copy_mb > 0:
         # a plain copy of known size: reads and writes copy_mb MiB once each
         src = torch.ones(args.copy_mb << 18, dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)
-        torch.cuda.synchronize()
+        sync()
         dst.copy_(src)
-        torch.cuda.synchronize()
+        sync()
         del src, dst
 
-    s64, wall64, wall64_ev, kt64, pc64, phi64 = run_form(cfg, mesh, "fp64", K, Wm, phi0)
-    value = cfg.dof * 4 * K / wall64
-    log(f"[bench] fp64: {wall64 * 1e3 / K:.4f} ms/step, {value:.4e} DOF-stage/s")
-
-    # roofline of the dominant kernel (HIP-event durations of the second timed region)
-    word = 8
-    kern = max(("grad_flux", "update"), key=lambda k: kt64[k][0])
-    ms, nl = kt64[kern]
-    avg_s = ms / nl * 1e-3
-    bytes_launch = kernel_bytes(cfg.ndims, cfg.order, word, kern) * cfg.nelem
-    achieved = bytes_launch / avg_s / 1e9
+    forms = [f for f in args.forms.split(",") if f]
+    if forms[0] != "fp64":
+        raise SystemExit("the first form must be fp64 (the reference of the comparison)")
+    K, Wm = args.steps, args.warmup
     hsh = kernel_source_hash()
-    traffic = load_traffic(cfg.name, kern, hsh)
-    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kern,
-                "alg_bytes_per_launch": bytes_launch,
-                "avg_launch_us": avg_s * 1e6}
-    kernels = {k: {"avg_us": (v[0] / v[1] * 1e3) if v[1] else None, "launches": v[1],
-                   "alg_bytes_per_launch": kernel_bytes(cfg.ndims, cfg.order, word, k) * cfg.nelem
-                   if k in ("grad_flux", "update") else None}
-               for k, v in kt64.items()}
-    for k in ("grad_flux", "update"):
-        if kernels[k]["avg_us"]:
-            kernels[k]["alg_GBs"] = kernels[k]["alg_bytes_per_launch"] / (kernels[k]["avg_us"] * 1e3)
-    step_bytes = step_alg_bytes_per_dof(cfg.ndims, cfg.order, word) * cfg.dof * 4
+    head = workload_leg(args.workload, forms, K, Wm, args.acc_steps, hsh)
+    f64 = head["forms"]["fp64"]
+    cfg = W.config(args.workload)
     out = {
-        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": K, "warmup": Wm,
-        "ms_per_step": wall64 * 1e3 / K, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": cfg.name, "description": cfg.description,
-                   "elements": cfg.nelem, "order": cfg.order, "dof": cfg.dof,
-                   "dt": cfg.dt(mesh), "reset_every": cfg.params.reset_every,
-                   "precond_iters": cfg.params.precond_iters},
-        "roofline": roofline,
-        "kernels_fp64": kernels,
-        "step_alg_GBs_fp64": step_bytes / (wall64 / K * 1e9),
-        "ms_per_step_with_events": wall64_ev * 1e3 / K,
-        "precondition_ms_fp64": pc64,
+        "metric": METRIC, "value": f64["value"], "unit": UNIT, "n_gpus": 1, "steps": K,
+        "warmup": Wm, "ms_per_step": f64["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": head["workload"], "description": head["description"],
+                   "elements": head["elements"], "order": head["order"], "dof": head["dof"],
+                   "dt": head["dt"], "reset_every": head["reset_every"],
+                   "precond_iters": head["precond_iters"],
+                   "timed_region": f"{K} RK4 steps after the step-0 reset + preconditioning "
+                                   f"and {Wm} warm-up steps"},
+        "roofline": f64["roofline"],
+        "kernels_fp64": f64["kernels"],
+        "precondition_ms_fp64": f64["precondition_ms"],
+        "forms": {k: v for k, v in head["forms"].items() if k != "fp64"},
+        "fp64_after_steps": f64.get("after_steps"),
+        "kernel_source_hash": hsh,
     }
-
-    forms = [f for f, off in (("fp32", args.no_fp32), ("bf16", args.no_bf16)) if not off]
-    if forms:
-        out["forms"] = {}
-        mass64 = s64.mass(phi64)
-        mass0 = s64.mass(torch.as_tensor(phi0))
-        ref = s64.mass(phi64)
-    for form in forms:
-        sf, wallf, _, ktf, pcf, phif = run_form(cfg, mesh, form, K, Wm, phi0)
-        vf = cfg.dof * 4 * K / wallf
-        l1 = s64.l1(phi64, phif.double())
-        massf = s64.mass(phif.double())
-        out["forms"][form] = {
-            "value": vf, "ms_per_step": wallf * 1e3 / K, "speedup_vs_fp64": vf / value,
-            "interface_l1_vs_fp64": l1, "interface_l1_vs_fp64_rel": l1 / ref,
-            "mass_drift": (massf - mass0) / mass0,
-            "mass_drift_fp64": (mass64 - mass0) / mass0, "precondition_ms": pcf,
-            "kernels": {k: {"avg_us": (v[0] / v[1] * 1e3) if v[1] else None}
-                        for k, v in ktf.items()}}
-        log(f"[bench] {form}: {wallf * 1e3 / K:.4f} ms/step, {vf:.4e} DOF-stage/s, "
-            f"int|phi_{form}-phi64| = {l1:.3e}")
-        del sf
-
-    if not args.no_accuracy and cfg.params.vel_kind == W.VEL_SINGLE_VORTEX:
-        out["accuracy"] = accuracy_leg(cfg, mesh, phi0)
-
-    if not args.no_rotation:
-        out["rotation"] = rotation_leg()
-
-    if args.deformation:
-        out["deformation"] = deformation_leg()
-
-    if args.vortex_table:
-        out["vortex_table"] = vortex_table_leg()
-
-    if args.leveque_table:
-        out["leveque_table"] = leveque_table_leg()
+    legs = [x for x in args.legs.split(",") if x and x != args.workload]
+    if legs:
+        out["legs"] = {}
+    for name in legs:
+        kl = max(K, LEG_MIN_STEPS.get(name, K))
+        lf = forms if W.config(name).ndims == 3 else [f for f in forms if f != "bf16"]
+        out["legs"][name] = workload_leg(name, lf, kl, Wm, args.acc_steps, hsh)
 
     if not args.no_adjoint:
         adj = {}
@@ -614,11 +744,28 @@ def main():
             / abs(adj["fp64"]["dL_dA"])
         out["adjoint"] = {"workload": "adjoint2d_64x64_p3", **adj}
 
+    if args.accuracy:
+        c2 = W.config("C2")
+        m2 = c2.mesh()
+        out["accuracy"] = accuracy_leg(c2, m2, initial_state(c2, m2))
+    if args.rotation:
+        out["rotation"] = rotation_leg()
+    if args.deformation:
+        out["deformation"] = deformation_leg()
+    if args.vortex_table:
+        out["vortex_table"] = vortex_table_leg()
+    if args.leveque_table:
+        out["leveque_table"] = leveque_table_leg()
+    if args.pseudo_sweep:
+        out["pseudo_sweep"] = pseudo_sweep_leg()
+
+    if not args.no_small_run:
+        out["small_workload_full_run"] = small_workload_run()
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(cfg, mesh, phi0, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
         log(f"[bench] oracle: {out['cpu_baseline']['value']:.4e} DOF-stage/s on "
-            f"{out['cpu_baseline']['cores']} cores")
+            f"{out['cpu_baseline']['cores']} cores ({out['cpu_baseline']['sample']})")
     print(json.dumps(out), flush=True)
 
 

@@ -16,9 +16,13 @@ class PCPFRun(torch.autograd.Function):
     @staticmethod
     def forward(ctx, phi0, psi0, amp, solver: Solver, dt: float, nsteps: int, t0: float = 0.0,
                 step0: int = 0, every: int | None = None):
-        solver.set_velocity_amplitude(float(amp))
+        a = float(amp)
+        solver.set_velocity_amplitude(a)
+        ctx.inputs = (phi0.detach().clone(), None if psi0 is None else psi0.detach().clone(), a,
+                      float(dt), int(nsteps), float(t0), int(step0), every)
         solver.set_state(phi0.detach(), None if psi0 is None else psi0.detach(), t0, step0)
         solver.forward_ckpt(dt, nsteps, every)
+        ctx.run_id = solver.run_id
         phi, psi, _, _ = solver.get_state(want_psi=True)
         ctx.solver = solver
         ctx.has_psi0 = psi0 is not None
@@ -30,6 +34,14 @@ class PCPFRun(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gphi, gpsi):
         s: Solver = ctx.solver
+        if s.run_id != ctx.run_id:
+            # the solver recorded another run (or ran an adjoint) since this forward: record
+            # this graph's run again from its saved inputs. The forward run is
+            # deterministic, so the checkpoints are bitwise those of the first recording.
+            phi0, psi0, a, dt, nsteps, t0, step0, every = ctx.inputs
+            s.set_velocity_amplitude(a)
+            s.set_state(phi0, psi0, t0, step0)
+            s.forward_ckpt(dt, nsteps, every)
         if gphi is None:
             gphi = torch.zeros((s.nelem, s.nupts), dtype=s.dtype, device=s.device)
         gphi0, gpsi0, ga = s.adjoint(gphi.contiguous(),

@@ -242,10 +242,18 @@ class Solver:
         nb = ctypes.c_size_t(0)
         self._chk(self.lib.pcpf_ckpt_bytes(self.ctx, int(nsteps), int(every), ctypes.byref(nb)))
         ck = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        self._run_id = getattr(self, "_run_id", 0) + 1
+        self._ckpt, self._ckpt_every = None, None
         self._chk(self.lib.pcpf_forward_ckpt(self.ctx, float(dt), int(nsteps), int(every),
                                              _ptr(ck), ctypes.c_size_t(nb.value)))
         self._ckpt, self._ckpt_every = ck, int(every)
         return ck
+
+    @property
+    def run_id(self) -> int:
+        """Identifier of the run the context has recorded for :meth:`adjoint` (0: none);
+        every :meth:`forward_ckpt` records a new run, replacing the previous one."""
+        return getattr(self, "_run_id", 0) if getattr(self, "_ckpt", None) is not None else 0
 
     def adjoint(self, gphi, gpsi=None, ckpt=None):
         """Reverse sweep of the last :meth:`forward_ckpt` run for the seed

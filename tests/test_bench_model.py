@@ -2,9 +2,9 @@
 
 B_alg per DOF-stage (5 V N_u RK4 register values + 2 V N_f face-exchange values per element,
 over N_u) against the per-configuration values 14.0 / 13.2 / 16.0 / 14.8 of the 2D p=3,
-2D p=4, 3D p=3 and 3D p=4 workloads, and the per-launch algorithmic bytes of the two
-kernels against a count written out from their argument lists (each array read or
-written once per launch)."""
+2D p=4, 3D p=3 and 3D p=4 workloads, and the words the two launches of a stage move
+against a count written out from their argument lists (each array read or written once
+per launch)."""
 import math
 import os
 import sys
@@ -17,26 +17,26 @@ import bench  # noqa: E402
 
 
 @pytest.mark.parametrize("d,p,values", [(2, 3, 14.0), (2, 4, 13.2), (3, 3, 16.0), (3, 4, 14.8)])
-def test_step_bytes_per_dof(d, p, values):
-    assert math.isclose(bench.step_alg_bytes_per_dof(d, p, 8) / 8, values, rel_tol=1e-12)
-    assert math.isclose(bench.step_alg_bytes_per_dof(d, p, 4) / 4, values, rel_tol=1e-12)
+def test_stage_alg_words_per_dof(d, p, values):
+    nu = (p + 1) ** d
+    assert math.isclose(bench.stage_words(d, p)["alg"] / nu, values, rel_tol=1e-12)
 
 
 @pytest.mark.parametrize("d,p", [(2, 3), (2, 4), (3, 3), (3, 4)])
-def test_kernel_bytes(d, p):
+def test_stage_impl_words(d, p):
     n = p + 1
     nu, nfa = n ** d, n ** (d - 1)
     geo = d + 2 * d * d + 1          # x0, J, J^-1, |J|
     # grad_flux: reads u (2 planes), the + face traces (2 d planes of nfa) and geo;
-    # writes P (2 planes) and the owned-face fluxes (2 d nfa)
-    gf = 2 * nu + 2 * d * nfa + geo + 2 * nu + 2 * d * nfa
+    # writes P (2 planes) and the + face common fluxes into its own and the neighbour's
+    # slots (2 x 2 d nfa)
+    gf = 2 * nu + 2 * d * nfa + geo + 2 * nu + 2 * 2 * d * nfa
     # update, averaged over the 4 stages: reads P, Fp, Fm, |J|, u_n and acc (not on stage
     # 1); writes acc (not on stage 4), the next stage input and the pushed traces
     up = 2 * nu + 2 * (2 * d * nfa) + 1 + 2 * nu + 0.75 * 2 * nu + 0.75 * 2 * nu + 2 * nu \
         + 2 * d * nfa
-    assert bench.kernel_bytes(d, p, 8, "grad_flux") == 8 * gf
-    assert bench.kernel_bytes(d, p, 8, "update") == 8 * up
-    # 128x128 p=4: 19.8 MB and 37.5 MB per launch (the figures of the roofline line)
-    if (d, p) == (2, 4):
-        assert abs(bench.kernel_bytes(2, 4, 8, "grad_flux") * 128 * 128 / 1e6 - 19.79) < 0.01
-        assert abs(bench.kernel_bytes(2, 4, 8, "update") * 128 * 128 / 1e6 - 37.49) < 0.01
+    w = bench.stage_words(d, p)
+    assert w["grad_flux"] == gf and w["update"] == up and w["impl"] == gf + up
+    # 96^3 p=4 FP64: 13.1 GB of algorithmic bytes per stage
+    if (d, p) == (3, 4):
+        assert abs(w["alg"] * 8 * 96 ** 3 / 1e9 - 13.095) < 1e-3

@@ -50,6 +50,9 @@ CASES = [
     ("3d_p3_perturbed", 3, 3, (3, 2, 3), dict(perturb=0.2, vel_u0=(0.3, 0.2, -0.5),
                                               precond_iters=1, reset_every=2), 3, 1, 1, True,
      False),
+    ("3d_p2_skew", 3, 2, (4, 5, 3), dict(shear=(0.25, 0.05, 0.2), vel_kind=W.VEL_LEVEQUE3D,
+                                         vel_period=3.0, precond_iters=2, reset_every=2),
+     3, 2, 0, False, True),
 ]
 
 
@@ -235,3 +238,137 @@ def test_adjoint_at_full_size_matches_oracle():
     assert abs(float(torch.sum((gp - ogp) * v))) <= TOL * abs(float(torch.sum(ogp * v)))
     assert _rel(gp, ogp) <= 1e-4, _rel(gp, ogp)
     assert abs(ga - oga) <= TOL * abs(oga), (ga, oga)
+
+
+def test_autograd_interleaved_runs_on_one_solver():
+    """Two differentiable runs on one Solver, the second recorded before the first one's
+    backward: each backward gives its own run's gradient (the binding records the stale
+    run again from its saved inputs), checked against the oracle's VJP of each run."""
+    from paper_2006_10967_amd.autograd import run
+    mesh, prm = W.small_case(2, 2, (5, 5), vel_kind=W.VEL_SINGLE_VORTEX, vel_period=4.0,
+                             precond_iters=2)
+    o = Oracle(2, 2, mesh, prm)
+    s = _solver(mesh, 2, prm)
+    phi_a, _, g_a, _ = _inputs(o, prm, 2, 3, False)
+    phi_b, _, g_b, _ = _inputs(o, prm, 2, 4, False)
+    dt = _dt(mesh)
+    pa = phi_a.cuda().requires_grad_(True)
+    pb = phi_b.cuda().requires_grad_(True)
+    Aa = torch.tensor(1.1, dtype=torch.float64, requires_grad=True)
+    Ab = torch.tensor(0.8, dtype=torch.float64, requires_grad=True)
+    phiT_a, _ = run(s, pa, Aa, dt, 3)
+    phiT_b, _ = run(s, pb, Ab, dt, 4)           # records over run a
+    torch.sum(phiT_a * g_a.cuda()).backward()   # run a's backward after run b's forward
+    torch.sum(phiT_b * g_b.cuda()).backward()
+    for p, A, phi0, g, amp, n in ((pa, Aa, phi_a, g_a, 1.1, 3), (pb, Ab, phi_b, g_b, 0.8, 4)):
+        ogp, _, oga, _ = _oracle_vjp(o, phi0, None, amp, 0.0, dt, n, 0, g, None)
+        assert _rel(p.grad, ogp) <= TOL, _rel(p.grad, ogp)
+        assert abs(float(A.grad) - oga) <= TOL * abs(oga), (float(A.grad), oga)
+
+
+def _c4_loss_setup(precision="fp64"):
+    cfg = W.config("C4")
+    mesh = cfg.mesh()
+    s = _solver(mesh, cfg.order, cfg.params, precision)
+    x = s.solution_coords()
+    phi0 = torch.tensor(W.ic_phi(x, cfg.centre, cfg.radius, cfg.params.eps_w))
+    tgt = torch.tensor(W.ic_phi(x, W.adjoint_target_centre(cfg), cfg.radius,
+                                cfg.params.eps_w)).cuda()
+    det = torch.as_tensor(mesh.jac).det()
+    w1 = torch.as_tensor(s.mesh.ops["weights"])
+    wq = (det[:, None] * torch.kron(w1, w1)[None, :]).cuda()
+    return cfg, mesh, s, phi0, tgt, wq
+
+
+def test_adjoint_full_horizon_central_differences():
+    """The adjoint workload at its own horizon: 64x64 p=3 single vortex, 512 RK4 steps
+    from a reset with ten preconditioning iterations, checkpoints every 32 steps, loss
+    L = 1/2 int (phi(T) - target)^2. The adjoint's dL/dA and its derivative along an
+    interface-supported direction of phi0 (phi0 (1 - phi0) times a seeded normal field,
+    where the map is well conditioned) agree with central differences of the GPU
+    forward run to 1e-6 relative."""
+    cfg, mesh, s, phi0, tgt, wq = _c4_loss_setup()
+    dt, nsteps, every = cfg.dt(mesh), cfg.steps, 32
+
+    def loss(phi_init, amp):
+        s.set_velocity_amplitude(amp)
+        s.set_state(phi_init, None, 0.0, 0)
+        s.step(dt, nsteps)
+        phi = s.get_state(want_psi=False)[0]
+        return 0.5 * float(torch.sum(wq * (phi - tgt) ** 2))
+
+    s.set_velocity_amplitude(1.0)
+    s.set_state(phi0, None, 0.0, 0)
+    s.forward_ckpt(dt, nsteps, every)
+    phiT = s.get_state(want_psi=False)[0]
+    gp, _, ga = s.adjoint(wq * (phiT - tgt))
+    h = 1e-5
+    fdA = (loss(phi0, 1.0 + h) - loss(phi0, 1.0 - h)) / (2 * h)
+    print(f"[adjoint] 512 steps: dL/dA adjoint {ga:.10e}, central difference {fdA:.10e}, "
+          f"rel {abs(fdA - ga) / abs(ga):.2e}")
+    assert abs(fdA - ga) <= 1e-6 * abs(ga), (fdA, ga)
+    v = phi0 * (1 - phi0) * torch.tensor(np.random.default_rng(2).standard_normal(phi0.shape))
+    v /= torch.linalg.vector_norm(v)
+    fd = (loss(phi0 + h * v, 1.0) - loss(phi0 - h * v, 1.0)) / (2 * h)
+    ad = float(torch.sum(gp.cpu() * v))
+    print(f"[adjoint] 512 steps: dL/dphi0 . v adjoint {ad:.10e}, central difference "
+          f"{fd:.10e}, rel {abs(fd - ad) / abs(ad):.2e}")
+    assert abs(fd - ad) <= 1e-6 * abs(ad), (fd, ad)
+
+
+def test_adjoint_matches_oracle_over_checkpoints_and_a_reset():
+    """The 64x64 p=3 workload over 40 steps with a reset at step 24 (ten preconditioning
+    iterations at step 0 and at step 24) and checkpoints every 16 steps, so the reverse
+    sweep crosses two checkpoint boundaries and a reset: GPU VJP against the oracle's
+    autograd. dL/dA and the interface-band / interface-direction parts of dL/dphi0 to
+    1e-10 (well conditioned there; elsewhere dL/dphi0 takes its direction from rounding
+    noise of grad psi, as in the two-step full-size test above)."""
+    import dataclasses
+    cfg = W.config("C4")
+    prm = dataclasses.replace(cfg.params, reset_every=24)
+    mesh = cfg.mesh()
+    o = Oracle(cfg.ndims, cfg.order, mesh, prm)
+    s = _solver(mesh, cfg.order, prm)
+    x = o.coords()
+    phi0 = torch.tensor(W.ic_phi(x, cfg.centre, cfg.radius, prm.eps_w))
+    tgt = torch.tensor(W.ic_phi(x, W.adjoint_target_centre(cfg), cfg.radius, prm.eps_w))
+    dt, nsteps, every = cfg.dt(mesh), 40, 16
+    wq = o.disc.tdetJ[:, None] * o.disc.tW[None, :]
+    with torch.no_grad():
+        phiT_o, _, _ = o.run(phi0, None, 0.0, dt, nsteps)
+    seed = wq * (phiT_o - tgt)
+    ogp, _, oga, _ = _oracle_vjp(o, phi0, None, prm.vel_amp, 0.0, dt, nsteps, 0, seed, None)
+    s.set_state(phi0, None, 0.0, 0)
+    s.forward_ckpt(dt, nsteps, every)
+    phiT = s.get_state(want_psi=False)[0]
+    assert _rel(phiT, phiT_o) <= TOL
+    gp, _, ga = s.adjoint(seed)
+    gp = gp.cpu()
+    scale = float(ogp.abs().max())
+    band = (phi0 * (1 - phi0)) > 1e-4
+    e_band = float(((gp - ogp) * band).abs().max()) / scale
+    v = phi0 * (1 - phi0)
+    e_dir = abs(float(torch.sum((gp - ogp) * v))) / abs(float(torch.sum(ogp * v)))
+    print(f"[adjoint] 40 steps, reset at 24: dL/dA rel {abs(ga - oga) / abs(oga):.2e}, "
+          f"band {e_band:.2e}, direction {e_dir:.2e}, all {_rel(gp, ogp):.2e}")
+    assert abs(ga - oga) <= TOL * abs(oga), (ga, oga)
+    assert e_band <= TOL and e_dir <= TOL
+
+
+def test_adjoint_fp32_amplitude_gradient_at_full_horizon():
+    """FP32 form of the adjoint workload at 512 steps against FP64: dL/dA within 5e-3
+    relative. The FP32 forward run differs from FP64 by the rounding of ~2000 stages
+    (interface L1 difference ~1e-6 of the loss's scale), and dL/dA is an integral of the
+    adjoint against the velocity derivative, whose FP32 relative error grows like the
+    forward one times the number of steps (a few 1e-4); measured 7.6e-4."""
+    res = []
+    for prec in ("fp64", "fp32"):
+        cfg, mesh, s, phi0, tgt, wq = _c4_loss_setup(prec)
+        s.set_state(phi0, None, 0.0, 0)
+        s.forward_ckpt(cfg.dt(mesh), cfg.steps, 32)
+        phiT = s.get_state(want_psi=False)[0]
+        res.append(s.adjoint(wq.to(s.dtype) * (phiT - tgt.to(s.dtype)))[2])
+        del s
+    rel = abs(res[1] - res[0]) / abs(res[0])
+    print(f"[adjoint] 512 steps: dL/dA fp64 {res[0]:.8e}, fp32 {res[1]:.8e}, rel {rel:.2e}")
+    assert rel <= 5e-3

@@ -1,7 +1,8 @@
 """bench.py's output contract, on the GPU: one JSON line (strict JSON, no NaN), the metric
-and config of the 128x128 p=4 vortex workload, a value consistent with ms_per_step, the
-roofline object of the dominant kernel and the CPU oracle baseline. A short run: 5 steps,
-2 oracle steps, no accuracy, rotation or adjoint legs."""
+and config of the chosen workload, a value consistent with ms_per_step, the stage
+roofline object and the CPU oracle baseline. A short run on the 64^3 p=3 workload: 5
+steps, a 2 s oracle sample, no legs, adjoint or small-workload run (the default run
+headlines the 96^3 p=4 workload the same way)."""
 import json
 import os
 import subprocess
@@ -20,7 +21,8 @@ def _reject(c):
 
 def test_bench_json_line():
     cmd = [sys.executable, os.path.join(ROOT, "bench.py"), "--steps", "5", "--warmup", "1",
-           "--cpu-steps", "2", "--no-accuracy", "--no-rotation", "--no-adjoint"]
+           "--workload", "C3", "--legs", "", "--acc-steps", "5", "--cpu-seconds", "2",
+           "--no-adjoint", "--no-small-run"]
     r = subprocess.run(cmd, capture_output=True, text=True, timeout=600, cwd=ROOT)
     assert r.returncode == 0, r.stderr[-2000:]
     lines = [l for l in r.stdout.splitlines() if l.strip()]
@@ -31,15 +33,22 @@ def test_bench_json_line():
               "roofline", "cpu_baseline"):
         assert k in d, k
     assert d["n_gpus"] == 1 and d["steps"] == 5 and d["warmup"] == 1 and d["dtype"] == "f64"
-    assert d["config"]["workload"] == "vortex2d_128x128_p4" and d["config"]["dof"] == 409600
-    assert abs(d["value"] - 409600 * 4 / (d["ms_per_step"] * 1e-3)) <= 1e-6 * d["value"]
+    dof = 64 ** 3 * 64
+    assert d["config"]["workload"] == "deform3d_64cube_p3" and d["config"]["dof"] == dof
+    assert abs(d["value"] - dof * 4 / (d["ms_per_step"] * 1e-3)) <= 1e-6 * d["value"]
     rl = d["roofline"]
     assert rl["bound"] == "hbm" and rl["unit"] == "GB/s" and rl["peak"] == 8000.0
-    assert abs(rl["frac"] - rl["achieved"] / rl["peak"]) < 1e-12 and 0 < rl["frac"] < 2
+    assert abs(rl["frac"] - rl["achieved"] / rl["peak"]) < 1e-12 and 0 < rl["frac"] < 1
+    # achieved = algorithmic bytes of a stage over the stage's kernel time
+    assert abs(rl["achieved"] - rl["alg_bytes_per_stage"] / (rl["stage_us"] * 1e3)) \
+        <= 1e-9 * rl["achieved"]
+    assert rl["alg_bytes_per_stage"] == 16 * 8 * dof
     cb = d["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["value"] > 0 and cb["cores"] >= 1
     # the FP32 and BF16 forms ran the same region
     assert set(d["forms"]) == {"fp32", "bf16"}
+    for f in d["forms"].values():
+        assert f["after_steps"]["steps"] == 5 and f["after_steps"]["interface_l1_vs_fp64"] >= 0
     # bench refuses more than one GPU with a message
     r2 = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                         capture_output=True, text=True, timeout=120, cwd=ROOT)

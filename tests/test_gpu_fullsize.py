@@ -7,7 +7,10 @@ neighbours' traces and the fluxes its - face neighbours compute, which need thei
 + face neighbours (every element within one layer, diagonals included). The oracle
 therefore reproduces, on a 7^3 sub-block cut out of the full mesh with copy boundaries,
 the full-mesh residual of every sub-block element that is not on the sub-block's outer
-layer (5^3 = 125 elements). The sub-block is placed across the interface.
+layer (5^3 = 125 elements). Two sub-blocks are sampled: one across the sphere's interface in
+the middle of the index range, and the block at the high-index corner (the last elements,
+where the 32-bit element offsets are largest), which a second, small sphere centred in it
+gives an interface too.
 
 Properties: per-residual mass conservation (the common flux is shared exactly by the two
 elements of a face, so on a periodic mesh sum |J| W R_phi vanishes to round-off) and
@@ -55,10 +58,22 @@ def _sub_block(mesh, lo, m):
     return sub, full, inner
 
 
-def _state(cfg, x):
-    phi = torch.tensor(W.ic_phi(x, cfg.centre, cfg.radius, cfg.params.eps_w))
-    psi = torch.tensor(W.signed_distance_ball(x, cfg.centre, cfg.radius))
-    return phi, psi
+def _corner_ball(mesh):
+    """A sphere centred in the last M^3 elements of the mesh (the high-index corner)."""
+    n = mesh.shape
+    lo = [np.asarray(mesh.planes[k])[n[k] - M + 1] for k in range(3)]
+    hi = [np.asarray(mesh.planes[k])[n[k] - 1] for k in range(3)]
+    c = 0.5 * (np.array(lo) + np.array(hi))
+    return c, 0.3 * float(min(h - l for l, h in zip(lo, hi)))
+
+
+def _state(cfg, mesh, x):
+    """The workload's sphere and the corner sphere: phi the tanh profile of the signed
+    distance to their union, psi that distance."""
+    c2, r2 = _corner_ball(mesh)
+    dist = np.maximum(W.signed_distance_ball(x, cfg.centre, cfg.radius),
+                      W.signed_distance_ball(x, c2, r2))
+    return torch.tensor(W.tanh_profile(dist, cfg.params.eps_w)), torch.tensor(dist)
 
 
 @pytest.mark.parametrize("name,lo", CASES, ids=[c[0] for c in CASES])
@@ -66,7 +81,7 @@ def test_full_size_sampled_residuals(name, lo):
     cfg = W.config(name)
     mesh = cfg.mesh()
     s = _solver(mesh, cfg.order, cfg.params)
-    phi, psi = _state(cfg, s.solution_coords())
+    phi, psi = _state(cfg, mesh, s.solution_coords())
     t = 0.4
     gp, gs = s.residual(phi, psi, t)
     s.set_state(phi)
@@ -77,21 +92,26 @@ def test_full_size_sampled_residuals(name, lo):
     psi0 = phi - 0.5
     _, gpc = s.residual(None, psi0, 0.0, mode=1)
 
-    sub, full, inner = _sub_block(mesh, lo, M)
-    o = Oracle(cfg.ndims, cfg.order, sub, cfg.params)
-    full_t = torch.as_tensor(full)
-    sphi, spsi = phi[full_t], psi[full_t]
-    assert float((sphi * (1 - sphi)).max()) > 0.2, "the sub-block must contain the interface"
-    Rp, Rs = o.residual(sphi, spsi, t)
-    osgn = ores.smeared_sign(o.disc, cfg.params, sphi - 0.5)
-    Rpc = o.precond_residual(sphi - 0.5, osgn)
-    sel = full_t[torch.as_tensor(inner)]
-    ins = torch.as_tensor(inner)
-    for g, r, what in ((gp, Rp, "R_phi"), (gs, Rs, "R_psi"), (gsgn, osgn, "sign"),
-                       (gpc, Rpc, "R_pc")):
-        e = _rel(g[sel.to(g.device)].double().cpu(), r[ins])
-        print(f"[fullsize] {name} {what}: rel L_inf over {int(ins.sum())} elements {e:.2e}")
-        assert e <= TOL, (name, what, e)
+    corner = tuple(n - M for n in mesh.shape)
+    for where, lo_b in (("middle", lo), ("corner", corner)):
+        sub, full, inner = _sub_block(mesh, lo_b, M)
+        o = Oracle(cfg.ndims, cfg.order, sub, cfg.params)
+        full_t = torch.as_tensor(full)
+        sphi, spsi = phi[full_t], psi[full_t]
+        assert float((sphi * (1 - sphi)).max()) > 0.2, "the sub-block must contain an interface"
+        Rp, Rs = o.residual(sphi, spsi, t)
+        osgn = ores.smeared_sign(o.disc, cfg.params, sphi - 0.5)
+        Rpc = o.precond_residual(sphi - 0.5, osgn)
+        sel = full_t[torch.as_tensor(inner)]
+        ins = torch.as_tensor(inner)
+        if where == "corner":
+            assert int(sel.max()) >= cfg.nelem - 2 * mesh.shape[0] ** 2
+        for g, r, what in ((gp, Rp, "R_phi"), (gs, Rs, "R_psi"), (gsgn, osgn, "sign"),
+                           (gpc, Rpc, "R_pc")):
+            e = _rel(g[sel.to(g.device)].double().cpu(), r[ins])
+            print(f"[fullsize] {name} {where} {what}: rel L_inf over {int(ins.sum())} "
+                  f"elements (largest index {int(sel.max())}) {e:.2e}")
+            assert e <= TOL, (name, where, what, e)
 
 
 @pytest.mark.parametrize("name", ["C3", "C5"])
@@ -100,7 +120,7 @@ def test_full_size_mass_conservation_and_free_stream(name):
     cfg = W.config(name)
     mesh = cfg.mesh()
     s = _solver(mesh, cfg.order, cfg.params)
-    phi, psi = _state(cfg, s.solution_coords())
+    phi, psi = _state(cfg, mesh, s.solution_coords())
     gp, _ = s.residual(phi, psi, 0.7)
     m = s.reduce(REDUCE_MASS, gp)
     a = s.reduce(REDUCE_L1, gp, torch.zeros_like(gp))

@@ -63,6 +63,13 @@ CASES = [
     ("2d_p4_mixed_bc", 2, 4, (9, 7), dict(periodic=(True, False), vel_u0=(0.7, -0.3))),
     ("3d_p3_mixed_bc", 3, 3, (4, 5, 3), dict(periodic=(False, True, False),
                                              vel_u0=(0.3, -0.4, 0.2))),
+    # skewed hexes (full, non-diagonal J; non-axis face normals), periodic with shifted
+    # wraps, and with walls
+    ("3d_p3_skew", 3, 3, (4, 5, 3), dict(shear=(0.25, 0.05, 0.2), vel_u0=(0.3, 0.2, -0.5))),
+    ("3d_p2_skew_leveque", 3, 2, (4, 5, 6), dict(shear=(0.25, 0.05, 0.2),
+                                                 vel_kind=W.VEL_LEVEQUE3D, vel_period=3.0)),
+    ("3d_p4_skew_copybc", 3, 4, (3, 3, 2), dict(shear=(0.3, -0.2, 0.1), periodic=False,
+                                                vel_u0=(-0.2, 0.5, 0.3))),
 ]
 
 
@@ -84,7 +91,8 @@ def test_physical_residual_parity(cid, d, p, shape, kw, kind):
 PC_CASES = [c for c in CASES if c[0] in ("2d_p3_uniform", "2d_p4_vortex_ragged",
                                          "2d_p3_copybc_rotation", "3d_p3_leveque_ragged",
                                          "3d_p4_perturbed", "3d_p2_copybc", "2d_single_element",
-                                         "3d_p3_mixed_bc")]
+                                         "3d_p3_mixed_bc", "3d_p3_skew",
+                                         "3d_p4_skew_copybc")]
 
 
 @pytest.mark.parametrize("cid,d,p,shape,kw", PC_CASES, ids=[c[0] for c in PC_CASES])
@@ -168,6 +176,28 @@ def test_trajectory_parity_mixed_walls():
     phi_g, psi_g, _, _ = s.get_state()
     assert _rel(phi_g, phi_o) <= 1e-10
     assert _rel(psi_g, psi_o) <= 1e-10
+
+
+def test_trajectory_parity_skewed_hexes():
+    """Skewed periodic hexes (4x5x3, p=3, full J) under the LeVeque field: reset + 3
+    pseudo iterations, 20 RK4 steps with a reset at step 12; phi and psi match the oracle
+    to 1e-10 and mass is conserved to round-off."""
+    mesh, prm = W.small_case(3, 3, (4, 5, 3), shear=(0.25, 0.05, 0.2),
+                             vel_kind=W.VEL_LEVEQUE3D, vel_period=3.0, precond_iters=3,
+                             reset_every=12)
+    o = Oracle(3, 3, mesh, prm)
+    s = _solver(mesh, 3, prm)
+    x = o.coords()
+    phi0 = torch.tensor(W.ic_phi(x, np.array([0.45, 0.5, 0.55]), 0.3, 0.08))
+    dt = 0.004
+    phi_o, psi_o, _ = o.run(phi0, None, 0.0, dt, 20)
+    s.set_state(phi0)
+    s.step(dt, 20)
+    phi_g, psi_g, _, _ = s.get_state()
+    assert _rel(phi_g, phi_o) <= 1e-10
+    assert _rel(psi_g, psi_o) <= 1e-10
+    m0 = s.mass(phi0)
+    assert abs(s.mass() - m0) / m0 <= 1e-12
 
 
 def test_full_size_vortex_residual():

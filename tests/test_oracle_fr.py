@@ -37,11 +37,12 @@ def make(d, p, shape, **kw):
     (2, 4, (3, 3), {"perturb": 0.2}),
     (3, 2, (2, 3, 2), {"perturb": 0.2}),
     (2, 2, (4, 4), {"shear": 0.25}),
+    (3, 2, (4, 5, 3), {"shear": (0.25, 0.05, 0.2)}),
 ])
 def test_corrected_gradient_exact_on_polynomials(d, p, shape, kw):
     o, mesh, prm = make(d, p, shape, periodic=False, **kw)
     x = o.disc.xs
-    sheared = kw.get("shear", 0.0) != 0.0
+    sheared = bool(np.any(np.asarray(kw.get("shear", 0.0)) != 0.0))
     for e in monomials(d, p):
         if sheared and sum(e) > p:
             continue
@@ -151,6 +152,7 @@ def test_fr_equals_dg_weak_forms(d, p):
     (2, 4, (4, 4), {"perturb": 0.2}),
     (2, 3, (4, 4), {"shear": 0.25}),
     (3, 3, (3, 3, 4), {"perturb": 0.2}),
+    (3, 2, (4, 5, 3), {"shear": (0.25, 0.05, 0.2)}),
 ])
 def test_free_stream_and_constant_state(d, p, shape, kw):
     """Uniform v: (a) on a periodic mesh a constant psi is preserved, and so is a
@@ -183,13 +185,14 @@ def test_free_stream_and_constant_state(d, p, shape, kw):
 
 
 # ---------------------------------------------------------------------------------- P7
-@pytest.mark.parametrize("d,p,shape,kind", [
-    (2, 3, (5, 4), W.VEL_UNIFORM),
-    (2, 4, (6, 6), W.VEL_SINGLE_VORTEX),
-    (3, 3, (3, 4, 3), W.VEL_LEVEQUE3D),
+@pytest.mark.parametrize("d,p,shape,kind,kw", [
+    (2, 3, (5, 4), W.VEL_UNIFORM, {"perturb": 0.2}),
+    (2, 4, (6, 6), W.VEL_SINGLE_VORTEX, {"perturb": 0.2}),
+    (3, 3, (3, 4, 3), W.VEL_LEVEQUE3D, {"perturb": 0.2}),
+    (3, 2, (4, 5, 3), W.VEL_LEVEQUE3D, {"shear": (0.25, 0.05, 0.2)}),
 ])
-def test_mass_conservation_per_residual(d, p, shape, kind):
-    o, mesh, prm = make(d, p, shape, vel_kind=kind, perturb=0.2)
+def test_mass_conservation_per_residual(d, p, shape, kind, kw):
+    o, mesh, prm = make(d, p, shape, vel_kind=kind, **kw)
     E, Nu = o.disc.E, o.ops.nupts
     rng = np.random.default_rng(1)
     phi = T(rng.uniform(0, 1, (E, Nu)))

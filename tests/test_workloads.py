@@ -8,6 +8,7 @@ of a rigid rotation."""
 import math
 
 import numpy as np
+import pytest
 import torch
 
 import workloads as W
@@ -87,3 +88,36 @@ def test_rotation_field_is_rigid():
         assert float((rel[:, 0] * v[:, 1] - rel[:, 1] * v[:, 0]).min()) > 0  # counter-clockwise
         assert float(ovel.spatial(ovel.ROTATION, torch.tensor([cen], dtype=torch.float64),
                                   (cen[0], cen[1], 0.0)).abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("shape,shear,periodic", [
+    ((4, 5, 3), (0.25, 0.05, 0.2), (True, True, True)),
+    ((3, 3, 4), (1.0 / 3, -2.0 / 9, 1.0 / 3), (True, True, True)),
+    ((4, 3, 3), (0.3, -0.2, 0.1), (False, False, False)),
+    ((4, 5, 3), (0.25, 0.05, 0.2), (True, False, True)),
+])
+def test_skewed_3d_mesh_adjacency(shape, shear, periodic):
+    """The skewed hex mesh (x = S b with a unit upper-triangular S): a full Jacobian, and
+    its face adjacency equals the pairing of flux points by physical coordinates that the
+    oracle builds independently (modulo the axis-aligned periods)."""
+    from oracle.mesh import Discretisation
+    from oracle.operators import ElementOperators
+    planes = [W.uniform_planes(n) for n in shape]
+    mesh = W.box_mesh(planes, periodic, shear=shear)
+    assert np.abs(mesh.jac[:, 0, 1]).max() > 0 or shear[0] == 0
+    assert np.abs(mesh.jac[:, 0, 2]).max() > 0 and np.abs(mesh.jac[:, 1, 2]).max() > 0
+    ops = ElementOperators(3, 2)
+    disc = Discretisation.from_box(ops, mesh)
+    nfa = 9
+    for e in range(mesh.nelem):
+        for f in range(6):
+            slots = np.arange(f * nfa, (f + 1) * nfa)
+            en = mesh.nbr[e, f]
+            if en < 0:
+                assert not disc.has_pair[e, slots].any()
+                continue
+            assert disc.has_pair[e, slots].all()
+            assert np.all(disc.pair_e[e, slots] == en)
+            # the partner slots lie on the opposite face of the neighbour, in the same order
+            g = f ^ 1
+            assert np.array_equal(disc.pair_j[e, slots], np.arange(g * nfa, (g + 1) * nfa))

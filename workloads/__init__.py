@@ -59,7 +59,7 @@ class BoxMesh:
     jac: np.ndarray           # [E, d, d] J[i, j] = dx_i / dxi_j (constant per element)
     nbr: np.ndarray           # [E, 2d] int32
     period: np.ndarray        # [d] domain length per dim (used for periodic wrap)
-    shear: float = 0.0
+    shear: object = 0.0        # 2D: s_xy; 3D: (s_xy, s_xz, s_yz)
 
     @property
     def nelem(self) -> int:
@@ -79,14 +79,16 @@ def perturbed_planes(n: int, amp_frac: float, rng: np.random.Generator,
     return p
 
 
-def box_mesh(planes: Sequence[np.ndarray], periodic: Sequence[bool], shear: float = 0.0) -> BoxMesh:
+def box_mesh(planes: Sequence[np.ndarray], periodic: Sequence[bool], shear=0.0) -> BoxMesh:
     """Build the element maps and adjacency of a box mesh from its grid planes.
 
-    ``shear`` (2D only) maps (x, y) -> (x + shear*y, y); with periodic y the wrap then
-    connects column ex to column ex + shear*nx, so shear*nx must be an integer and the x
-    planes uniform.
+    ``shear`` in 2D (a number s) maps (x, y) -> (x + s*y, y); with periodic y the wrap then
+    connects column ex to column ex + s*nx, so s*nx must be an integer and the x planes
+    uniform. In 3D it is a triple (s_xy, s_xz, s_yz) (see ``_skew_mesh_3d``).
     """
     d = len(planes)
+    if d == 3 and np.any(np.asarray(shear, dtype=np.float64) != 0.0):
+        return _skew_mesh_3d(planes, periodic, tuple(float(x) for x in shear))
     shape = tuple(len(p) - 1 for p in planes)
     E = int(np.prod(shape))
     idx = np.arange(E)
@@ -104,9 +106,8 @@ def box_mesh(planes: Sequence[np.ndarray], periodic: Sequence[bool], shear: floa
         jac[:, k, k] = 0.5 * (hi - lo)
     period = np.array([planes[k][-1] - planes[k][0] for k in range(d)])
     shift = 0
-    if shear != 0.0:
-        if d != 2:
-            raise ValueError("shear is a 2D option")
+    if np.any(np.asarray(shear) != 0.0):
+        shear = float(shear)
         x0[:, 0] += shear * x0[:, 1]
         jac[:, 0, 1] = shear * jac[:, 1, 1]
         nx = shape[0]
@@ -136,6 +137,79 @@ def box_mesh(planes: Sequence[np.ndarray], periodic: Sequence[bool], shear: floa
     return BoxMesh(ndims=d, shape=shape, planes=[np.asarray(p) for p in planes],
                    periodic=tuple(bool(x) for x in periodic), x0=x0, jac=jac, nbr=nbr,
                    period=period, shear=shear)
+
+
+def _skew_mesh_3d(planes, periodic, shear) -> BoxMesh:
+    """A box grid mapped by the unit upper-triangular matrix
+    S = [[1, s_xy, s_xz], [0, 1, s_yz], [0, 0, 1]]: x = S b for every point b of the box
+    grid, so every element is affine with J = S diag(h_k / 2), a full (non-diagonal)
+    Jacobian whose faces have non-axis normals.
+
+    With periodic directions the mesh stays periodic under the axis-aligned periods of
+    the box (L_x, L_y, L_z): crossing the y wrap moves the x index by s_xy L_y / h_x cells,
+    crossing the z wrap moves it by (s_xz - s_xy s_yz) L_z / h_x cells and the y index by
+    s_yz L_z / h_y cells. These must be whole numbers and the x and y planes uniform
+    (the z planes may be perturbed). Tangential axes of neighbouring faces point the same
+    way (every element has the same S)."""
+    sxy, sxz, syz = shear
+    S = np.array([[1.0, sxy, sxz], [0.0, 1.0, syz], [0.0, 0.0, 1.0]])
+    shape = tuple(len(p) - 1 for p in planes)
+    nx, ny, nz = shape
+    E = nx * ny * nz
+    idx = np.arange(E)
+    ix, iy, iz = idx % nx, (idx // nx) % ny, idx // (nx * ny)
+    L = np.array([planes[k][-1] - planes[k][0] for k in range(3)])
+    h = L / np.array(shape)
+
+    def whole(v, what):
+        if abs(v - round(v)) > 1e-9:
+            raise ValueError(f"skew: {what} must be a whole number of cells (got {v})")
+        return int(round(v))
+
+    for k in (0, 1):
+        if not np.allclose(np.diff(planes[k]), h[k], rtol=0, atol=1e-12 * L[k]):
+            raise ValueError("skew: the x and y planes must be uniform")
+    kx_y = whole(sxy * L[1] / h[0], "s_xy L_y / h_x") if periodic[1] else 0
+    kx_z = whole((sxz - sxy * syz) * L[2] / h[0], "(s_xz - s_xy s_yz) L_z / h_x") if periodic[2] else 0
+    ky_z = whole(syz * L[2] / h[1], "s_yz L_z / h_y") if periodic[2] else 0
+    lo = np.stack([planes[0][ix], planes[1][iy], planes[2][iz]], -1)
+    hi = np.stack([planes[0][ix + 1], planes[1][iy + 1], planes[2][iz + 1]], -1)
+    x0 = lo @ S.T
+    jac = np.einsum("ij,ej->eij", S, 0.5 * (hi - lo))
+    nbr = np.full((E, 6), -1, dtype=np.int32)
+    for k in range(3):
+        for sd, step in ((0, -1), (1, 1)):
+            c = [ix.copy(), iy.copy(), iz.copy()]
+            c[k] = c[k] + step
+            ok = np.ones(E, dtype=bool)
+            # leave the box through z: wrap z and shift x, y; then y (shifts x); then x
+            up, dn = c[2] >= nz, c[2] < 0
+            if periodic[2]:
+                c[0] = c[0] + np.where(up, kx_z, 0) - np.where(dn, kx_z, 0)
+                c[1] = c[1] + np.where(up, ky_z, 0) - np.where(dn, ky_z, 0)
+                c[2] = c[2] % nz
+            else:
+                ok &= ~(up | dn)
+            while True:
+                up, dn = c[1] >= ny, c[1] < 0
+                if not (up.any() or dn.any()):
+                    break
+                if periodic[1]:
+                    c[0] = c[0] + np.where(up, kx_y, 0) - np.where(dn, kx_y, 0)
+                    c[1] = np.where(up, c[1] - ny, np.where(dn, c[1] + ny, c[1]))
+                else:
+                    ok &= ~(up | dn)
+                    c[1] = np.clip(c[1], 0, ny - 1)
+            if periodic[0]:
+                c[0] = c[0] % nx
+            else:
+                ok &= (c[0] >= 0) & (c[0] < nx)
+                c[0] = np.clip(c[0], 0, nx - 1)
+            e2 = c[0] + nx * (c[1] + ny * c[2])
+            nbr[:, 2 * k + sd] = np.where(ok, e2, -1).astype(np.int32)
+    return BoxMesh(ndims=3, shape=shape, planes=[np.asarray(p) for p in planes],
+                   periodic=tuple(bool(x) for x in periodic), x0=x0, jac=jac, nbr=nbr,
+                   period=L, shear=shear)
 
 
 # --------------------------------------------------------------------------------------
