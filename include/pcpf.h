@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define PCPF_ABI_VERSION 1
+#define PCPF_ABI_VERSION 2
 #define PCPF_MAX_ORDER 6
 
 typedef enum pcpf_status {
@@ -132,6 +132,46 @@ typedef struct pcpf_params {
     int32_t stop_mode;   /* PCPF_STOP_FIXED (default) or PCPF_STOP_RMS */
 } pcpf_params;
 
+/* Element shapes of a dense description. */
+enum { PCPF_SHAPE_TENSOR = 0,   /* quadrilateral (d = 2) / hexahedral (d = 3) element */
+       PCPF_SHAPE_TRIANGLE = 1 };/* triangle (d = 2) */
+
+/* The mesh and FR operators in the dense form the method is written in (§3.1, Steps 1-6:
+ * each operator an N_f x N_u or N_u x N_u matrix acting on the values of one element), the
+ * per-element affine geometry (§3.1 mapping, Jacobian and transformed-flux equations) and
+ * the per-flux-point connectivity (§3.1 Step 2: each flux point of a face paired with
+ * the coincident flux point of the neighbouring element). Host memory, row-major, float64
+ * unless stated. Solution point i = sum_k i_k n^k (i_0 fastest); flux point j = f N_fa + t
+ * on face f = 2k + s (s = 0: xi_k = -1, s = 1: xi_k = +1), t the index of its tangential
+ * Gauss-Legendre positions, first tangential axis fastest. */
+typedef struct pcpf_dense_mesh {
+    int32_t ndims;              /* d */
+    int32_t order;              /* p */
+    int32_t shape;              /* PCPF_SHAPE_* */
+    int32_t nupts;              /* N_u: (p+1)^d for tensor elements */
+    int32_t nfpts;              /* N_f: 2d (p+1)^(d-1) for tensor elements */
+    int64_t nelem;              /* E */
+    const double* M0;           /* [N_f][N_u] interpolation to the flux points (Step 1) */
+    const double* D;            /* [d][N_u][N_u] reference derivatives (Steps 3, 6) */
+    const double* LiftN;        /* [d][N_u][N_f] gradient correction, nhat_k-signed (Step 3) */
+    const double* Lift;         /* [N_u][N_f] divergence correction (Step 6) */
+    const double* Vinv;         /* [N_u][N_u] nodal -> orthonormal modal (sensor, §3.2) */
+    const uint8_t* topmask;     /* [N_u] 1 on the modes dropped by the sensor's truncation */
+    const double* W;            /* [N_u] quadrature weights of the solution points */
+    const double* ref_fnorm;    /* [N_f][d] reference outward unit normal nhat_j */
+    const double* jinv;         /* [E][d][d] J^-1, J = dx/dxi */
+    const double* detj;         /* [E] det J */
+    const double* fnorm;        /* [E][N_f][d] physical unit normal J^-T nhat / |J^-T nhat| */
+    const double* fscale;       /* [E][N_f] det J |J^-T nhat| */
+    const double* xorig;        /* [E][d] image of the reference corner (-1, ..., -1) */
+    const double* jac;          /* optional ([E][d][d] J itself; NULL: J = inv(jinv)) */
+    const int32_t* nbr_slot;    /* [E N_f] partner flux point e' N_f + j', -1 = boundary
+                                   (copy boundary condition, §3.3) */
+    const uint8_t* owner;       /* [E N_f] 1 where this element computes the face's common
+                                   flux (the side whose LDG beta is +1/2) */
+    double period[3];           /* as pcpf_mesh.period */
+} pcpf_dense_mesh;
+
 typedef struct pcpf_ctx pcpf_ctx;
 
 /* ABI version of the loaded library (PCPF_ABI_VERSION of its build). */
@@ -168,6 +208,27 @@ pcpf_status pcpf_workspace_bytes(const pcpf_mesh* mesh, const pcpf_params* param
  * EINVAL, EUNSUPPORTED, EDEVICE. */
 pcpf_status pcpf_create(const pcpf_mesh* mesh, const pcpf_params* params, void* d_ws,
                         size_t ws_bytes, void* stream, pcpf_ctx** out);
+
+/* The dense description of pcpf_dense_mesh, validated and mapped onto the kernels' form.
+ * The kernels apply the operators of a tensor-product element line by line (the sum-
+ * factorised form of the same matrices), so the description is accepted when
+ *   - its operators are those of the order-p Gauss-Legendre tensor element with DG
+ *     correction functions in the point and face order stated above (each matrix entry
+ *     within 1e-12 of the library's, relative to the operator's largest entry), and
+ *   - every face is paired whole with the opposite face of one neighbour, flux point t
+ *     with flux point t (the orientation rule of pcpf_mesh), owner = 1 exactly on the
+ *     + faces of paired slots, and
+ *   - the geometry is that of one affine map per element (det J, normals and face scales
+ *     consistent with J^-1 within 1e-12).
+ * Triangles and other point sets or orientations are valid descriptions that this build
+ * does not run: EUNSUPPORTED. Inconsistent sizes, non-reciprocal pairs, several or no
+ * owners on a pair, or geometry that disagrees with J: EINVAL. The host arrays are read
+ * during the call only. pcpf_workspace_bytes_dense runs the same validation (no GPU
+ * needed); pcpf_create_dense then behaves as pcpf_create on the equivalent pcpf_mesh. */
+pcpf_status pcpf_workspace_bytes_dense(const pcpf_dense_mesh* mesh, const pcpf_params* params,
+                                       size_t* nbytes);
+pcpf_status pcpf_create_dense(const pcpf_dense_mesh* mesh, const pcpf_params* params,
+                              void* d_ws, size_t ws_bytes, void* stream, pcpf_ctx** out);
 
 /* Free the host-side context (the workspace stays with the caller). NULL is a no-op. */
 void pcpf_destroy(pcpf_ctx* ctx);
@@ -208,7 +269,10 @@ pcpf_status pcpf_precondition(pcpf_ctx* ctx, int32_t iters);
 pcpf_status pcpf_precond_info(const pcpf_ctx* ctx, int32_t* iters, double* rms);
 
 /* One residual evaluation (the parity entry point). PCPF_MODE_PHYS: d/dt of (phi, psi)
- * at time t from d_phi, d_psi into d_rphi, d_rpsi. PCPF_MODE_PRECOND: d/dtau of psi from
+ * at time t from d_phi, d_psi into d_rphi, d_rpsi: the FR residual of §3.1 (Steps 1-6,
+ * du/dt = -div f / det J) of the localized system of §2 (Eq. altconservativephasefieldeq
+ * for phi, the transport of psi). PCPF_MODE_PRECOND: d/dtau of psi (§3.2, Eq.
+ * pseudotimesystem: the viscous flux with the sensor's nu_s plus the eikonal source) from
  * d_psi using the smeared sign of the last reset (d_phi, d_rphi ignored, may be NULL).
  * Inputs and outputs are [E][N_u] in the state type; outputs may not alias inputs.
  * Uses the context's scratch registers: the stored state is not changed. */

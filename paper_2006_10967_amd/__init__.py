@@ -6,8 +6,9 @@ The method runs in the HIP library ``libpcpf.so`` built from ``csrc/`` (C ABI in
 """
 from ._lib import PcpfError, load  # noqa: F401
 from .solver import (BF16, FP32, FP64, MODE_PHYS, MODE_PRECOND, REDUCE_L1, REDUCE_MASS,  # noqa: F401
-                     REDUCE_RMS, MeshArgs, Solver, line_operators, make_params)
+                     REDUCE_RMS, DenseMeshArgs, MeshArgs, Solver, line_operators,
+                     make_params)
 
-__all__ = ["Solver", "MeshArgs", "line_operators", "make_params", "PcpfError", "load",
+__all__ = ["Solver", "MeshArgs", "DenseMeshArgs", "line_operators", "make_params", "PcpfError", "load",
            "FP64", "FP32", "BF16", "MODE_PHYS", "MODE_PRECOND", "REDUCE_MASS", "REDUCE_L1",
            "REDUCE_RMS"]

@@ -19,7 +19,9 @@ PCPF_NORMAL_PSI, PCPF_NORMAL_PHI = 0, 1
 PCPF_REDUCE_MASS, PCPF_REDUCE_L1, PCPF_REDUCE_RMS = 0, 1, 2
 PCPF_SGN_PSI0, PCPF_SGN_CURRENT = 0, 1
 PCPF_STOP_FIXED, PCPF_STOP_RMS = 0, 1
+PCPF_SHAPE_TENSOR, PCPF_SHAPE_TRIANGLE = 0, 1
 MAX_ORDER = 6
+ABI_VERSION = 2
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -29,6 +31,19 @@ class PcpfMesh(ctypes.Structure):
                 ("nodes", _dp), ("weights", _dp), ("deriv", _dp), ("lminus", _dp),
                 ("lplus", _dp), ("cminus", _dp), ("cplus", _dp), ("vinv", _dp),
                 ("x0", _dp), ("jac", _dp), ("nbr", ctypes.POINTER(ctypes.c_int32)),
+                ("period", ctypes.c_double * 3)]
+
+
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+
+
+class PcpfDenseMesh(ctypes.Structure):
+    _fields_ = [("ndims", ctypes.c_int32), ("order", ctypes.c_int32), ("shape", ctypes.c_int32),
+                ("nupts", ctypes.c_int32), ("nfpts", ctypes.c_int32), ("nelem", ctypes.c_int64),
+                ("M0", _dp), ("D", _dp), ("LiftN", _dp), ("Lift", _dp), ("Vinv", _dp),
+                ("topmask", _u8p), ("W", _dp), ("ref_fnorm", _dp), ("jinv", _dp),
+                ("detj", _dp), ("fnorm", _dp), ("fscale", _dp), ("xorig", _dp), ("jac", _dp),
+                ("nbr_slot", ctypes.POINTER(ctypes.c_int32)), ("owner", _u8p),
                 ("period", ctypes.c_double * 3)]
 
 
@@ -80,6 +95,11 @@ def load() -> ctypes.CDLL:
                                       ctypes.POINTER(ctypes.c_size_t)]),
         "pcpf_create": (st, [ctypes.POINTER(PcpfMesh), ctypes.POINTER(PcpfParams), vp,
                              ctypes.c_size_t, vp, ctypes.POINTER(vp)]),
+        "pcpf_workspace_bytes_dense": (st, [ctypes.POINTER(PcpfDenseMesh),
+                                            ctypes.POINTER(PcpfParams),
+                                            ctypes.POINTER(ctypes.c_size_t)]),
+        "pcpf_create_dense": (st, [ctypes.POINTER(PcpfDenseMesh), ctypes.POINTER(PcpfParams), vp,
+                                   ctypes.c_size_t, vp, ctypes.POINTER(vp)]),
         "pcpf_destroy": (None, [vp]),
         "pcpf_sizes": (st, [vp, ctypes.POINTER(i64), ctypes.POINTER(i32)]),
         "pcpf_set_state": (st, [vp, vp, vp, dbl, i64]),
@@ -103,7 +123,7 @@ def load() -> ctypes.CDLL:
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
-    if lib.pcpf_abi_version() != 1:
+    if lib.pcpf_abi_version() != ABI_VERSION:
         raise ImportError("libpcpf ABI version mismatch")
     _LIB = lib
     return lib

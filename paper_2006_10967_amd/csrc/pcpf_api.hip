@@ -1251,6 +1251,242 @@ pcpf_status out_of_memory(pcpf_ctx* c) noexcept {
     return PCPF_ENOMEM;
 }
 
+// ------------------------------------------------------------------------------------
+// dense description -> line factors
+// ------------------------------------------------------------------------------------
+// The dense operators of a Gauss-Legendre tensor element are Kronecker products of the 1D
+// factors with identities (interpolation and lifting touch one line; derivatives act
+// along one axis), so such a description is mapped onto the 1D factors the kernels apply.
+struct DenseLine {
+    std::vector<double> nodes, weights, deriv, lm, lp, cm, cp, vinv, x0, jac;
+    std::vector<int32_t> nbr;
+    pcpf_mesh m{};
+};
+
+// Compare a given operator with the expected one entry by entry (relative to the largest
+// expected entry, at least 1).
+template <typename F>
+bool same_operator(const double* given, size_t count, F expected) {
+    double scale = 1.0;
+    for (size_t i = 0; i < count; ++i) scale = std::max(scale, std::fabs(expected(i)));
+    for (size_t i = 0; i < count; ++i)
+        if (!(std::fabs(given[i] - expected(i)) <= 1e-12 * scale)) return false;
+    return true;
+}
+
+pcpf_status dense_to_line(const pcpf_dense_mesh* dm, DenseLine* h) {
+    if (!dm) return fail(nullptr, PCPF_EINVAL, "dense mesh is NULL");
+    if (dm->ndims != 2 && dm->ndims != 3) return fail(nullptr, PCPF_EINVAL, "ndims must be 2 or 3");
+    if (dm->shape == PCPF_SHAPE_TRIANGLE)
+        return fail(nullptr, PCPF_EUNSUPPORTED, "triangular elements are not built");
+    if (dm->shape != PCPF_SHAPE_TENSOR) return fail(nullptr, PCPF_EINVAL, "unknown element shape");
+    const int d = dm->ndims, p = dm->order;
+    const int pmax = d == 2 ? PCPF_MAX_ORDER : 5;
+    if (p < 1 || p > PCPF_MAX_ORDER) return fail(nullptr, PCPF_EINVAL, "order out of range 1..6");
+    if (p > pmax) return fail(nullptr, PCPF_EUNSUPPORTED, "3D orders above 5 are not built");
+    const int n = p + 1, nu = ipow(n, d), nfa = ipow(n, d - 1), nf = 2 * d * nfa;
+    if (dm->nupts != nu || dm->nfpts != nf)
+        return fail(nullptr, PCPF_EINVAL, "nupts / nfpts do not match the tensor element of order p");
+    if (dm->nelem < 1 || dm->nelem > ((int64_t)1 << 31))
+        return fail(nullptr, PCPF_EINVAL, "nelem out of range");
+    if (!dm->M0 || !dm->D || !dm->LiftN || !dm->Lift || !dm->Vinv || !dm->topmask || !dm->W ||
+        !dm->ref_fnorm || !dm->jinv || !dm->detj || !dm->fnorm || !dm->fscale || !dm->xorig ||
+        !dm->nbr_slot || !dm->owner)
+        return fail(nullptr, PCPF_EINVAL, "dense mesh has a NULL array");
+    const int64_t E = dm->nelem;
+    h->nodes.resize(n);
+    h->weights.resize(n);
+    h->deriv.resize(n * n);
+    h->lm.resize(n);
+    h->lp.resize(n);
+    h->cm.resize(n);
+    h->cp.resize(n);
+    h->vinv.resize(n * n);
+    pcpf_status st = pcpf_line_operators(p, h->nodes.data(), h->weights.data(), h->deriv.data(),
+                                         h->lm.data(), h->lp.data(), h->cm.data(), h->cp.data(),
+                                         h->vinv.data());
+    if (st != PCPF_OK) return st;
+    // multi-indices of the solution points and the (face, direction, side, tangential
+    // position) of the flux points
+    std::vector<int> mi((size_t)nu * d), fk(nf), fs(nf), tmi((size_t)nf * d, -1);
+    for (int i = 0; i < nu; ++i) {
+        int r = i;
+        for (int k = 0; k < d; ++k) {
+            mi[(size_t)i * d + k] = r % n;
+            r /= n;
+        }
+    }
+    for (int j = 0; j < nf; ++j) {
+        const int f = j / nfa, k = f / 2;
+        int t = j % nfa;
+        fk[j] = k;
+        fs[j] = f % 2;
+        for (int m = 0; m < d; ++m) {
+            if (m == k) continue;
+            tmi[(size_t)j * d + m] = t % n;
+            t /= n;
+        }
+    }
+    // point i lies on the line through flux point j (every index but the normal one agrees)
+    auto on_line = [&](int i, int j) {
+        for (int m = 0; m < d; ++m)
+            if (m != fk[j] && mi[(size_t)i * d + m] != tmi[(size_t)j * d + m]) return false;
+        return true;
+    };
+    auto lift1 = [&](int i, int j) {
+        if (!on_line(i, j)) return 0.0;
+        return (fs[j] ? h->cp : h->cm)[mi[(size_t)i * d + fk[j]]];
+    };
+    const char* bad = nullptr;
+    if (!same_operator(dm->M0, (size_t)nf * nu, [&](size_t q) {
+            const int j = (int)(q / nu), i = (int)(q % nu);
+            return on_line(i, j) ? (fs[j] ? h->lp : h->lm)[mi[(size_t)i * d + fk[j]]] : 0.0;
+        }))
+        bad = "M0";
+    else if (!same_operator(dm->D, (size_t)d * nu * nu, [&](size_t q) {
+                 const int k = (int)(q / ((size_t)nu * nu));
+                 const int i = (int)((q / nu) % nu), i2 = (int)(q % nu);
+                 for (int m = 0; m < d; ++m)
+                     if (m != k && mi[(size_t)i * d + m] != mi[(size_t)i2 * d + m]) return 0.0;
+                 return h->deriv[mi[(size_t)i * d + k] * n + mi[(size_t)i2 * d + k]];
+             }))
+        bad = "D";
+    else if (!same_operator(dm->Lift, (size_t)nu * nf, [&](size_t q) {
+                 return lift1((int)(q / nf), (int)(q % nf));
+             }))
+        bad = "Lift";
+    else if (!same_operator(dm->LiftN, (size_t)d * nu * nf, [&](size_t q) {
+                 const int k = (int)(q / ((size_t)nu * nf));
+                 const int i = (int)((q / nf) % nu), j = (int)(q % nf);
+                 if (fk[j] != k) return 0.0;
+                 return (fs[j] ? 1.0 : -1.0) * lift1(i, j);
+             }))
+        bad = "LiftN";
+    else if (!same_operator(dm->Vinv, (size_t)nu * nu, [&](size_t q) {
+                 const int J = (int)(q / nu), i = (int)(q % nu);
+                 double v = 1.0;
+                 for (int k = 0; k < d; ++k)
+                     v *= h->vinv[mi[(size_t)J * d + k] * n + mi[(size_t)i * d + k]];
+                 return v;
+             }))
+        bad = "Vinv";
+    else if (!same_operator(dm->W, (size_t)nu, [&](size_t i) {
+                 double w = 1.0;
+                 for (int k = 0; k < d; ++k) w *= h->weights[mi[i * d + k]];
+                 return w;
+             }))
+        bad = "W";
+    else if (!same_operator(dm->ref_fnorm, (size_t)nf * d, [&](size_t q) {
+                 const int j = (int)(q / d), k = (int)(q % d);
+                 return k == fk[j] ? (fs[j] ? 1.0 : -1.0) : 0.0;
+             }))
+        bad = "ref_fnorm";
+    if (bad)
+        return fail(nullptr, PCPF_EUNSUPPORTED,
+                    std::string("dense operator ") + bad +
+                        " is not that of the Gauss-Legendre tensor element with DG correction "
+                        "functions in the stated point and face order (the only element built)");
+    for (int J = 0; J < nu; ++J) {
+        int top = 0;
+        for (int k = 0; k < d; ++k) top |= mi[(size_t)J * d + k] == p;
+        if ((dm->topmask[J] != 0) != (top != 0))
+            return fail(nullptr, PCPF_EUNSUPPORTED,
+                        "topmask does not select the modes of degree p in some direction");
+    }
+    // geometry: one affine map per element
+    h->x0.assign(dm->xorig, dm->xorig + E * d);
+    h->jac.resize((size_t)E * d * d);
+    std::vector<double> Jm(d * d), Ji(d * d);
+    for (int64_t e = 0; e < E; ++e) {
+        const double* gi = dm->jinv + e * d * d;
+        double det;
+        if (dm->jac) {
+            std::copy(dm->jac + e * d * d, dm->jac + (e + 1) * d * d, Jm.begin());
+            inv_det(d, Jm.data(), Ji.data(), &det);
+            double sc = 0.0;
+            for (int q = 0; q < d * d; ++q) sc = std::max(sc, std::fabs(gi[q]));
+            for (int q = 0; q < d * d; ++q)
+                if (!(std::fabs(Ji[q] - gi[q]) <= 1e-12 * sc))
+                    return fail(nullptr, PCPF_EINVAL, "jinv is not the inverse of jac");
+        } else {
+            double idet;
+            inv_det(d, gi, Jm.data(), &idet);
+            det = 1.0 / idet;
+        }
+        if (!(det > 0.0)) return fail(nullptr, PCPF_EINVAL, "element with det J <= 0");
+        if (!(std::fabs(det - dm->detj[e]) <= 1e-12 * det))
+            return fail(nullptr, PCPF_EINVAL, "detj disagrees with the Jacobian");
+        for (int j = 0; j < nf; ++j) {
+            const int k = fk[j];
+            const double sg = fs[j] ? 1.0 : -1.0;
+            double mag = 0.0;
+            for (int i = 0; i < d; ++i) mag += gi[k * d + i] * gi[k * d + i];
+            mag = std::sqrt(mag);
+            for (int i = 0; i < d; ++i)
+                if (!(std::fabs(dm->fnorm[(e * nf + j) * d + i] - sg * gi[k * d + i] / mag) <= 1e-12))
+                    return fail(nullptr, PCPF_EINVAL, "fnorm disagrees with the Jacobian");
+            if (!(std::fabs(dm->fscale[e * nf + j] - det * mag) <= 1e-12 * det * mag))
+                return fail(nullptr, PCPF_EINVAL, "fscale disagrees with the Jacobian");
+        }
+        std::copy(Jm.begin(), Jm.end(), h->jac.begin() + e * d * d);
+    }
+    // connectivity: whole faces paired with the opposite face of one neighbour
+    h->nbr.assign((size_t)E * 2 * d, -1);
+    const int64_t S = E * nf;
+    for (int64_t e = 0; e < E; ++e) {
+        for (int f = 0; f < 2 * d; ++f) {
+            const int64_t s0 = e * nf + (int64_t)f * nfa;
+            const int32_t first = dm->nbr_slot[s0];
+            if (first < -1 || first >= S) return fail(nullptr, PCPF_EINVAL, "nbr_slot out of range");
+            const int64_t en = first >= 0 ? first / nf : -1;
+            for (int t = 0; t < nfa; ++t) {
+                const int64_t sl = s0 + t;
+                const int32_t ns = dm->nbr_slot[sl];
+                if (ns < -1 || ns >= S) return fail(nullptr, PCPF_EINVAL, "nbr_slot out of range");
+                if (ns < 0) {
+                    if (first >= 0)
+                        return fail(nullptr, PCPF_EUNSUPPORTED,
+                                    "a face with paired and boundary flux points is not built");
+                    if (dm->owner[sl] != 1)
+                        return fail(nullptr, PCPF_EINVAL, "a boundary flux point must be owned");
+                    continue;
+                }
+                if (dm->nbr_slot[ns] != sl)
+                    return fail(nullptr, PCPF_EINVAL, "nbr_slot pairs are not reciprocal");
+                if ((dm->owner[sl] != 0) == (dm->owner[ns] != 0) || dm->owner[sl] > 1 ||
+                    dm->owner[ns] > 1)
+                    return fail(nullptr, PCPF_EINVAL, "each flux-point pair needs exactly one owner");
+                if (ns / nf != en || ns % nf != (int64_t)(f ^ 1) * nfa + t)
+                    return fail(nullptr, PCPF_EUNSUPPORTED,
+                                "face pairing other than the whole opposite face with flux points "
+                                "in the same tangential order is not built");
+                if ((dm->owner[sl] != 0) != ((f & 1) != 0))
+                    return fail(nullptr, PCPF_EUNSUPPORTED,
+                                "owners other than the + face side (LDG beta = +1/2 there) are "
+                                "not built");
+            }
+            h->nbr[e * 2 * d + f] = (int32_t)en;
+        }
+    }
+    pcpf_mesh& m = h->m;
+    m.ndims = d;
+    m.order = p;
+    m.nelem = E;
+    m.nodes = h->nodes.data();
+    m.weights = h->weights.data();
+    m.deriv = h->deriv.data();
+    m.lminus = h->lm.data();
+    m.lplus = h->lp.data();
+    m.cminus = h->cm.data();
+    m.cplus = h->cp.data();
+    m.vinv = h->vinv.data();
+    m.x0 = h->x0.data();
+    m.jac = h->jac.data();
+    m.nbr = h->nbr.data();
+    for (int q = 0; q < 3; ++q) m.period[q] = dm->period[q];
+    return PCPF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1335,6 +1571,28 @@ pcpf_status pcpf_create(const pcpf_mesh* m, const pcpf_params* p, void* d_ws, si
     }
     *out = hold.release();
     return PCPF_OK;
+} catch (...) {
+    return out_of_memory(nullptr);
+}
+
+pcpf_status pcpf_workspace_bytes_dense(const pcpf_dense_mesh* dm, const pcpf_params* p,
+                                       size_t* nbytes) try {
+    DenseLine h;
+    pcpf_status st = dense_to_line(dm, &h);
+    if (st != PCPF_OK) return st;
+    return pcpf_workspace_bytes(&h.m, p, nbytes);
+} catch (...) {
+    return out_of_memory(nullptr);
+}
+
+pcpf_status pcpf_create_dense(const pcpf_dense_mesh* dm, const pcpf_params* p, void* d_ws,
+                              size_t ws_bytes, void* stream, pcpf_ctx** out) try {
+    if (!out) return fail(nullptr, PCPF_EINVAL, "out is NULL");
+    *out = nullptr;
+    DenseLine h;
+    pcpf_status st = dense_to_line(dm, &h);
+    if (st != PCPF_OK) return st;
+    return pcpf_create(&h.m, p, d_ws, ws_bytes, stream, out);
 } catch (...) {
     return out_of_memory(nullptr);
 }

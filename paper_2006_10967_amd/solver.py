@@ -12,7 +12,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import PcpfMesh, PcpfParams, check
+from ._lib import PcpfDenseMesh, PcpfMesh, PcpfParams, check
 
 FP64, FP32, BF16 = _lib.PCPF_FP64, _lib.PCPF_FP32, _lib.PCPF_BF16
 MODE_PHYS, MODE_PRECOND = _lib.PCPF_MODE_PHYS, _lib.PCPF_MODE_PRECOND
@@ -69,6 +69,49 @@ class MeshArgs:
         return xs
 
 
+class DenseMeshArgs:
+    """A pcpf_dense_mesh (the dense operators, per-element geometry and per-flux-point
+    connectivity of the method's statement) whose host arrays stay alive as long as this
+    object. Arrays are given as numpy arrays of the shapes in include/pcpf.h; ``jac`` is
+    optional."""
+
+    _F64 = ("M0", "D", "LiftN", "Lift", "Vinv", "W", "ref_fnorm", "jinv", "detj", "fnorm",
+            "fscale", "xorig")
+
+    def __init__(self, ndims, order, nelem, nupts, nfpts, arrays: dict, period=(0.0, 0.0, 0.0),
+                 shape=_lib.PCPF_SHAPE_TENSOR):
+        self.keep = {}
+        c = PcpfDenseMesh()
+        c.ndims, c.order, c.shape = int(ndims), int(order), int(shape)
+        c.nupts, c.nfpts, c.nelem = int(nupts), int(nfpts), int(nelem)
+        for name in self._F64:
+            a = np.ascontiguousarray(arrays[name], dtype=np.float64)
+            self.keep[name] = a
+            setattr(c, name, _dptr(a))
+        jac = arrays.get("jac")
+        if jac is not None:
+            a = np.ascontiguousarray(jac, dtype=np.float64)
+            self.keep["jac"] = a
+            c.jac = _dptr(a)
+        for name in ("topmask", "owner"):
+            a = np.ascontiguousarray(arrays[name], dtype=np.uint8)
+            self.keep[name] = a
+            setattr(c, name, a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+        a = np.ascontiguousarray(arrays["nbr_slot"], dtype=np.int32)
+        self.keep["nbr_slot"] = a
+        c.nbr_slot = a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        c.period = (ctypes.c_double * 3)(*[float(x) for x in (list(period) + [0.0] * 3)[:3]])
+        self.c = c
+        self.ndims, self.order, self.nelem, self.nupts = int(ndims), int(order), int(nelem), int(nupts)
+
+    def workspace_bytes(self, params, precision="fp64") -> int:
+        lib = _lib.load()
+        nb = ctypes.c_size_t(0)
+        cp = make_params(params, _PRECISIONS[precision])
+        check(lib.pcpf_workspace_bytes_dense(ctypes.byref(self.c), ctypes.byref(cp), ctypes.byref(nb)))
+        return nb.value
+
+
 def make_params(prm, precision) -> PcpfParams:
     """pcpf_params from any object with the workloads.Params attribute names."""
     c = PcpfParams()
@@ -96,19 +139,24 @@ class Solver:
     """One FR-PCPF context on a CUDA/HIP device."""
 
     def __init__(self, ndims, order, x0, jac, nbr, params, precision="fp64", device="cuda",
-                 period=(0.0, 0.0, 0.0)):
+                 period=(0.0, 0.0, 0.0), dense: "DenseMeshArgs | None" = None):
         self.lib = _lib.load()
         self.device = torch.device(device)
         if self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
-        self.mesh = MeshArgs(ndims, order, x0, jac, nbr, period)
+        self.dense = dense
+        self.mesh = MeshArgs(ndims, order, x0, jac, nbr, period) if dense is None else None
         self.params = params
         self.precision = _PRECISIONS[precision]
         self.dtype = _DTYPES[self.precision]
         self.cparams = make_params(params, self.precision)
         nb = ctypes.c_size_t(0)
-        check(self.lib.pcpf_workspace_bytes(ctypes.byref(self.mesh.c), ctypes.byref(self.cparams),
-                                            ctypes.byref(nb)))
+        if dense is None:
+            check(self.lib.pcpf_workspace_bytes(ctypes.byref(self.mesh.c),
+                                                ctypes.byref(self.cparams), ctypes.byref(nb)))
+        else:
+            check(self.lib.pcpf_workspace_bytes_dense(ctypes.byref(dense.c),
+                                                      ctypes.byref(self.cparams), ctypes.byref(nb)))
         self.ws_bytes = nb.value
         with torch.cuda.device(self.device):
             self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
@@ -116,12 +164,27 @@ class Solver:
             self._ws_ptr = (base + 255) // 256 * 256
             self.stream = torch.cuda.current_stream(self.device)
         ctx = ctypes.c_void_p()
-        check(self.lib.pcpf_create(ctypes.byref(self.mesh.c), ctypes.byref(self.cparams),
-                                   ctypes.c_void_p(self._ws_ptr), ctypes.c_size_t(self.ws_bytes),
-                                   ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx)))
+        if dense is None:
+            check(self.lib.pcpf_create(ctypes.byref(self.mesh.c), ctypes.byref(self.cparams),
+                                       ctypes.c_void_p(self._ws_ptr), ctypes.c_size_t(self.ws_bytes),
+                                       ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx)))
+            self.nelem = self.mesh.nelem
+            self.nupts = self.mesh.nupts
+        else:
+            check(self.lib.pcpf_create_dense(ctypes.byref(dense.c), ctypes.byref(self.cparams),
+                                             ctypes.c_void_p(self._ws_ptr),
+                                             ctypes.c_size_t(self.ws_bytes),
+                                             ctypes.c_void_p(self.stream.cuda_stream),
+                                             ctypes.byref(ctx)))
+            self.nelem = dense.nelem
+            self.nupts = dense.nupts
         self.ctx = ctx
-        self.nelem = self.mesh.nelem
-        self.nupts = self.mesh.nupts
+
+    @classmethod
+    def from_dense(cls, dense: "DenseMeshArgs", params, precision="fp64", device="cuda"):
+        """A context from the dense description of pcpf_dense_mesh."""
+        return cls(dense.ndims, dense.order, None, None, None, params, precision, device,
+                   dense=dense)
 
     @classmethod
     def from_box(cls, mesh, order, params, precision="fp64", device="cuda"):
@@ -151,6 +214,8 @@ class Solver:
 
     # -- the C ABI ------------------------------------------------------------------------
     def solution_coords(self) -> np.ndarray:
+        if self.mesh is None:
+            raise ValueError("a context made from a dense description has no line-factor mesh")
         return self.mesh.solution_coords()
 
     def set_state(self, phi, psi=None, t=0.0, step=0):

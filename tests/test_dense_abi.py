@@ -1,0 +1,192 @@
+"""The dense description at the C ABI (pcpf_dense_mesh: the FR operators as the dense
+matrices of §3.1, per-element affine geometry and per-flux-point pairing with an owner
+flag), validated and mapped onto the kernels' line form.
+
+The dense inputs are built by the FP64 oracle (its own Gauss-Legendre element, its own
+pairing of flux points by coordinates, its own normals and face scales), so the library's
+mapping is checked against an independent producer of the method's operators.
+
+CPU (no GPU needed, pcpf_workspace_bytes_dense runs the whole validation): accepted
+descriptions give the workspace of the equivalent line mesh; each kind of wrong or
+unsupported input gets its status. GPU: contexts made from the dense description give
+residuals, preconditioning and trajectories bitwise equal to those of the line-factor
+path on the same mesh.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle.mesh import Discretisation
+from oracle.operators import ElementOperators
+
+
+def dense_arrays(d, p, mesh, with_jac=True):
+    ops = ElementOperators(d, p)
+    disc = Discretisation.from_box(ops, mesh)
+    E, nf = disc.E, ops.nfpts
+    slot = np.arange(E * nf).reshape(E, nf)
+    partner = disc.pair_e * nf + disc.pair_j
+    nbr_slot = np.where(disc.has_pair, partner, -1).reshape(-1)
+    owner = np.where(disc.has_pair, disc.beta > 0, True).reshape(-1)
+    arr = {"M0": ops.M0, "D": np.stack(ops.D), "LiftN": np.stack(ops.LiftN),
+           "Lift": ops.LiftDiv, "Vinv": ops.Vt_inv, "topmask": ops.topmask, "W": ops.W,
+           "ref_fnorm": ops.nhat, "jinv": disc.Jinv, "detj": disc.detJ, "fnorm": disc.normal,
+           "fscale": disc.fscale, "xorig": mesh.x0, "nbr_slot": nbr_slot, "owner": owner}
+    if with_jac:
+        arr["jac"] = mesh.jac
+    assert np.all(slot.reshape(-1)[nbr_slot[nbr_slot >= 0]] == nbr_slot[nbr_slot >= 0])
+    return arr, ops
+
+
+def _period(mesh):
+    return [float(mesh.period[k]) if mesh.periodic[k] else 0.0 for k in range(mesh.ndims)]
+
+
+def _dense(d, p, mesh, arr, ops, **kw):
+    from paper_2006_10967_amd import DenseMeshArgs
+    return DenseMeshArgs(d, p, mesh.nelem, ops.nupts, ops.nfpts, arr, _period(mesh), **kw)
+
+
+MESHES = [
+    ("2d_p3_perturbed", 2, 3, dict(shape=(5, 4), perturb=0.2, vel_kind=W.VEL_SINGLE_VORTEX)),
+    ("2d_p2_sheared", 2, 2, dict(shape=(8, 8), shear=0.25, vel_u0=(0.3, -0.7))),
+    ("3d_p2_skew", 3, 2, dict(shape=(4, 5, 3), shear=(0.25, 0.05, 0.2),
+                              vel_kind=W.VEL_LEVEQUE3D, vel_period=3.0)),
+    ("3d_p3_copybc", 3, 3, dict(shape=(3, 2, 3), periodic=False, vel_u0=(0.3, 0.2, -0.5))),
+]
+
+
+def _case(d, p, kw):
+    kw = dict(kw)
+    shape = kw.pop("shape")
+    return W.small_case(d, p, shape, **kw)
+
+
+def _status_of(fn):
+    from paper_2006_10967_amd import PcpfError
+    try:
+        fn()
+    except PcpfError as e:
+        return e.status
+    return 0
+
+
+@pytest.mark.parametrize("cid,d,p,kw", MESHES, ids=[m[0] for m in MESHES])
+def test_dense_description_accepted(cid, d, p, kw):
+    from paper_2006_10967_amd import MeshArgs, Solver  # noqa: F401
+    from paper_2006_10967_amd import _lib
+    import ctypes
+    from paper_2006_10967_amd.solver import make_params
+    mesh, prm = _case(d, p, kw)
+    for with_jac in (True, False):
+        arr, ops = dense_arrays(d, p, mesh, with_jac)
+        dm = _dense(d, p, mesh, arr, ops)
+        nb = dm.workspace_bytes(prm)
+        line = MeshArgs(d, p, mesh.x0, mesh.jac, mesh.nbr, _period(mesh))
+        ref = ctypes.c_size_t(0)
+        _lib.check(_lib.load().pcpf_workspace_bytes(ctypes.byref(line.c),
+                                                    ctypes.byref(make_params(prm, 0)),
+                                                    ctypes.byref(ref)))
+        assert nb == ref.value
+
+
+def _mutations(d, p, mesh, arr, ops):
+    """(name, expected status, mutated arrays or kwargs)."""
+    from paper_2006_10967_amd import _lib
+    EINVAL, EUNSUP = _lib.PCPF_EINVAL, _lib.PCPF_EUNSUPPORTED
+    nf, nfa = ops.nfpts, ops.nfpts_face
+    out = []
+
+    def mod(name, fn):
+        a = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in arr.items()}
+        fn(a)
+        return a
+
+    out.append(("D entry", EUNSUP, mod("D", lambda a: a["D"].__setitem__((0, 1, 2), a["D"][0, 1, 2] + 1e-6))))
+    out.append(("M0 other point order", EUNSUP, mod("M0", lambda a: a.__setitem__("M0", a["M0"][::-1].copy()))))
+    out.append(("Lift sign", EUNSUP, mod("Lift", lambda a: a.__setitem__("Lift", -a["Lift"]))))
+    out.append(("LiftN unsigned", EUNSUP, mod("LiftN", lambda a: a.__setitem__("LiftN", np.abs(a["LiftN"])))))
+    out.append(("W", EUNSUP, mod("W", lambda a: a.__setitem__("W", a["W"] * 1.01))))
+    out.append(("topmask", EUNSUP, mod("t", lambda a: a["topmask"].__setitem__(0, 1.0))))
+    out.append(("detj", EINVAL, mod("detj", lambda a: a["detj"].__setitem__(1, a["detj"][1] * 1.001))))
+    out.append(("fnorm", EINVAL, mod("fnorm", lambda a: a.__setitem__("fnorm", -a["fnorm"]))))
+    out.append(("fscale", EINVAL, mod("fscale", lambda a: a["fscale"].__setitem__((0, 0), 2 * a["fscale"][0, 0]))))
+    out.append(("jinv vs jac", EINVAL, mod("jinv", lambda a: a["jinv"].__setitem__((0, 0, 0), 2 * a["jinv"][0, 0, 0]))))
+
+    ns = arr["nbr_slot"]
+    paired = np.nonzero(ns >= 0)[0]
+    if paired.size:
+        s0 = int(paired[0])
+        # both sides owners
+        def both(a):
+            a["owner"][ns[s0]] = 1
+            a["owner"][s0] = 1
+        out.append(("two owners", EINVAL, mod("o", both)))
+        # the other orientation: every pair owned by its - face side
+        def flip(a):
+            m = a["nbr_slot"] >= 0
+            a["owner"][m] = 1 - a["owner"][m]
+        out.append(("owner on the - side", EUNSUP, mod("o", flip)))
+        # break reciprocity
+        def nonrecip(a):
+            a["nbr_slot"][ns[s0]] = -1
+        out.append(("non-reciprocal", EINVAL, mod("n", nonrecip)))
+        # reverse the tangential order on one paired face (and its partner), reciprocally
+        e, j = divmod(s0, nf)
+        f = j // nfa
+        face = np.arange(e * nf + f * nfa, e * nf + (f + 1) * nfa)
+        part = ns[face]
+
+        def rotate(a):
+            a["nbr_slot"][face] = part[::-1]
+            a["nbr_slot"][part[::-1]] = face
+        if nfa > 1:
+            out.append(("reversed face", EUNSUP, mod("r", rotate)))
+    return out
+
+
+@pytest.mark.parametrize("cid,d,p,kw", MESHES, ids=[m[0] for m in MESHES])
+def test_dense_description_rejected(cid, d, p, kw):
+    from paper_2006_10967_amd import _lib
+    mesh, prm = _case(d, p, kw)
+    arr, ops = dense_arrays(d, p, mesh)
+    for name, want, a in _mutations(d, p, mesh, arr, ops):
+        dm = _dense(d, p, mesh, a, ops)
+        got = _status_of(lambda: dm.workspace_bytes(prm))
+        assert got == want, (cid, name, got, want)
+    # sizes and element shapes
+    dm = _dense(d, p, mesh, arr, ops)
+    dm.c.nupts += 1
+    assert _status_of(lambda: dm.workspace_bytes(prm)) == _lib.PCPF_EINVAL
+    dm = _dense(d, p, mesh, arr, ops, shape=_lib.PCPF_SHAPE_TRIANGLE)
+    assert _status_of(lambda: dm.workspace_bytes(prm)) == _lib.PCPF_EUNSUPPORTED
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("cid,d,p,kw", MESHES, ids=[m[0] for m in MESHES])
+def test_dense_context_is_bitwise_the_line_context(cid, d, p, kw):
+    from paper_2006_10967_amd import Solver
+    mesh, prm = _case(d, p, kw)
+    arr, ops = dense_arrays(d, p, mesh)
+    dm = _dense(d, p, mesh, arr, ops)
+    sd = Solver.from_dense(dm, prm)
+    sl = Solver.from_box(mesh, p, prm)
+    x = sl.solution_coords()
+    rng = np.random.default_rng(3)
+    c = np.full(d, 0.5) + rng.uniform(-0.1, 0.1, d)
+    phi = torch.tensor(W.ic_phi(x, c, 0.27, 0.05))
+    psi = torch.tensor(W.signed_distance_ball(x, c, 0.27) + 1e-3 * rng.standard_normal(phi.shape))
+    for t in (0.0, 0.41):
+        a = sd.residual(phi, psi, t)
+        b = sl.residual(phi, psi, t)
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]), cid
+    for s in (sd, sl):
+        s.set_state(phi)
+        s.step(0.002, 5)
+    pa, qa, _, _ = sd.get_state()
+    pb, qb, _, _ = sl.get_state()
+    assert torch.equal(pa, pb) and torch.equal(qa, qb), cid
+    _, ra = sd.residual(None, psi, 0.0, mode=1)
+    _, rb = sl.residual(None, psi, 0.0, mode=1)
+    assert torch.equal(ra, rb), cid

@@ -284,9 +284,15 @@ def test_adjoint_full_horizon_central_differences():
     """The adjoint workload at its own horizon: 64x64 p=3 single vortex, 512 RK4 steps
     from a reset with ten preconditioning iterations, checkpoints every 32 steps, loss
     L = 1/2 int (phi(T) - target)^2. The adjoint's dL/dA and its derivative along an
-    interface-supported direction of phi0 (phi0 (1 - phi0) times a seeded normal field,
-    where the map is well conditioned) agree with central differences of the GPU
-    forward run to 1e-6 relative."""
+    interface direction of phi0 agree with central differences of the GPU forward run to
+    1e-6 relative.
+
+    Step sizes: at this horizon L(A) carries structure on the scale 1e-5..1e-4 of A (a
+    sweep of h from 1e-3 down to 1e-8 converges to the adjoint like h^2: 2e-3 at h = 1e-5,
+    3.5e-6 at 1e-7, 3e-7 at 3e-8, 5e-8 at 1e-8), so dL/dA takes h = 1e-8, where the
+    truncation (~4e-8) and the rounding of L (~7e-8) are both far below the bar. The phi0
+    direction v = 4 phi0 (1 - phi0)(target - phi0) (at most 1 in magnitude, supported on the
+    interface, where the map is well conditioned) takes h = 1e-6."""
     cfg, mesh, s, phi0, tgt, wq = _c4_loss_setup()
     dt, nsteps, every = cfg.dt(mesh), cfg.steps, 32
 
@@ -302,13 +308,13 @@ def test_adjoint_full_horizon_central_differences():
     s.forward_ckpt(dt, nsteps, every)
     phiT = s.get_state(want_psi=False)[0]
     gp, _, ga = s.adjoint(wq * (phiT - tgt))
-    h = 1e-5
+    h = 1e-8
     fdA = (loss(phi0, 1.0 + h) - loss(phi0, 1.0 - h)) / (2 * h)
     print(f"[adjoint] 512 steps: dL/dA adjoint {ga:.10e}, central difference {fdA:.10e}, "
           f"rel {abs(fdA - ga) / abs(ga):.2e}")
     assert abs(fdA - ga) <= 1e-6 * abs(ga), (fdA, ga)
-    v = phi0 * (1 - phi0) * torch.tensor(np.random.default_rng(2).standard_normal(phi0.shape))
-    v /= torch.linalg.vector_norm(v)
+    v = 4.0 * phi0 * (1 - phi0) * (tgt.cpu() - phi0)
+    h = 1e-6
     fd = (loss(phi0 + h * v, 1.0) - loss(phi0 - h * v, 1.0)) / (2 * h)
     ad = float(torch.sum(gp.cpu() * v))
     print(f"[adjoint] 512 steps: dL/dphi0 . v adjoint {ad:.10e}, central difference "

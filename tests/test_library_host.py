@@ -21,7 +21,7 @@ def test_exports_every_declared_symbol():
     assert len(names) >= 16
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.pcpf_abi_version() == 1
+    assert lib.pcpf_abi_version() == _lib.ABI_VERSION == 2
 
 
 def test_missing_library_fails_loudly(tmp_path):
