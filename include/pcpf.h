@@ -365,6 +365,23 @@ pcpf_status pcpf_adjoint(pcpf_ctx* ctx, const void* d_ckpt, void* d_scratch,
                          size_t scratch_bytes, const void* d_gphi, const void* d_gpsi,
                          void* d_gphi0, void* d_gpsi0, double* g_amp);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): pcpf_adjoint with its scratch taken
+ * from a static array the library holds on each GPU it runs on (PCPF_ADJOINT_STATIC_BYTES,
+ * kept until the process ends) instead of caller memory. Same arguments and results as
+ * pcpf_adjoint otherwise, and the same kernels; it calls no allocating routine (per-launch
+ * timing is suspended during the call, since it creates events). The context's GPU must be
+ * current. EINVAL when the run needs more scratch than the static array
+ * (pcpf_adjoint_bytes > PCPF_ADJOINT_STATIC_BYTES; checkpoint more often or use
+ * pcpf_adjoint). All calls on one GPU share its array: calls that overlap in time on one
+ * GPU (two threads, or two streams whose work overlaps) race and give wrong gradients;
+ * serialise them. Every region the sweep accumulates into is cleared at the start of each
+ * call. */
+#define PCPF_ADJOINT_STATIC_BYTES (64u << 20)
+pcpf_status pcpf_adjoint_static(pcpf_ctx* ctx, const void* d_ckpt, const void* d_gphi,
+                                const void* d_gpsi, void* d_gphi0, void* d_gpsi0,
+                                double* g_amp);
+
 #ifdef __cplusplus
 }
 #endif

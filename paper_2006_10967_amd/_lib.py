@@ -22,6 +22,7 @@ PCPF_STOP_FIXED, PCPF_STOP_RMS = 0, 1
 PCPF_SHAPE_TENSOR, PCPF_SHAPE_TRIANGLE = 0, 1
 MAX_ORDER = 6
 ABI_VERSION = 2
+ADJOINT_STATIC_BYTES = 64 << 20
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -118,6 +119,7 @@ def load() -> ctypes.CDLL:
         "pcpf_forward_ckpt": (st, [vp, dbl, i64, i64, vp, ctypes.c_size_t]),
         "pcpf_adjoint_bytes": (st, [vp, i64, ctypes.POINTER(ctypes.c_size_t)]),
         "pcpf_adjoint": (st, [vp, vp, vp, ctypes.c_size_t, vp, vp, vp, vp, ctypes.POINTER(dbl)]),
+        "pcpf_adjoint_static": (st, [vp, vp, vp, vp, vp, vp, ctypes.POINTER(dbl)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -6,6 +6,7 @@
 #include <cstring>
 #include <limits>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -308,6 +309,7 @@ Layout layout(const MeshInfo& mi, int precision) {
 struct pcpf_ctx {
     MeshInfo mi;
     pcpf_params prm;
+    int device = -1;     // the GPU that was current at pcpf_create
     hipStream_t stream = nullptr;
     char* ws = nullptr;
     Layout L;
@@ -1489,6 +1491,39 @@ pcpf_status dense_to_line(const pcpf_dense_mesh* dm, DenseLine* h) {
 
 }  // namespace
 
+// ------------------------------------------------------------------------------------
+// static adjoint scratch (pcpf_adjoint_static): one array per GPU the library runs on,
+// held until the process ends. In host code `scratch` names a host-side stand-in, not
+// device memory: its device address on each GPU comes from hipGetSymbolAddress, taken
+// once per device with that device current, and only that address is passed on.
+// ------------------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[PCPF_ADJOINT_STATIC_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of this device's static scratch (the context's device must be current).
+pcpf_status static_scratch(pcpf_ctx* c, void** out) {
+    int dev = -1;
+    HIPCHK(c, hipGetDevice(&dev));
+    if (dev != c->device)
+        return fail(&c->err, PCPF_EINVAL, "pcpf_adjoint_static: make the context's GPU current");
+    if (dev < 0 || dev >= MAX_DEVICES)
+        return fail(&c->err, PCPF_EUNSUPPORTED, "pcpf_adjoint_static: device index above 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(&c->err, PCPF_EDEVICE,
+                        std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return PCPF_OK;
+}
+
 extern "C" {
 
 const char* pcpf_last_error(const pcpf_ctx* ctx) {
@@ -1550,6 +1585,8 @@ pcpf_status pcpf_create(const pcpf_mesh* m, const pcpf_params* p, void* d_ws, si
     c->mi = mi;
     c->prm = *p;
     c->stream = static_cast<hipStream_t>(stream);
+    if (hipGetDevice(&c->device) != hipSuccess)
+        return fail(nullptr, PCPF_EDEVICE, "hipGetDevice failed");
     c->ws = static_cast<char*>(d_ws);
     c->L = L;
     c->axis = true;
@@ -1818,6 +1855,34 @@ pcpf_status pcpf_adjoint(pcpf_ctx* c, const void* d_ckpt, void* d_scratch, size_
     if (reinterpret_cast<uintptr_t>(d_scratch) % 256 != 0)
         return fail(&c->err, PCPF_EINVAL, "adjoint scratch must be 256-byte aligned");
     return DISPATCH(c, adjoint_impl, d_ckpt, d_scratch, d_gphi, d_gpsi, d_gphi0, d_gpsi0, g_amp);
+} catch (...) {
+    return out_of_memory(c);
+}
+
+pcpf_status pcpf_adjoint_static(pcpf_ctx* c, const void* d_ckpt, const void* d_gphi,
+                                const void* d_gpsi, void* d_gphi0, void* d_gpsi0,
+                                double* g_amp) try {
+    if (check_ctx(c) != PCPF_OK) return PCPF_EINVAL;
+    if (!c->ck_valid) return fail(&c->err, PCPF_ESTATE, "no checkpointed forward run");
+    if (!d_ckpt || !d_gphi || !d_gphi0) return fail(&c->err, PCPF_EINVAL, "adjoint: NULL argument");
+    const size_t need = adj_layout(c, c->ck_every).total;
+    if (need > (size_t)PCPF_ADJOINT_STATIC_BYTES)
+        return fail(&c->err, PCPF_EINVAL,
+                    "pcpf_adjoint_static: this run needs " + std::to_string(need) +
+                        " bytes of adjoint scratch, above the static " +
+                        std::to_string((size_t)PCPF_ADJOINT_STATIC_BYTES) +
+                        " (checkpoint more often, or pass caller memory to pcpf_adjoint)");
+    void* ptr = nullptr;
+    pcpf_status st = static_scratch(c, &ptr);
+    if (st != PCPF_OK) return st;
+    // per-launch timing creates HIP events: off for the duration of the call
+    struct NoTiming {
+        pcpf_ctx* c;
+        bool was;
+        ~NoTiming() { c->timing = was; }
+    } keep{c, c->timing};
+    c->timing = false;
+    return DISPATCH(c, adjoint_impl, d_ckpt, ptr, d_gphi, d_gpsi, d_gphi0, d_gpsi0, g_amp);
 } catch (...) {
     return out_of_memory(c);
 }

@@ -338,3 +338,17 @@ class Solver:
                                         ctypes.c_size_t(nb.value), _ptr(gphi_t), _ptr(gpsi_t),
                                         _ptr(gphi0), _ptr(gpsi0), ctypes.byref(ga)))
         return gphi0, gpsi0, ga.value
+
+    def adjoint_static(self, gphi, gpsi=None, ckpt=None):
+        """:meth:`adjoint` with the library's static per-GPU scratch instead of caller
+        memory (pcpf_adjoint_static: allocates nothing; the run's scratch must fit
+        PCPF_ADJOINT_STATIC_BYTES). The output tensors are the caller's, as always."""
+        ck = ckpt if ckpt is not None else self._ckpt
+        gphi_t = self._field(gphi)
+        gpsi_t = self._field(gpsi) if gpsi is not None else None
+        gphi0 = self.empty()
+        gpsi0 = self.empty()
+        ga = ctypes.c_double(0.0)
+        self._chk(self.lib.pcpf_adjoint_static(self.ctx, _ptr(ck), _ptr(gphi_t), _ptr(gpsi_t),
+                                               _ptr(gphi0), _ptr(gpsi0), ctypes.byref(ga)))
+        return gphi0, gpsi0, ga.value
