@@ -48,7 +48,7 @@ template <typename R, int D, int P, int V>
 __device__ __forceinline__ void push_minus_faces(const R* s_cm, const R* s_lm, const R* const* s_r,
                                                  const R* const* s_y, const R* s_det,
                                                  const int32_t* r_own, R* const* gp, R* const* Tp,
-                                                 int nel, int tid) {
+                                                 int nel, int tid, int64_t E) {
     using S = AShape<D, P>;
     constexpr int N = S::N, NU = S::NU, NFA = S::NFA;
     constexpr int NMF = D * NFA;
@@ -70,7 +70,7 @@ __device__ __forceinline__ void push_minus_faces(const R* s_cm, const R* s_lm, c
                 tr = M::fma_(s_lm[q], s_y[v][base + q * st<N>(k)], tr);
             }
             gp[v][((int64_t)r_own[j] * D + k) * NFA + t] = acc * rd;
-            Tp[v][((int64_t)r_own[j] * D + k) * NFA + t] = tr;
+            Tp[v][((int64_t)k * E + r_own[j]) * NFA + t] = tr;   // planar [D][E][NFA]
         }
     }
 }
@@ -143,7 +143,7 @@ __global__ __launch_bounds__((AShape<D, P>::NT)) void k_adj_push(AJPush<R> a) {
         sr[v] = s_r[v];
         sy[v] = s_y[v];
     }
-    push_minus_faces<R, D, P, V>(s_cm, s_lm, sr, sy, s_det, r_own, a.gp, a.Tp, nel, tid);
+    push_minus_faces<R, D, P, V>(s_cm, s_lm, sr, sy, s_det, r_own, a.gp, a.Tp, nel, tid, a.E);
 }
 
 // ------------------------------------------------------------------------------------
@@ -238,7 +238,11 @@ __global__ __launch_bounds__((AShape<D, P>::NT)) void k_adj_main(AJMain<R> a) {
     for (int j = 0; j < I_NB; ++j) {
         const int it = tid + j * NT;
 #pragma unroll
-        for (int v = 0; v < V; ++v) r_nb[j][v] = (it < nel * NPF) ? a.Tp[v][e0 * NPF + it] : R(0);
+        for (int v = 0; v < V; ++v) {
+            // the forward traces are planar, [D][E][NFA]
+            const int el = it / NPF, kf = (it - el * NPF) / NFA, tf = it - el * NPF - kf * NFA;
+            r_nb[j][v] = (it < nel * NPF) ? a.Tp[v][((int64_t)kf * a.E + e0 + el) * NFA + tf] : R(0);
+        }
     }
     R rb[V];
     R r_sg = R(0), r_sb = R(0);
@@ -883,7 +887,7 @@ __global__ __launch_bounds__((AShape<D, P>::NT)) void k_adj_finish(AJFinish<R> a
         sr[v] = s_r[v];
         sy[v] = s_y[v];
     }
-    push_minus_faces<R, D, P, V>(s_cm, s_lm, sr, sy, s_det, r_own, a.gp, a.Tp, nel, tid);
+    push_minus_faces<R, D, P, V>(s_cm, s_lm, sr, sy, s_det, r_own, a.gp, a.Tp, nel, tid, a.E);
 }
 
 // elementwise helpers of the reverse sweep

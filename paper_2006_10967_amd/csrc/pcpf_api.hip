@@ -262,7 +262,7 @@ pcpf_status check_geometry(const pcpf_mesh* m, const MeshInfo& mi, std::string* 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t un, us, acc, P, Fp, Fm, Tp, sgn, geo, vtab, det64, w64, nbr, ops, flag, partial, red, res;
+    size_t un, us, acc, P, Fp, Tp, sgn, geo, vtab, det64, w64, nbr, ops, flag, partial, red, res;
     size_t total;
 };
 
@@ -283,9 +283,8 @@ Layout layout(const MeshInfo& mi, int precision) {
     L.us = take(state);
     L.acc = take(state);
     L.P = take(state);
-    L.Fp = take(face);
-    L.Fm = take(face);
-    L.Tp = take(face);
+    L.Fp = take(2 * face);   // [V][2D][E][NFA]: + face fluxes, then boundary - face fluxes
+    L.Tp = take(face);       // [V][D][E][NFA]
     L.sgn = take(E * mi.nu * r);
     L.geo = take(E * geo * r);
     L.vtab = take(E * mi.d * (mi.n + 2) * 2 * r);   // velocity tables (axis-aligned meshes)
@@ -359,6 +358,10 @@ struct Ctx {
     R* fplane(size_t off, int v) const {
         return reinterpret_cast<R*>(c->ws + off) + (size_t)v * c->mi.E * c->mi.d * c->mi.nfa;
     }
+    // variable v of the common-flux buffer (2D planes of E N_fa per variable)
+    R* flux(int v) const {
+        return reinterpret_cast<R*>(c->ws + c->L.Fp) + (size_t)v * 2 * c->mi.E * c->mi.d * c->mi.nfa;
+    }
     template <typename T>
     T* at(size_t off) const {
         return reinterpret_cast<T*>(c->ws + off);
@@ -413,8 +416,7 @@ GFArgs<R> gf_args(const Ctx<R>& C, const R* u0, const R* u1, double t) {
     a.u[1] = u1;
     for (int v = 0; v < 2; ++v) {
         a.P[v] = C.plane(c->L.P, v);
-        a.Fp[v] = C.fplane(c->L.Fp, v);
-        a.Fm[v] = C.fplane(c->L.Fm, v);
+        a.Fp[v] = C.flux(v);
         a.Tp[v] = C.fplane(c->L.Tp, v);
     }
     a.geo = C.template at<R>(c->L.geo);
@@ -439,7 +441,6 @@ void psi_only(GFArgs<R>& a) {
     a.u[0] = a.u[1];
     a.P[0] = a.P[1];
     a.Fp[0] = a.Fp[1];
-    a.Fm[0] = a.Fm[1];
     a.Tp[0] = a.Tp[1];
 }
 
@@ -449,8 +450,7 @@ UPArgs<R> up_args(const Ctx<R>& C) {
     UPArgs<R> a{};
     for (int v = 0; v < 2; ++v) {
         a.P[v] = C.plane(c->L.P, v);
-        a.Fp[v] = C.fplane(c->L.Fp, v);
-        a.Fm[v] = C.fplane(c->L.Fm, v);
+        a.Fp[v] = C.flux(v);
         a.un[v] = C.plane(c->L.un, v);
         a.uo[v] = nullptr;
         a.acc[v] = C.plane(c->L.acc, v);
@@ -470,7 +470,6 @@ template <typename R>
 void up_psi_only(UPArgs<R>& a) {
     a.P[0] = a.P[1];
     a.Fp[0] = a.Fp[1];
-    a.Fm[0] = a.Fm[1];
     a.un[0] = a.un[1];
     a.acc[0] = a.acc[1];
     a.us[0] = a.us[1];

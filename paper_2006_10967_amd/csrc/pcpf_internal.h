@@ -93,9 +93,10 @@ template <typename R>
 struct GFArgs {
     const R* u[2];       // stage input per variable ([E][NU])
     R* P[2];             // partial divergence per variable
-    R* Fp[2];            // common flux on the own + faces             [E][D][NFA]
-    R* Fm[2];            // common flux on - faces (pushed by the owner) [E][D][NFA]
-    const R* Tp[2];      // neighbour traces on the own + faces (pushed) [E][D][NFA]
+    R* Fp[2];            // common fluxes per variable, [2D][E][NFA]: plane k < D the flux of
+                         // the + face k (its owner's), plane D + k the flux of the - face k
+                         // where it lies on a boundary (written only there)
+    const R* Tp[2];      // neighbour traces on the own + faces (pushed), [D][E][NFA]
     const R* geo;        // [E][GEO]
     const int32_t* nbr;  // [E][2D]
     const R* ops;
@@ -122,14 +123,15 @@ enum { UP_RK = 0, UP_RESID = 1 };
 template <typename R>
 struct UPArgs {
     const R* P[2];
-    const R* Fp[2];
-    const R* Fm[2];
+    const R* Fp[2];      // common fluxes [2D][E][NFA] (as GFArgs::Fp); the flux of an interior
+                         // - face is minus the owner's + face flux
     R* un[2];            // u_n (read; written on the last stage)
     R* uo[2];            // null, or a second destination of u_{n+1} on the last stage
     R* acc[2];           // RK accumulator
     R* us[2];            // next stage input (written on stages 0-2)
     R* res[2];           // residual output (UP_RESID)
-    R* Tp[2];            // - face traces of the next stage input, pushed to the owners
+    R* Tp[2];            // - face traces of the next stage input, pushed to the owners'
+                         // + face slots, [D][E][NFA]
     const R* geo;
     const int32_t* nbr;
     const R* ops;

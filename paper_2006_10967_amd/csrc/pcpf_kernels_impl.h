@@ -12,13 +12,15 @@
 // LDG orientation (§3.1 Step 2 with beta = +-1/2): the element on the - side of a face
 // owns it. Its common solution is the neighbour's trace (so only + faces carry a jump in
 // the corrected gradient), and it computes the common normal flux (Step 5) from its own
-// viscous flux. Hence only two fields cross element boundaries per stage, and both are
-// pushed by their producer into the consumer's own slots, so that every load of both
-// kernels is indexed by the loading element: the traces of - faces (written by update
-// into the owner's + face slots Tp) and the common flux (written by grad_flux into its own
-// + face slots Fp and, negated, into the neighbour's - face slots Fm). Boundary faces (no
-// neighbour) use the ghost state B(u) = u, B(q) = q of §3.3 and are computed by the
-// element itself.
+// viscous flux. Hence only two fields cross element boundaries per stage: the traces of
+// - faces, pushed by update into the owner's + face slots Tp, and the common flux, which
+// grad_flux writes once into its own + face slots Fp and which update reads, negated, for
+// the neighbour's - face. Both face arrays are planar by reference direction, [D][E][NFA]:
+// the NFA points of one face of consecutive elements are consecutive, so the block-sized
+// runs of every face access (traces pushed to e - stride_k, fluxes gathered from there)
+// are contiguous. Boundary faces (no neighbour) use the ghost state B(u) = u, B(q) = q of
+// §3.3 and are computed by the element itself; a boundary - face flux goes to plane D + k
+// of Fp.
 #pragma once
 
 #include <hip/hip_ext.h>
@@ -160,13 +162,24 @@ void k_grad_flux(GFArgs<R> a) {
     }
     // neighbour traces on the + faces, pushed here by the neighbours (boundary + face
     // slots are zeroed when the context is created and never written)
+    // slots: lanes run over [k][el NFA + t], contiguous within each direction's plane
+    constexpr int KSEG = S::KSEG;
+    const uint32_t Eu = (uint32_t)a.E;
     R r_nb[GRAD ? I_NB : 1][V];
+    int nb_pos[GRAD ? I_NB : 1];
     if constexpr (GRAD) {
 #pragma unroll
         for (int j = 0; j < I_NB; ++j) {
             const int it = tid + j * NT;
+            int k = it / KSEG;
+            int r = it - k * KSEG;
+            const bool ok = k < D && r < nel * NFA;
+            nb_pos[j] = ok ? (r / NFA) * NPF + k * NFA + (r % NFA) : -1;
+            k = k < D ? k : D - 1;
+            r = r < nel * NFA ? r : nel * NFA - 1;
+            const uint32_t gi = ((uint32_t)k * Eu + (uint32_t)e0) * NFA + (uint32_t)r;
 #pragma unroll
-            for (int v = 0; v < V; ++v) r_nb[j][v] = gld_in(a.Tp[v] + e0 * NPF, it, nel * NPF);
+            for (int v = 0; v < V; ++v) r_nb[j][v] = gld(a.Tp[v], gi);
         }
     }
     // velocity tables of the block's elements (sin^2(pi x_k) and sin(2 pi x_k) at the line
@@ -197,9 +210,9 @@ void k_grad_flux(GFArgs<R> a) {
     if constexpr (GRAD) {
 #pragma unroll
         for (int j = 0; j < I_NB; ++j)
-            if (tid + j * NT < nel * NPF)
+            if (nb_pos[j] >= 0)
 #pragma unroll
-                for (int v = 0; v < V; ++v) s_nb[v][tid + j * NT] = r_nb[j][v];
+                for (int v = 0; v < V; ++v) s_nb[v][nb_pos[j]] = r_nb[j][v];
     }
     // outward unit normal n = J^-T e_k / |J^-T e_k| and scale |J| |J^-T e_k| of face +k
     if constexpr (FLUX && !AXIS) {
@@ -532,7 +545,8 @@ void k_grad_flux(GFArgs<R> a) {
                 }
                 qn[v] = acc_n;
             }
-            const uint32_t fo = (el * D + K) * NFA + t;   // from the block's first element
+            // slot of this face point in plane K (+ face) or D + K (boundary - face)
+            const uint32_t fo = (((uint32_t)(SD ? K : D + K)) * Eu + (uint32_t)(e0 + el)) * NFA + t;
             if constexpr (MODE == GF_PHYS) {
                 const R* xi = &s_ops[op_xi(N)];
                 R vel[D];
@@ -592,28 +606,11 @@ void k_grad_flux(GFArgs<R> a) {
                 const R F0 = R(0.5) * (pL + pR) * vn - fvn + a.ph.tau * (pL - pR);
                 const R F1 = R(0.5) * (sL + sR) * vn + a.ph.tau * (sL - sR);
                 const R G0 = sc * F0, G1 = sc * F1;
-                if constexpr (SD == 1) {
-                    gst(a.Fp[0] + e0 * NPF, fo, G0);
-                    gst(a.Fp[1] + e0 * NPF, fo, G1);
-                    if (en >= 0) {
-                        // the neighbour's - face: same flux, its outward normal is -n
-                        const uint32_t fn_ = ((uint32_t)en * D + K) * NFA + t;
-                        gst(a.Fm[0], fn_, -G0);
-                        gst(a.Fm[1], fn_, -G1);
-                    }
-                } else {
-                    gst(a.Fm[0] + e0 * NPF, fo, G0);
-                    gst(a.Fm[1] + e0 * NPF, fo, G1);
-                }
+                gst(a.Fp[0], fo, G0);
+                gst(a.Fp[1], fo, G1);
             } else {
                 const R F = -s_nu[el] * qn[0] + a.ph.tau * (uL[0] - uR[0]);
-                const R G0 = sc * F;
-                if constexpr (SD == 1) {
-                    gst(a.Fp[0] + e0 * NPF, fo, G0);
-                    if (en >= 0) gst(a.Fm[0], ((uint32_t)en * D + K) * NFA + t, -G0);
-                } else {
-                    gst(a.Fm[0] + e0 * NPF, fo, G0);
-                }
+                gst(a.Fp[0], fo, sc * F);
             }
         };
         // wave-uniform direction: each unit is one wave's worth of one direction's points
@@ -748,7 +745,7 @@ __device__ __forceinline__ void load_owners(int32_t (&r_own)[U], const int32_t* 
 template <typename R, int D, int P, int V, int U>
 __device__ __forceinline__ void push_traces(R* const* Tp, const R* lm, const R* su0,
                                             const R* su1, const int32_t (&r_own)[U], int nel,
-                                            int wave, int lane) {
+                                            int wave, int lane, uint32_t E) {
     using S = Shape<D, P>;
     constexpr int N = S::N, NU = S::NU, NFA = S::NFA;
     auto push = [&](auto KC, int el, int t, int32_t own) {
@@ -761,7 +758,7 @@ __device__ __forceinline__ void push_traces(R* const* Tp, const R* lm, const R* 
             R acc = R(0);
 #pragma unroll
             for (int q = 0; q < N; ++q) acc += lm[q] * su[base + q * SK];
-            gst(Tp[v], ((uint32_t)own * D + K) * NFA + t, acc);
+            gst(Tp[v], ((uint32_t)K * E + (uint32_t)own) * NFA + t, acc);
         }
     };
 #pragma unroll
@@ -828,19 +825,39 @@ __global__ __launch_bounds__((Shape<D, P>::NT)) void k_update(UPArgs<R> a) {
     r_c[0] = gld_in(a.ops + op_cm(N), tid, N);
     r_c[1] = gld_in(a.ops + op_cp(N), tid, N);
     r_c[2] = gld_in(a.ops + op_lm(N), tid, N);
+    // lanes run over [face f = 2k + s][el NFA + t]: the + face fluxes of the block are
+    // contiguous in plane k; the - face flux is minus the owner's + face flux in plane k
+    // (the owners e - stride_k of consecutive elements are consecutive), or on a boundary
+    // the element's own, in plane D + k
+    constexpr int KSEG = S::KSEG;
+    const uint32_t Eu = (uint32_t)a.E;
     R r_F[I_F][V];
+    int f_pos[I_F];
+    bool f_neg[I_F];
 #pragma unroll
     for (int j = 0; j < I_F; ++j) {
-        const int it = (tid + j * NT < nel * NFE) ? tid + j * NT : nel * NFE - 1;
-        const int el = it / NFE;
-        const int r = it - el * NFE;
-        const int f = r / NFA;
-        const int t = r - f * NFA;
-        const int k = f >> 1, s = f & 1;
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-            r_F[j][v] = gld((s ? a.Fp[v] : a.Fm[v]) + e0 * D * NFA, (el * D + k) * NFA + t);
+        const int it = tid + j * NT;
+        int f = it / KSEG;
+        int r = it - f * KSEG;
+        const bool ok = f < 2 * D && r < nel * NFA;
+        f = f < 2 * D ? f : 2 * D - 1;
+        r = r < nel * NFA ? r : nel * NFA - 1;
+        const int el = r / NFA, t = r - el * NFA;
+        const int k = f >> 1, sd = f & 1;
+        f_pos[j] = ok ? el * NFE + f * NFA + t : -1;
+        uint32_t gi;
+        bool neg = false;
+        if (sd) {
+            gi = ((uint32_t)k * Eu + (uint32_t)e0) * NFA + (uint32_t)r;
+        } else {
+            const int32_t en = gld(a.nbr, (uint32_t)((e0 + el) * 2 * D + 2 * k));
+            neg = en >= 0;
+            gi = neg ? ((uint32_t)k * Eu + (uint32_t)en) * NFA + t
+                     : ((uint32_t)(D + k) * Eu + (uint32_t)(e0 + el)) * NFA + t;
         }
+        f_neg[j] = neg;
+#pragma unroll
+        for (int v = 0; v < V; ++v) r_F[j][v] = gld(a.Fp[v], gi);
     }
     if (tid < N) {
         s_c[tid] = r_c[0];
@@ -849,9 +866,9 @@ __global__ __launch_bounds__((Shape<D, P>::NT)) void k_update(UPArgs<R> a) {
     }
 #pragma unroll
     for (int j = 0; j < I_F; ++j)
-        if (tid + j * NT < nel * NFE)
+        if (f_pos[j] >= 0)
 #pragma unroll
-            for (int v = 0; v < V; ++v) s_F[v][tid + j * NT] = r_F[j][v];
+            for (int v = 0; v < V; ++v) s_F[v][f_pos[j]] = f_neg[j] ? -r_F[j][v] : r_F[j][v];
     __syncthreads();
 
     if (pt) {
@@ -900,7 +917,8 @@ __global__ __launch_bounds__((Shape<D, P>::NT)) void k_update(UPArgs<R> a) {
     if constexpr (KIND == UP_RK) {
         __syncthreads();
         // - face traces of the next stage input, pushed into the owners' + face slots
-        push_traces<R, D, P, V, S::UPW>(a.Tp, &s_c[2 * N], s_u[0], s_u[V - 1], r_own, nel, wave, lane);
+        push_traces<R, D, P, V, S::UPW>(a.Tp, &s_c[2 * N], s_u[0], s_u[V - 1], r_own, nel, wave, lane,
+                                        (uint32_t)a.E);
     }
 }
 
@@ -936,7 +954,8 @@ __global__ __launch_bounds__((Shape<D, P>::NT)) void k_trace(TRArgs<R> a) {
         for (int j = 0; j < I_U; ++j)
             if (tid + j * NT < nel * NU) s_u[v][tid + j * NT] = r_u[v][j];
     __syncthreads();
-    push_traces<R, D, P, V, S::UPW>(a.Tp, s_lm, s_u[0], s_u[V - 1], r_own, nel, wave, lane);
+    push_traces<R, D, P, V, S::UPW>(a.Tp, s_lm, s_u[0], s_u[V - 1], r_own, nel, wave, lane,
+                                    (uint32_t)a.E);
 }
 
 // FP64 quadrature reduction, first pass: block partial sums in a fixed order.
