@@ -722,14 +722,523 @@ void k_grad_flux(GFArgs<R> a) {
 }
 
 // ------------------------------------------------------------------------------------
+// grad_flux, physical mode, by element lines (3D): the same Steps 1-5 and volume part of
+// Step 6 as k_grad_flux, with every line product done in registers by one thread per
+// element line instead of one LDS read per operator entry per point.
+//   A   loads, as k_grad_flux.
+//   B1  line threads (direction K uniform in a wave): the line's N values of each variable
+//       from LDS, the corrected derivative along K at its N points (Step 3) to LDS, and in
+//       registers the + face values of the line: the own trace, the neighbour's trace and
+//       the interpolated K component of the gradient.
+//   B2  line threads: the common flux of the + face point (Step 5), reading only the other
+//       gradient components at the face; all threads: the flux at their solution point
+//       (Step 4) to LDS.
+//   E1  line threads: DH_K applied along the line (volume part of Step 6), to LDS.
+//   E2  all threads: P = the sum over the directions (fixed order), to global.
+// On axis-aligned meshes the LDS holds the physical gradient (one metric factor per
+// component); otherwise the reference components, transformed where they are used.
+// ------------------------------------------------------------------------------------
+// Occupancy target (waves per SIMD). In float64 the kernel holds 86-114 VGPRs, which caps
+// it at 4-5 waves; forcing more, with a few registers spilled to scratch, overlaps the
+// blocks' load, LDS and arithmetic phases better (96^3 p4: 2382 us at 4, 2141 at 5, 2066 at
+// 6; 64^3 p3: 281 at 5, 268 at 6, 257 at 7). The float32 form fits 8 waves anyway.
+constexpr int lines_waves(int p) { return p <= 3 ? 7 : 6; }
+template <typename R, int D, int P, bool AXIS, bool NPHI>
+__global__ __launch_bounds__((Shape<D, P>::NT))
+__attribute__((amdgpu_waves_per_eu(lines_waves(P))))
+void k_grad_flux_lines(GFArgs<R> a) {
+    using S = Shape<D, P>;
+    constexpr int N = S::N, NU = S::NU, NFA = S::NFA, EPB = S::EPB, NT = S::NT, G = S::GEO;
+    constexpr int V = 2;
+    constexpr int NV = NPHI ? 0 : 1;               // variable the interface normal is of
+    constexpr int NOPS = ops_size(N);
+    constexpr int NPF = D * NFA;
+    constexpr int NTB = N + 2;
+    constexpr int XST = EPB * NU;
+    constexpr int KSEG = S::KSEG;
+    constexpr int UPW = S::UPW;
+    using M = Math<R>;
+
+    __shared__ R s_ops[NOPS];
+    __shared__ R s_geo[EPB * G];
+    __shared__ R s_u[V][XST];
+    // one field of V D components per point, reused in place: the gradient (B1), the flux
+    // at the point (B2, each thread overwriting its own point), the directions' DH f~ (E1,
+    // each line thread overwriting its own line)
+    __shared__ R s_x[V * D * XST];
+    __shared__ R s_nb[V][EPB * NPF];                // + face neighbour traces
+    __shared__ R s_vt[AXIS ? EPB * D * NTB * 2 : 1];
+    __shared__ R s_fn[AXIS ? 1 : EPB * D * (D + 1)]; // + face unit normal, scale
+    __shared__ int s_nbr[EPB * 2 * D];
+
+    const int tid = threadIdx.x;
+    const int64_t e0 = (int64_t)block_chunk<R>(a.E * NU) * EPB;
+    const int nel = (int)((a.E - e0) < EPB ? (a.E - e0) : EPB);
+    const bool pt = tid < nel * NU;
+    const int le = tid / NU;
+    const int ip = tid - le * NU;
+    const uint32_t Eu = (uint32_t)a.E;
+    const bool trig = a.ph.vel_kind == PCPF_VEL_SINGLE_VORTEX || a.ph.vel_kind == PCPF_VEL_LEVEQUE3D;
+
+    // ---- A: loads (every global load issued before the first wait) ----------------------
+    constexpr int I_OPS = (NOPS + NT - 1) / NT;
+    constexpr int I_GEO = (EPB * G + NT - 1) / NT;
+    constexpr int I_NBR = (EPB * 2 * D + NT - 1) / NT;
+    constexpr int I_U = (EPB * NU + NT - 1) / NT;
+    constexpr int I_NB = (EPB * NPF + NT - 1) / NT;
+    constexpr int I_TB = AXIS ? (EPB * D * NTB * 2 + NT - 1) / NT : 1;
+    R r_ops[I_OPS], r_geo[I_GEO], r_u[V][I_U];
+    int32_t r_nbr[I_NBR];
+#pragma unroll
+    for (int j = 0; j < I_OPS; ++j) r_ops[j] = gld_in(a.ops, tid + j * NT, NOPS);
+#pragma unroll
+    for (int j = 0; j < I_GEO; ++j) r_geo[j] = gld_in(a.geo + e0 * G, tid + j * NT, nel * G);
+#pragma unroll
+    for (int j = 0; j < I_NBR; ++j) r_nbr[j] = gld_in(a.nbr + e0 * 2 * D, tid + j * NT, nel * 2 * D);
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+        for (int j = 0; j < I_U; ++j) r_u[v][j] = gld_in(a.u[v] + e0 * NU, tid + j * NT, nel * NU);
+    R r_ji[D], r_det = R(1);
+    const bool fn_thread = !AXIS && tid < nel * D;
+    if constexpr (!AXIS) {
+        if (fn_thread) {
+            const int el = tid / D, k = tid - el * D;
+            const R* gb = a.geo + e0 * G;
+#pragma unroll
+            for (int i = 0; i < D; ++i) r_ji[i] = gld(gb, el * G + D + D * D + k * D + i);
+            r_det = gld(gb, el * G + D + 2 * D * D);
+        }
+    }
+    // neighbour traces: lanes over [k][el NFA + t], contiguous in each direction's plane
+    R r_nb[I_NB][V];
+    int nb_pos[I_NB];
+#pragma unroll
+    for (int j = 0; j < I_NB; ++j) {
+        const int it = tid + j * NT;
+        int k = it / KSEG;
+        int r = it - k * KSEG;
+        const bool ok = k < D && r < nel * NFA;
+        nb_pos[j] = ok ? (r / NFA) * NPF + k * NFA + (r % NFA) : -1;
+        k = k < D ? k : D - 1;
+        r = r < nel * NFA ? r : nel * NFA - 1;
+        const uint32_t gi = ((uint32_t)k * Eu + (uint32_t)e0) * NFA + (uint32_t)r;
+#pragma unroll
+        for (int v = 0; v < V; ++v) r_nb[j][v] = gld(a.Tp[v], gi);
+    }
+    R r_vt[I_TB];
+    if constexpr (AXIS) {
+#pragma unroll
+        for (int j = 0; j < I_TB; ++j)
+            r_vt[j] = trig ? gld_in(a.vtab + e0 * D * NTB * 2, tid + j * NT, nel * D * NTB * 2) : R(0);
+    }
+#pragma unroll
+    for (int j = 0; j < I_OPS; ++j)
+        if (tid + j * NT < NOPS) s_ops[tid + j * NT] = r_ops[j];
+#pragma unroll
+    for (int j = 0; j < I_GEO; ++j)
+        if (tid + j * NT < nel * G) s_geo[tid + j * NT] = r_geo[j];
+#pragma unroll
+    for (int j = 0; j < I_NBR; ++j)
+        if (tid + j * NT < nel * 2 * D) s_nbr[tid + j * NT] = r_nbr[j];
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+        for (int j = 0; j < I_U; ++j)
+            if (tid + j * NT < nel * NU) s_u[v][tid + j * NT] = r_u[v][j];
+#pragma unroll
+    for (int j = 0; j < I_NB; ++j)
+        if (nb_pos[j] >= 0)
+#pragma unroll
+            for (int v = 0; v < V; ++v) s_nb[v][nb_pos[j]] = r_nb[j][v];
+    if constexpr (!AXIS) {
+        if (fn_thread) {
+            R mag2 = R(0);
+#pragma unroll
+            for (int i = 0; i < D; ++i) mag2 += r_ji[i] * r_ji[i];
+            const R mag = M::sqrt_(mag2);
+            R* fn = &s_fn[tid * (D + 1)];
+#pragma unroll
+            for (int i = 0; i < D; ++i) fn[i] = r_ji[i] / mag;
+            fn[D] = r_det * mag;
+        }
+    }
+    if constexpr (AXIS) {
+        if (trig) {
+#pragma unroll
+            for (int j = 0; j < I_TB; ++j)
+                if (tid + j * NT < nel * D * NTB * 2) s_vt[tid + j * NT] = r_vt[j];
+        }
+    }
+    __syncthreads();
+
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const R* lp = &s_ops[op_lp(N)];
+    const R* cpv = &s_ops[op_cp(N)];
+    const R* xi = &s_ops[op_xi(N)];
+    // line units: unit u = wave + j NW covers direction k = u / WK (uniform in the wave) and
+    // the lines (u % WK) 64 + lane of that direction: element el, + face point t
+    auto for_units = [&](auto body) {
+#pragma unroll
+        for (int j = 0; j < UPW; ++j) {
+            const int u = wave + j * S::NW;
+            if (u >= S::NUNITS) break;
+            const int k = u / S::WK;
+            const int item = (u - k * S::WK) * 64 + lane;
+            if (item >= nel * NFA) continue;
+            const int el = item / NFA, t = item - el * NFA;
+            if (k == 0) {
+                body(std::integral_constant<int, 0>{}, j, el, t);
+            } else if (k == 1) {
+                body(std::integral_constant<int, 1>{}, j, el, t);
+            } else if constexpr (D == 3) {
+                body(std::integral_constant<int, 2>{}, j, el, t);
+            }
+        }
+    };
+
+    // ---- B1: corrected derivative along each line (Steps 1-3) ---------------------------
+    R fu[UPW][V], fnb[UPW][V], fq[UPW][V];     // + face: own trace, neighbour trace, q_K
+    for_units([&](auto KC, int j, int el, int t) {
+        constexpr int K = decltype(KC)::value;
+        constexpr int SK = st<N>(K);
+        const int base = el * NU + face_base<D, N>(K, t);
+        // + face with a neighbour: the LDG jump (nb - own trace) is lifted; the own-trace
+        // part is folded into DT = D1 - cp (x) lp (boundary + faces: s_nb holds 0)
+        const bool hk = s_nbr[el * 2 * D + 2 * K + 1] >= 0;
+        const R* Dm = &s_ops[hk ? op_dt(N) : OP_D1];
+        const R jkk = AXIS ? s_geo[el * G + D + D * D + K * D + K] : R(1);
+        R ul[V][N], nbv[V], uf[V], qf[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+#pragma unroll
+            for (int q = 0; q < N; ++q) ul[v][q] = s_u[v][base + q * SK];
+            nbv[v] = s_nb[v][el * NPF + K * NFA + t];
+            uf[v] = R(0);
+            qf[v] = R(0);
+        }
+        // one operator row at a time, applied to both variables
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            R row[N];
+#pragma unroll
+            for (int b = 0; b < N; ++b) row[b] = Dm[q * N + b];
+            const R c = cpv[q], l = lp[q];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                R acc = R(0);
+#pragma unroll
+                for (int b = 0; b < N; ++b) acc += row[b] * ul[v][b];
+                acc += c * nbv[v];
+                const R qv = AXIS ? jkk * acc : acc;
+                s_x[(v * D + K) * XST + base + q * SK] = qv;
+                uf[v] += l * ul[v][q];
+                qf[v] += l * qv;
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            fu[j][v] = uf[v];
+            fnb[j][v] = nbv[v];
+            fq[j][v] = qf[v];
+        }
+    });
+    __syncthreads();
+
+    // ---- B2: common normal flux on the + face points (Step 5) ----------------------------
+    // velocity at reference position pos (node indices, N / N + 1 for the -1 / +1 end)
+    auto vel_at = [&](int el, const int (&pos)[D], R (&vel)[D]) {
+        const R* gg = &s_geo[el * G];
+        if constexpr (AXIS) {
+            if (trig) {
+                velocity_tab<R, D, NTB>(a.ph, &s_vt[el * D * NTB * 2], pos, vel);
+            } else {
+                R x[D];
+#pragma unroll
+                for (int m = 0; m < D; ++m) {
+                    const R xr = pos[m] == N ? R(0) : (pos[m] == N + 1 ? R(2) : xi[pos[m]] + R(1));
+                    x[m] = gg[m] + gg[D + m * D + m] * xr;
+                }
+                velocity_lin<R, D>(a.ph, x, vel);
+            }
+        } else {
+            R x[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                R acc = gg[i];
+#pragma unroll
+                for (int m = 0; m < D; ++m) {
+                    const R xr = pos[m] == N ? R(0) : (pos[m] == N + 1 ? R(2) : xi[pos[m]] + R(1));
+                    acc += gg[D + i * D + m] * xr;
+                }
+                x[i] = acc;
+            }
+            velocity<R, D>(a.ph, x, vel);
+        }
+    };
+    // the common flux of face point t of face (K, SD) from its traces and gradient
+    auto face_flux = [&](auto KC, auto SC, int el, int t, int32_t en, const R (&uL)[V],
+                         const R (&uR)[V], const R (&qfa)[V][D]) {
+        constexpr int K = decltype(KC)::value;
+        constexpr int SD = decltype(SC)::value;
+        const R* gg = &s_geo[el * G];
+        R nrm[D], sc;
+        if constexpr (AXIS) {
+            const R jk = gg[D + D * D + K * D + K];
+            sc = gg[D + 2 * D * D] * M::fabs_(jk);
+#pragma unroll
+            for (int i = 0; i < D; ++i) nrm[i] = R(0);
+            nrm[K] = ((jk > R(0)) == (SD == 1)) ? R(1) : R(-1);
+        } else {
+            const R* fn = &s_fn[(el * D + K) * (D + 1)];
+            sc = fn[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) nrm[i] = SD ? fn[i] : -fn[i];
+        }
+        R qn[V], g2 = R(0);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            R acc_n = R(0);
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                if constexpr (AXIS) {
+                    if (i == K) acc_n = qfa[v][K] * nrm[K];
+                } else {
+                    acc_n += qfa[v][i] * nrm[i];
+                }
+                if (v == NV) g2 += qfa[v][i] * qfa[v][i];
+            }
+            qn[v] = acc_n;
+        }
+        int pos[D];
+        {
+            int tt = t;
+#pragma unroll
+            for (int m = 0; m < D; ++m) {
+                if (m == K) {
+                    pos[m] = N + SD;
+                } else {
+                    pos[m] = tt % N;
+                    tt /= N;
+                }
+            }
+        }
+        R vel[D];
+        vel_at(el, pos, vel);
+        R v2 = R(0), vn = R(0);
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            v2 += vel[i] * vel[i];
+            if constexpr (AXIS) {
+                if (i == K) vn = vel[K] * nrm[K];
+            } else {
+                vn += vel[i] * nrm[i];
+            }
+        }
+        const R mm = max_sqrt(v2, a.ph.gamma);
+        const R rn = M::rsqrt_(g2 + a.ph.delta_n * a.ph.delta_n);
+        const R pL = uL[0], pR = uR[0], sL = uL[1], sR = uR[1];
+        const R fvn = mm * (a.ph.eps * qn[0] - a.ph.gamma * pL * (R(1) - pL) * qn[NV] * rn);
+        const R F0 = R(0.5) * (pL + pR) * vn - fvn + a.ph.tau * (pL - pR);
+        const R F1 = R(0.5) * (sL + sR) * vn + a.ph.tau * (sL - sR);
+        const uint32_t fo = (((uint32_t)(SD ? K : D + K)) * Eu + (uint32_t)(e0 + el)) * NFA + t;
+        gst(a.Fp[0], fo, sc * F0);
+        gst(a.Fp[1], fo, sc * F1);
+        (void)en;
+    };
+    // physical gradient at a face point from its interpolated reference (non-axis) or
+    // physical (axis) components
+    auto to_physical = [&](int el, const R (&qt)[D], R (&q)[D]) {
+        if constexpr (AXIS) {
+#pragma unroll
+            for (int i = 0; i < D; ++i) q[i] = qt[i];
+        } else {
+            const R* Ji = &s_geo[el * G + D + D * D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                R acc = R(0);
+#pragma unroll
+                for (int k = 0; k < D; ++k) acc += Ji[k * D + i] * qt[k];
+                q[i] = acc;
+            }
+        }
+    };
+    for_units([&](auto KC, int j, int el, int t) {
+        constexpr int K = decltype(KC)::value;
+        constexpr int SK = st<N>(K);
+        const int base = el * NU + face_base<D, N>(K, t);
+        const int32_t en = s_nbr[el * 2 * D + 2 * K + 1];
+        R uL[V], uR[V], qfa[V][D];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            uL[v] = fu[j][v];
+            uR[v] = (en >= 0) ? fnb[j][v] : fu[j][v];
+            // the components other than K, interpolated to the face along the line (on
+            // axis-aligned meshes only those of the interface normal's variable are needed)
+            R qt[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                if (i == K) {
+                    qt[i] = fq[j][v];
+                } else if (!AXIS || v == NV) {
+                    R acc = R(0);
+#pragma unroll
+                    for (int q = 0; q < N; ++q) acc += lp[q] * s_x[(v * D + i) * XST + base + q * SK];
+                    qt[i] = acc;
+                } else {
+                    qt[i] = R(0);
+                }
+            }
+            to_physical(el, qt, qfa[v]);
+        }
+        face_flux(KC, std::integral_constant<int, 1>{}, el, t, en, uL, uR, qfa);
+    });
+    // - faces on a boundary (face 2k without a neighbour): everything read from LDS along
+    // the line, interpolated to the - end
+    if (a.bnd_minus) {
+        const R* lm = &s_ops[op_lm(N)];
+        for_units([&](auto KC, int j, int el, int t) {
+            (void)j;
+            constexpr int K = decltype(KC)::value;
+            constexpr int SK = st<N>(K);
+            const int32_t en = s_nbr[el * 2 * D + 2 * K];
+            if (en >= 0) return;
+            const int base = el * NU + face_base<D, N>(K, t);
+            R uL[V], qfa[V][D];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                R acc = R(0);
+#pragma unroll
+                for (int q = 0; q < N; ++q) acc += lm[q] * s_u[v][base + q * SK];
+                uL[v] = acc;
+                R qt[D];
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    R ai = R(0);
+#pragma unroll
+                    for (int q = 0; q < N; ++q) ai += lm[q] * s_x[(v * D + i) * XST + base + q * SK];
+                    qt[i] = ai;
+                }
+                to_physical(el, qt, qfa[v]);
+            }
+            face_flux(KC, std::integral_constant<int, 0>{}, el, t, en, uL, uL, qfa);
+        });
+    }
+
+    // the point fluxes below overwrite the gradient the face phase reads along lines
+    __syncthreads();
+
+    // ---- B2: fluxes at the solution points (Step 4) --------------------------------------
+    if (pt) {
+        const R* gg = &s_geo[le * G];
+        const R det = gg[D + 2 * D * D];
+        const R* Ji = gg + D + D * D;            // Jinv[k][i] = Ji[k*D + i]
+        int mi[D];
+        {
+            int r = ip;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                mi[k] = r % N;
+                r /= N;
+            }
+        }
+        R q[V][D];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            R qt[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) qt[i] = s_x[(v * D + i) * XST + tid];
+            to_physical(le, qt, q[v]);
+        }
+        R vel[D];
+        vel_at(le, mi, vel);
+        R v2 = R(0), g2 = R(0);
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            v2 += vel[i] * vel[i];
+            g2 += q[NV][i] * q[NV][i];
+        }
+        const R mm = max_sqrt(v2, a.ph.gamma);
+        const R rn = M::rsqrt_(g2 + a.ph.delta_n * a.ph.delta_n);
+        const R phi = s_u[0][tid], psi = s_u[1][tid];
+        const R sharp = a.ph.gamma * phi * (R(1) - phi) * rn;
+        R f0[D], f1[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const R fvis = mm * (a.ph.eps * q[0][i] - sharp * q[NV][i]);
+            f0[i] = phi * vel[i] - fvis;
+            f1[i] = psi * vel[i];
+        }
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            R a0, a1;
+            if constexpr (AXIS) {
+                a0 = Ji[k * D + k] * f0[k];
+                a1 = Ji[k * D + k] * f1[k];
+            } else {
+                a0 = R(0);
+                a1 = R(0);
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    a0 += Ji[k * D + i] * f0[i];
+                    a1 += Ji[k * D + i] * f1[i];
+                }
+            }
+            s_x[(0 * D + k) * XST + tid] = det * a0;
+            s_x[(1 * D + k) * XST + tid] = det * a1;
+        }
+    }
+    __syncthreads();
+
+    // ---- E1: DH_K f~_K along each line (volume part of Step 6), in place ------------------
+    const R* DH = &s_ops[op_dh(N)];
+    for_units([&](auto KC, int j, int el, int t) {
+        (void)j;
+        constexpr int K = decltype(KC)::value;
+        constexpr int SK = st<N>(K);
+        const int base = el * NU + face_base<D, N>(K, t);
+        R fl[V][N];
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+#pragma unroll
+            for (int b = 0; b < N; ++b) fl[v][b] = s_x[(v * D + K) * XST + base + b * SK];
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            R row[N];
+#pragma unroll
+            for (int b = 0; b < N; ++b) row[b] = DH[q * N + b];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                R acc = R(0);
+#pragma unroll
+                for (int b = 0; b < N; ++b) acc += row[b] * fl[v][b];
+                s_x[(v * D + K) * XST + base + q * SK] = acc;
+            }
+        }
+    });
+    __syncthreads();
+
+    // ---- E2: P = sum over the directions ------------------------------------------------
+    if (pt) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            R acc = R(0);
+#pragma unroll
+            for (int k = 0; k < D; ++k) acc += s_x[(v * D + k) * XST + tid];
+            gst(a.P[v] + e0 * NU, tid, acc);
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------
 // - face traces of the block's elements pushed into the owners' + face slots. Face unit
 // j of a wave covers direction k = u / WK, points (u % WK) * 64 + lane of that direction
 // (u = wave + j NW), so the direction is uniform in the wave.
 // ------------------------------------------------------------------------------------
-template <int D, int P, int U>
+template <int D, int P, int U, typename S = Shape<D, P>>
 __device__ __forceinline__ void load_owners(int32_t (&r_own)[U], const int32_t* nbr, int64_t e0,
                                             int nel, int wave, int lane) {
-    using S = Shape<D, P>;
 #pragma unroll
     for (int j = 0; j < S::UPW; ++j) {
         const int u = wave + j * S::NW;
@@ -742,11 +1251,10 @@ __device__ __forceinline__ void load_owners(int32_t (&r_own)[U], const int32_t* 
     }
 }
 
-template <typename R, int D, int P, int V, int U>
+template <typename R, int D, int P, int V, int U, typename S = Shape<D, P>>
 __device__ __forceinline__ void push_traces(R* const* Tp, const R* lm, const R* su0,
                                             const R* su1, const int32_t (&r_own)[U], int nel,
                                             int wave, int lane, uint32_t E) {
-    using S = Shape<D, P>;
     constexpr int N = S::N, NU = S::NU, NFA = S::NFA;
     auto push = [&](auto KC, int el, int t, int32_t own) {
         constexpr int K = decltype(KC)::value;
@@ -786,8 +1294,8 @@ __device__ __forceinline__ void push_traces(R* const* Tp, const R* lm, const R* 
 //   input are written (UP_RK).
 // ------------------------------------------------------------------------------------
 template <typename R, int D, int P, int V, int KIND>
-__global__ __launch_bounds__((Shape<D, P>::NT)) void k_update(UPArgs<R> a) {
-    using S = Shape<D, P>;
+__global__ __launch_bounds__((Shape<D, P, update_tpb(D, P)>::NT)) void k_update(UPArgs<R> a) {
+    using S = Shape<D, P, update_tpb(D, P)>;
     constexpr int N = S::N, NU = S::NU, NFA = S::NFA, EPB = S::EPB, NT = S::NT, G = S::GEO;
     constexpr int NFE = 2 * D * NFA;
     __shared__ R s_c[3 * N];                 // cm, cp, lm
@@ -807,7 +1315,7 @@ __global__ __launch_bounds__((Shape<D, P>::NT)) void k_update(UPArgs<R> a) {
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
     int32_t r_own[S::UPW];
-    if constexpr (KIND == UP_RK) load_owners<D, P, S::UPW>(r_own, a.nbr, e0, nel, wave, lane);
+    if constexpr (KIND == UP_RK) load_owners<D, P, S::UPW, S>(r_own, a.nbr, e0, nel, wave, lane);
     R rP[V], rU[V], rA[V];
     const uint32_t so = e0 * NU;     // first state value of the block (per plane)
     // lanes past the block's points load its last point (values unused)
@@ -917,8 +1425,8 @@ __global__ __launch_bounds__((Shape<D, P>::NT)) void k_update(UPArgs<R> a) {
     if constexpr (KIND == UP_RK) {
         __syncthreads();
         // - face traces of the next stage input, pushed into the owners' + face slots
-        push_traces<R, D, P, V, S::UPW>(a.Tp, &s_c[2 * N], s_u[0], s_u[V - 1], r_own, nel, wave, lane,
-                                        (uint32_t)a.E);
+        push_traces<R, D, P, V, S::UPW, S>(a.Tp, &s_c[2 * N], s_u[0], s_u[V - 1], r_own, nel, wave,
+                                           lane, (uint32_t)a.E);
     }
 }
 
@@ -1012,8 +1520,13 @@ struct Impl {
 
     template <int MODE, bool AXIS, bool MF, bool NPHI>
     static void gf_launch(const GFArgs<R>& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-        hipExtLaunchKernelGGL((k_grad_flux<R, D, P, MODE, AXIS, MF, NPHI>), dim3(grid(a.E)),
-                              dim3(S::NT), 0, st, e0, e1, 0, a);
+        if constexpr (MODE == GF_PHYS && !MF && D == 3) {
+            hipExtLaunchKernelGGL((k_grad_flux_lines<R, D, P, AXIS, NPHI>), dim3(grid(a.E)),
+                                  dim3(S::NT), 0, st, e0, e1, 0, a);
+        } else {
+            hipExtLaunchKernelGGL((k_grad_flux<R, D, P, MODE, AXIS, MF, NPHI>), dim3(grid(a.E)),
+                                  dim3(S::NT), 0, st, e0, e1, 0, a);
+        }
     }
     template <int MODE, bool MF>
     static void gf_mode(const GFArgs<R>& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
@@ -1055,7 +1568,8 @@ struct Impl {
     }
     static void update(int kind, int nvar, const UPArgs<R>& a, hipStream_t st, hipEvent_t e0,
                        hipEvent_t e1) {
-        const dim3 g(grid(a.E)), b(S::NT);
+        using U = Shape<D, P, update_tpb(D, P)>;
+        const dim3 g((unsigned)((a.E + U::EPB - 1) / U::EPB)), b(U::NT);
         if (nvar == 2) {
             if (kind == UP_RK) hipExtLaunchKernelGGL((k_update<R, D, P, 2, UP_RK>), g, b, 0, st, e0, e1, 0, a);
             else hipExtLaunchKernelGGL((k_update<R, D, P, 2, UP_RESID>), g, b, 0, st, e0, e1, 0, a);
