@@ -11,6 +11,7 @@ discrete adjoint of the whole map.
 Modules
   basis      1D Gauss-Legendre nodal basis, Vandermonde, DG (Radau) correction functions
   operators  dense tensor-product element operators (interpolation, derivative, lifting)
+  triangle   the triangle element: points, dense operators, geometry and pairing
   mesh       solution/flux point coordinates, slot pairing by coordinates, affine geometry
   velocity   the analytic velocity fields of §4
   residual   physical residual (§3.1) and preconditioning residual with the sensor (§3.2)

@@ -62,42 +62,9 @@ class Discretisation:
 
     # ------------------------------------------------------------------------------
     def _pair_slots(self):
-        ops, E, d = self.ops, self.E, self.d
-        Nf = ops.nfpts
-        pts = self.xf.reshape(-1, d).copy()
-        box = np.zeros(d)
-        for k in range(d):
-            lo = pts[:, k].min()
-            if self.periodic[k]:
-                box[k] = self.period[k]
-                pts[:, k] = np.mod(pts[:, k], self.period[k])
-                # points that round to the period itself belong at 0
-                pts[:, k] = np.where(pts[:, k] >= self.period[k], 0.0, pts[:, k])
-            else:
-                pts[:, k] -= lo
-                box[k] = 4.0 * (pts[:, k].max() + 1.0)
-        hmin = float(np.min(np.abs(self.detJ)) ** (1.0 / d))
-        tol = 1e-8 * hmin
-        tree = cKDTree(pts, boxsize=box)
-        dist, idx = tree.query(pts, k=3)
-        me = np.arange(pts.shape[0])
-        # the nearest point is the slot itself (or a coincident partner)
-        partner = np.full(pts.shape[0], -1)
-        for c in range(3):
-            cand = (dist[:, c] < tol) & (idx[:, c] != me)
-            partner = np.where(cand & (partner < 0), idx[:, c], partner)
-        ncoinc = np.sum(dist < tol, axis=1)
-        if np.any(ncoinc > 2):
-            raise ValueError("more than two coincident flux points")
-        has = partner >= 0
-        if np.any(has & (partner[np.maximum(partner, 0)] != me)):
-            raise ValueError("slot pairing is not symmetric")
-        if all(self.periodic) and not np.all(has):
-            raise ValueError("unpaired flux point on a fully periodic mesh")
-        self.has_pair = has.reshape(E, Nf)
-        pe, pj = np.divmod(np.where(has, partner, me), Nf)
-        self.pair_e = pe.reshape(E, Nf)
-        self.pair_j = pj.reshape(E, Nf)
+        ops = self.ops
+        self.has_pair, self.pair_e, self.pair_j = pair_by_coordinates(
+            self.xf, self.detJ, self.d, self.period, self.periodic)
         # paired normals must be opposite
         nL = self.normal
         nR = self.normal[self.pair_e, self.pair_j]
@@ -136,3 +103,41 @@ class Discretisation:
     @classmethod
     def from_box(cls, ops: ElementOperators, mesh) -> "Discretisation":
         return cls(ops, mesh.x0, mesh.jac, mesh.period, mesh.periodic)
+
+
+def pair_by_coordinates(xf, detJ, d, period, periodic):
+    """Pair every flux point [E, Nf, d] with the coincident flux point of another element,
+    comparing physical coordinates (modulo the period in periodic directions). Returns
+    (has_pair [E, Nf], pair_e, pair_j); unpaired points are paired with themselves."""
+    E, Nf = xf.shape[:2]
+    pts = xf.reshape(-1, d).copy()
+    box = np.zeros(d)
+    for k in range(d):
+        if periodic[k]:
+            box[k] = period[k]
+            pts[:, k] = np.mod(pts[:, k], period[k])
+            # points that round to the period itself belong at 0
+            pts[:, k] = np.where(pts[:, k] >= period[k], 0.0, pts[:, k])
+        else:
+            pts[:, k] -= pts[:, k].min()
+            box[k] = 4.0 * (pts[:, k].max() + 1.0)
+    hmin = float(np.min(np.abs(detJ)) ** (1.0 / d))
+    tol = 1e-8 * hmin
+    tree = cKDTree(pts, boxsize=box)
+    dist, idx = tree.query(pts, k=3)
+    me = np.arange(pts.shape[0])
+    # the nearest point is the slot itself (or a coincident partner)
+    partner = np.full(pts.shape[0], -1)
+    for c in range(3):
+        cand = (dist[:, c] < tol) & (idx[:, c] != me)
+        partner = np.where(cand & (partner < 0), idx[:, c], partner)
+    ncoinc = np.sum(dist < tol, axis=1)
+    if np.any(ncoinc > 2):
+        raise ValueError("more than two coincident flux points")
+    has = partner >= 0
+    if np.any(has & (partner[np.maximum(partner, 0)] != me)):
+        raise ValueError("slot pairing is not symmetric")
+    if all(periodic) and not np.all(has):
+        raise ValueError("unpaired flux point on a fully periodic mesh")
+    pe, pj = np.divmod(np.where(has, partner, me), Nf)
+    return has.reshape(E, Nf), pe.reshape(E, Nf), pj.reshape(E, Nf)

@@ -27,8 +27,13 @@ LINEAR, LOGIT = 0, 1
 
 class Oracle:
     def __init__(self, ndims, order, mesh, prm):
-        self.ops = ElementOperators(ndims, order)
-        self.disc = Discretisation.from_box(self.ops, mesh)
+        if getattr(mesh, "element", "tensor") == "triangle":
+            from .triangle import TriangleDiscretisation, TriangleOperators
+            self.ops = TriangleOperators(order)
+            self.disc = TriangleDiscretisation.from_mesh(self.ops, mesh)
+        else:
+            self.ops = ElementOperators(ndims, order)
+            self.disc = Discretisation.from_box(self.ops, mesh)
         self.prm = prm
 
     # -- building blocks -------------------------------------------------------------

@@ -212,6 +212,96 @@ def _skew_mesh_3d(planes, periodic, shear) -> BoxMesh:
                    period=L, shear=shear)
 
 
+@dataclass
+class TriMesh:
+    """Triangle mesh from diagonally split grid cells (§4.2, the uniform split triangular
+    mesh). Triangle corners v0, v1, v2 counter-clockwise; affine map x = x0 + J (r, s) with
+    J = [v1 - v0, v2 - v0] from the reference triangle {r, s >= 0, r + s <= 1}. Edge
+    f = 0, 1, 2 runs v0 -> v1, v1 -> v2, v2 -> v0. nbr[e, f] = (element, edge) across edge f,
+    or (-1, -1) on a boundary; the two elements traverse a shared edge in opposite
+    directions."""
+    ndims: int
+    shape: tuple
+    periodic: tuple
+    x0: np.ndarray            # [E, 2]
+    jac: np.ndarray           # [E, 2, 2]
+    nbr: np.ndarray           # [E, 3, 2] int32: neighbour element and its edge
+    period: np.ndarray
+    element: str = "triangle"
+
+    @property
+    def nelem(self) -> int:
+        return self.x0.shape[0]
+
+    def slot_pairs(self, npe: int) -> np.ndarray:
+        """Partner flux point e' 3 npe + f' npe + t' of every flux point e 3 npe + f npe + t
+        (npe points per edge, ordered along the edge), -1 on boundaries: the shared edge is
+        walked the other way by the neighbour, so t' = npe - 1 - t."""
+        E = self.nelem
+        out = np.full((E, 3, npe), -1, dtype=np.int64)
+        t = np.arange(npe)
+        for f in range(3):
+            en, fn = self.nbr[:, f, 0], self.nbr[:, f, 1]
+            ok = en >= 0
+            part = (en[:, None] * 3 + fn[:, None]) * npe + (npe - 1 - t)[None, :]
+            out[:, f, :] = np.where(ok[:, None], part, -1)
+        return out.reshape(-1)
+
+
+def split_tri_mesh(n: int, periodic=True, lo: float = 0.0, hi: float = 1.0,
+                   perturb: float = 0.0, seed: int = 1) -> TriMesh:
+    """n x n grid cells of [lo, hi]^2, each split along its lower-left to upper-right
+    diagonal into the triangles A = (c00, c10, c11) and B = (c00, c11, c01). Cell (i, j),
+    triangle A = element 2 (i + n j), B = element 2 (i + n j) + 1. ``perturb`` shifts the
+    interior grid lines by U(-perturb h, perturb h) (seeded), keeping every triangle affine."""
+    rng = np.random.default_rng(seed)
+    planes = [perturbed_planes(n, perturb, rng, lo, hi) if perturb > 0 else uniform_planes(n, lo, hi)
+              for _ in range(2)]
+    per = periodic if isinstance(periodic, (list, tuple)) else (periodic, periodic)
+    E = 2 * n * n
+    x0 = np.zeros((E, 2))
+    jac = np.zeros((E, 2, 2))
+    nbr = np.full((E, 3, 2), -1, dtype=np.int32)
+    px, py = planes
+
+    def cell(i, j):
+        if per[0]:
+            i %= n
+        if per[1]:
+            j %= n
+        return (i, j) if (0 <= i < n and 0 <= j < n) else None
+
+    for j in range(n):
+        for i in range(n):
+            c00 = np.array([px[i], py[j]])
+            c10 = np.array([px[i + 1], py[j]])
+            c11 = np.array([px[i + 1], py[j + 1]])
+            c01 = np.array([px[i], py[j + 1]])
+            a, b = 2 * (i + n * j), 2 * (i + n * j) + 1
+            x0[a], jac[a] = c00, np.stack([c10 - c00, c11 - c00], 1)
+            x0[b], jac[b] = c00, np.stack([c11 - c00, c01 - c00], 1)
+            # A: edge 0 (c00 -> c10) bottom, edge 1 (c10 -> c11) right, edge 2 (c11 -> c00)
+            # diagonal; B: edge 0 (c00 -> c11) diagonal, edge 1 (c11 -> c01) top, edge 2
+            # (c01 -> c00) left
+            nbr[a, 2] = (b, 0)
+            nbr[b, 0] = (a, 2)
+            down = cell(i, j - 1)
+            if down is not None:
+                nbr[a, 0] = (2 * (down[0] + n * down[1]) + 1, 1)
+            right = cell(i + 1, j)
+            if right is not None:
+                nbr[a, 1] = (2 * (right[0] + n * right[1]) + 1, 2)
+            up = cell(i, j + 1)
+            if up is not None:
+                nbr[b, 1] = (2 * (up[0] + n * up[1]), 0)
+            left = cell(i - 1, j)
+            if left is not None:
+                nbr[b, 2] = (2 * (left[0] + n * left[1]), 1)
+    period = np.array([hi - lo, hi - lo])
+    return TriMesh(ndims=2, shape=(n, n), periodic=tuple(bool(x) for x in per), x0=x0,
+                   jac=jac, nbr=nbr, period=period)
+
+
 # --------------------------------------------------------------------------------------
 # initial condition (§4, Eq. initialCond with the distance of Eq. discEq)
 # --------------------------------------------------------------------------------------
