@@ -37,6 +37,7 @@ element on the - side of every face, the reading used for the quadrilaterals.
 from __future__ import annotations
 
 import math
+from fractions import Fraction
 
 import numpy as np
 import torch
@@ -81,8 +82,46 @@ VERTS = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])
 EDGES = [(0, 1), (1, 2), (2, 0)]
 
 
+def _exact_inverse(A):
+    """Inverse of a square matrix of Fractions by Gauss-Jordan elimination (exact)."""
+    n = len(A)
+    M = [list(row) + [Fraction(int(i == j)) for j in range(n)] for i, row in enumerate(A)]
+    for c in range(n):
+        piv = next(r for r in range(c, n) if M[r][c] != 0)
+        M[c], M[piv] = M[piv], M[c]
+        pv = M[c][c]
+        M[c] = [x / pv for x in M[c]]
+        for r in range(n):
+            if r != c and M[r][c] != 0:
+                f = M[r][c]
+                M[r] = [a - f * b for a, b in zip(M[r], M[c])]
+    return [row[n:] for row in M]
+
+
+def _matmul(A, B):
+    return [[sum(A[i][k] * B[k][j] for k in range(len(B))) for j in range(len(B[0]))]
+            for i in range(len(A))]
+
+
 class TriangleOperators:
+    """The element's operators. The solution points, the centroid and the monomial moments
+    are rational, so everything except the Gauss-Legendre edge points is built in exact
+    rational arithmetic (Fractions) and rounded once at the end: the nodal mass matrix of
+    the lattice points is ill conditioned (it costs float64 about 1e-11 at p = 4)."""
+
+    _cache = {}
+
+    def __new__(cls, p: int):
+        if p not in cls._cache:
+            obj = super().__new__(cls)
+            obj._build(p)
+            cls._cache[p] = obj
+        return cls._cache[p]
+
     def __init__(self, p: int):
+        pass
+
+    def _build(self, p: int):
         self.d = 2
         self.p = p
         self.shape = "triangle"
@@ -90,8 +129,10 @@ class TriangleOperators:
         self.mons = mons
         self.nupts = Nu = len(mons)
         self.nfpts_face = n = p + 1
-        self.nfpts = Nf = 3 * n
-        self.upt_ref = solution_points(p)
+        self.nfpts = 3 * n
+        pts_q = [(Fraction(3 * i + 1, 3 * (p + 1)), Fraction(3 * j + 1, 3 * (p + 1)))
+                 for j in range(p + 1) for i in range(p + 1 - j)]
+        self.upt_ref = np.array([[float(x), float(y)] for x, y in pts_q])
         xi, wq = np.polynomial.legendre.leggauss(n)
         fpt, nhat, wf, face = [], [], [], []
         for e, (a, b) in enumerate(EDGES):
@@ -108,10 +149,24 @@ class TriangleOperators:
         self.nhat = np.array(nhat)
         self.wf = np.array(wf)
         self.fpt_face = np.array(face)
+        c = Fraction(1, 3)
+
+        def mono_q(x, y, diff=None):
+            """Centred monomials (or a derivative) at one point, exact."""
+            X, Y = x - c, y - c
+            out = []
+            for a, b in mons:
+                if diff is None:
+                    out.append(X ** a * Y ** b)
+                elif diff == 0:
+                    out.append(a * X ** (a - 1) * Y ** b if a > 0 else Fraction(0))
+                else:
+                    out.append(b * X ** a * Y ** (b - 1) if b > 0 else Fraction(0))
+            return out
 
         def mono(x, diff=None):
-            """Monomials about the centroid, (r - 1/3)^a (s - 1/3)^b (or their derivative
-            along diff), at points x[N, 2] -> [N, Nu]."""
+            """Centred monomials (r - 1/3)^a (s - 1/3)^b (or their derivative along diff) at
+            float points x[N, 2] -> [N, Nu] (float64)."""
             X, Y = x[:, 0] - CENTRE, x[:, 1] - CENTRE
             out = np.zeros((x.shape[0], Nu))
             for m, (a, b) in enumerate(mons):
@@ -124,23 +179,51 @@ class TriangleOperators:
             return out
 
         self.mono = mono
-        Vm = mono(self.upt_ref)                      # Vm[i, m] = mono_m(x_i)
-        if np.linalg.matrix_rank(Vm) < Nu:
-            raise ValueError("solution points are not unisolvent")
-        C = np.linalg.inv(Vm)                        # l_i = sum_m C[m, i] mono_m
-        self.lagrange_coeffs = C
-        self.M0 = mono(self.fpt_ref) @ C
-        self.D = [mono(self.upt_ref, k) @ C for k in range(2)]
-        G = np.array([[centred_integral(a + a2, b + b2) for (a2, b2) in mons] for (a, b) in mons])
-        self.mass = C.T @ G @ C
-        self.W = C.T @ np.array([centred_integral(a, b) for (a, b) in mons])
-        Emat = (self.M0 * self.wf[:, None]).T        # E[i, j] = w_j l_i(x_j)
-        self.LiftDiv = np.linalg.solve(self.mass, Emat)
+        Vm = [mono_q(x, y) for x, y in pts_q]                      # Vm[i][m]
+        C = _exact_inverse(Vm)                                     # l_i = sum_m C[m][i] mono_m
+        self.lagrange_coeffs = np.array([[float(v) for v in row] for row in C])
+        fq = [(Fraction(float(x)), Fraction(float(y))) for x, y in self.fpt_ref]
+        M0 = _matmul([mono_q(x, y) for x, y in fq], C)
+        self.M0 = np.array([[float(v) for v in row] for row in M0])
+        self.D = [np.array([[float(v) for v in row]
+                            for row in _matmul([mono_q(x, y, k) for x, y in pts_q], C)])
+                  for k in range(2)]
+        # exact moments of the centred monomials, the nodal mass matrix and weights
+        def cmom(a, b):
+            tot = Fraction(0)
+            for i in range(a + 1):
+                for j in range(b + 1):
+                    tot += (math.comb(a, i) * math.comb(b, j) * (-c) ** (a - i) * (-c) ** (b - j)
+                            * Fraction(math.factorial(i) * math.factorial(j),
+                                       math.factorial(i + j + 2)))
+            return tot
+        G = [[cmom(a + a2, b + b2) for (a2, b2) in mons] for (a, b) in mons]
+        CT = [[C[m][i] for m in range(Nu)] for i in range(Nu)]
+        Mass = _matmul(_matmul(CT, G), C)
+        self.mass = np.array([[float(v) for v in row] for row in Mass])
+        self.W = np.array([float(sum(CT[i][m] * cmom(*mons[m]) for m in range(Nu)))
+                           for i in range(Nu)])
+        # LiftDiv = M^-1 E with E[i][j] = w_j l_i(x_j) (exact given the float edge data)
+        Minv = _exact_inverse(Mass)
+        E = [[Fraction(float(self.wf[j])) * M0[j][i] for j in range(self.nfpts)] for i in range(Nu)]
+        self.LiftDiv = np.array([[float(v) for v in row] for row in _matmul(Minv, E)])
         self.LiftN = [self.LiftDiv * self.nhat[:, k][None, :] for k in range(2)]
-        # orthonormal modes: psi = L^-1 mono with G = L L^T (graded order is kept)
-        Lc = np.linalg.cholesky(G)
-        self.ortho_coeffs = np.linalg.inv(Lc)        # psi_j = sum_m ortho[j, m] mono_m
-        self.Vt = mono(self.upt_ref) @ self.ortho_coeffs.T
+        # orthonormal modes: Gram-Schmidt of the centred monomials in graded order with the
+        # exact inner product (orthogonal, exact), then each mode divided by its norm
+        ortho = []      # coefficient rows over the monomials
+        for m in range(Nu):
+            v = [Fraction(int(k == m)) for k in range(Nu)]
+            for u in ortho:
+                num = sum(u[a] * G[a][b] * v[b] for a in range(Nu) for b in range(Nu))
+                den = sum(u[a] * G[a][b] * u[b] for a in range(Nu) for b in range(Nu))
+                f = num / den
+                v = [vi - f * ui for vi, ui in zip(v, u)]
+            ortho.append(v)
+        norms = [math.sqrt(float(sum(u[a] * G[a][b] * u[b] for a in range(Nu) for b in range(Nu))))
+                 for u in ortho]
+        Vq = _matmul(Vm, [[ortho[j][m] for j in range(Nu)] for m in range(Nu)])   # phi~_j(x_i)
+        self.Vt = np.array([[float(Vq[i][j]) / norms[j] for j in range(Nu)] for i in range(Nu)])
+        self.ortho_coeffs = np.array([[float(v) / norms[j] for v in ortho[j]] for j in range(Nu)])
         self.Vt_inv = np.linalg.inv(self.Vt)
         self.topmask = np.array([1.0 if a + b == p else 0.0 for (a, b) in mons])
 
