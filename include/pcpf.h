@@ -141,15 +141,19 @@ enum { PCPF_SHAPE_TENSOR = 0,   /* quadrilateral (d = 2) / hexahedral (d = 3) el
  * per-element affine geometry (§3.1 mapping, Jacobian and transformed-flux equations) and
  * the per-flux-point connectivity (§3.1 Step 2: each flux point of a face paired with
  * the coincident flux point of the neighbouring element). Host memory, row-major, float64
- * unless stated. Solution point i = sum_k i_k n^k (i_0 fastest); flux point j = f N_fa + t
- * on face f = 2k + s (s = 0: xi_k = -1, s = 1: xi_k = +1), t the index of its tangential
- * Gauss-Legendre positions, first tangential axis fastest. */
+ * unless stated. Tensor elements: solution point i = sum_k i_k n^k (i_0 fastest); flux
+ * point j = f N_fa + t on face f = 2k + s (s = 0: xi_k = -1, s = 1: xi_k = +1), t the index
+ * of its tangential Gauss-Legendre positions, first tangential axis fastest. Triangles:
+ * the point order of pcpf_triangle_operators (flux point j = e (p+1) + t, t along the walk
+ * of edge e). */
 typedef struct pcpf_dense_mesh {
     int32_t ndims;              /* d */
     int32_t order;              /* p */
     int32_t shape;              /* PCPF_SHAPE_* */
-    int32_t nupts;              /* N_u: (p+1)^d for tensor elements */
-    int32_t nfpts;              /* N_f: 2d (p+1)^(d-1) for tensor elements */
+    int32_t nupts;              /* N_u: (p+1)^d for tensor elements, (p+1)(p+2)/2 for
+                                   triangles */
+    int32_t nfpts;              /* N_f: 2d (p+1)^(d-1) for tensor elements, 3(p+1) for
+                                   triangles */
     int64_t nelem;              /* E */
     const double* M0;           /* [N_f][N_u] interpolation to the flux points (Step 1) */
     const double* D;            /* [d][N_u][N_u] reference derivatives (Steps 3, 6) */
@@ -163,7 +167,8 @@ typedef struct pcpf_dense_mesh {
     const double* detj;         /* [E] det J */
     const double* fnorm;        /* [E][N_f][d] physical unit normal J^-T nhat / |J^-T nhat| */
     const double* fscale;       /* [E][N_f] det J |J^-T nhat| */
-    const double* xorig;        /* [E][d] image of the reference corner (-1, ..., -1) */
+    const double* xorig;        /* [E][d] image of the reference corner (-1, ..., -1);
+                                   of the vertex (0, 0) for triangles */
     const double* jac;          /* optional ([E][d][d] J itself; NULL: J = inv(jinv)) */
     const int32_t* nbr_slot;    /* [E N_f] partner flux point e' N_f + j', -1 = boundary
                                    (copy boundary condition, §3.3) */
@@ -190,6 +195,21 @@ const char* pcpf_last_error(const pcpf_ctx* ctx);
 pcpf_status pcpf_line_operators(int32_t order, double* nodes, double* weights,
                                 double* deriv, double* lminus, double* lplus,
                                 double* cminus, double* cplus, double* vinv);
+
+/* Dense operators of the order-p triangle (§3.1 on triangles; the paper names the
+ * Williams-Shunn solution points but prints no coordinates, so this library places them on
+ * the interior lattice ((i + 1/3), (j + 1/3)) / (p + 1) of the reference triangle
+ * {r, s >= 0, r + s <= 1}, j outer, i inner; p + 1 Gauss-Legendre flux points on each edge,
+ * edges v0 -> v1, v1 -> v2, v2 -> v0 with v0 = (0, 0), v1 = (1, 0), v2 = (0, 1), each walked
+ * in that direction; DG correction functions, Lift = M^-1 E). The arrays, host, float64,
+ * caller-owned, have the shapes and meanings of pcpf_dense_mesh with N_u = (p+1)(p+2)/2,
+ * N_f = 3 (p + 1), plus upt_ref [N_u][2] and fpt_ref [N_f][2], the reference coordinates of
+ * the solution and flux points (a triangle element maps as x = xorig + J (r, s)).
+ * EINVAL if order is outside 1..5 or a pointer is NULL. */
+pcpf_status pcpf_triangle_operators(int32_t order, double* upt_ref, double* fpt_ref,
+                                    double* M0, double* D, double* LiftN, double* Lift,
+                                    double* Vinv, uint8_t* topmask, double* W,
+                                    double* ref_fnorm);
 
 /* Physical coordinates of every solution point, xs[(e*N_u + i)*d + k] (host, float64,
  * caller-owned, E*N_u*d values). EINVAL on a malformed mesh. */
@@ -220,11 +240,19 @@ pcpf_status pcpf_create(const pcpf_mesh* mesh, const pcpf_params* params, void* 
  *     + faces of paired slots, and
  *   - the geometry is that of one affine map per element (det J, normals and face scales
  *     consistent with J^-1 within 1e-12).
- * Triangles and other point sets or orientations are valid descriptions that this build
- * does not run: EUNSUPPORTED. Inconsistent sizes, non-reciprocal pairs, several or no
- * owners on a pair, or geometry that disagrees with J: EINVAL. The host arrays are read
- * during the call only. pcpf_workspace_bytes_dense runs the same validation (no GPU
- * needed); pcpf_create_dense then behaves as pcpf_create on the equivalent pcpf_mesh. */
+ * Other point sets or orientations of tensor elements are valid descriptions that this
+ * build does not run: EUNSUPPORTED. Inconsistent sizes, non-reciprocal pairs, several or no
+ * owners on a pair, or geometry that disagrees with J: EINVAL.
+ * Triangles (shape PCPF_SHAPE_TRIANGLE, d = 2, p = 1..5) run on dense per-element kernels:
+ * the operators must be those of pcpf_triangle_operators (same tolerance), any pairing of
+ * flux points is accepted when it is reciprocal, the paired points coincide (up to the
+ * periods) and each pair has exactly one owner (boundary points are owned), and the map is
+ * x = xorig + J (r, s). The common normal flux of a pair is computed once, by its owner,
+ * as a physical flux; each side transforms it with its own fscale (the two sides of an edge
+ * may sit on reference edges of different lengths). The adjoint and the BF16 form are not
+ * built for triangles (EUNSUPPORTED). The host arrays are read during the call only.
+ * pcpf_workspace_bytes_dense runs the same validation (no GPU needed); for tensor elements
+ * pcpf_create_dense then behaves as pcpf_create on the equivalent pcpf_mesh. */
 pcpf_status pcpf_workspace_bytes_dense(const pcpf_dense_mesh* mesh, const pcpf_params* params,
                                        size_t* nbytes);
 pcpf_status pcpf_create_dense(const pcpf_dense_mesh* mesh, const pcpf_params* params,

@@ -7,8 +7,8 @@ The method runs in the HIP library ``libpcpf.so`` built from ``csrc/`` (C ABI in
 from ._lib import PcpfError, load  # noqa: F401
 from .solver import (BF16, FP32, FP64, MODE_PHYS, MODE_PRECOND, REDUCE_L1, REDUCE_MASS,  # noqa: F401
                      REDUCE_RMS, DenseMeshArgs, MeshArgs, Solver, line_operators,
-                     make_params)
+                     make_params, triangle_operators)
 
-__all__ = ["Solver", "MeshArgs", "DenseMeshArgs", "line_operators", "make_params", "PcpfError", "load",
+__all__ = ["Solver", "MeshArgs", "DenseMeshArgs", "line_operators", "triangle_operators", "make_params", "PcpfError", "load",
            "FP64", "FP32", "BF16", "MODE_PHYS", "MODE_PRECOND", "REDUCE_MASS", "REDUCE_L1",
            "REDUCE_RMS"]

@@ -92,6 +92,7 @@ def load() -> ctypes.CDLL:
         "pcpf_last_error": (ctypes.c_char_p, [vp]),
         "pcpf_line_operators": (st, [i32] + [_dp] * 8),
         "pcpf_solution_coords": (st, [ctypes.POINTER(PcpfMesh), _dp]),
+        "pcpf_triangle_operators": (st, [i32] + [_dp] * 7 + [_u8p, _dp, _dp]),
         "pcpf_workspace_bytes": (st, [ctypes.POINTER(PcpfMesh), ctypes.POINTER(PcpfParams),
                                       ctypes.POINTER(ctypes.c_size_t)]),
         "pcpf_create": (st, [ctypes.POINTER(PcpfMesh), ctypes.POINTER(PcpfParams), vp,

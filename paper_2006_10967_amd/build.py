@@ -12,7 +12,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpcpf.so")
 SOURCES = ["pcpf_kernels.hip", "pcpf_kernels_2d_f64.hip", "pcpf_kernels_2d_f32.hip",
-           "pcpf_kernels_3d_f64.hip", "pcpf_kernels_3d_f32.hip", "pcpf_adjoint.hip", "pcpf_api.hip"]
+           "pcpf_kernels_3d_f64.hip", "pcpf_kernels_3d_f32.hip", "pcpf_tri.hip", "pcpf_adjoint.hip",
+           "pcpf_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",

@@ -12,6 +12,7 @@
 
 #include "pcpf_adjoint.h"
 #include "pcpf_internal.h"
+#include "pcpf_tri.h"
 
 using namespace pcpf;
 
@@ -70,6 +71,214 @@ void gauss_legendre(int n, double* x, double* w) {
         w[n - 1 - i] = wi;
     }
     if (n % 2 == 1) x[n / 2] = 0.0;
+}
+
+// ------------------------------------------------------------------------------------
+// triangle element (host, float64): the reference triangle {r, s >= 0, r + s <= 1},
+// vertices (0, 0), (1, 0), (0, 1), edges v0 -> v1, v1 -> v2, v2 -> v0
+// ------------------------------------------------------------------------------------
+// The triangle operators are built in long double (64-bit mantissa on the host) and
+// rounded once: the nodal mass matrix of the lattice points is ill conditioned (double
+// loses about 1e-11 of the lifting at p = 4 through it).
+using LD = long double;
+
+// Legendre P_n and P_n' valid on all of [-1, 1] (P'_k = x P'_{k-1} + k P_{k-1}).
+void legendre_pd(int n, LD x, LD* p, LD* dp) {
+    if (n == 0) {
+        *p = 1.0L;
+        *dp = 0.0L;
+        return;
+    }
+    LD p0 = 1.0L, p1 = x, d1 = 1.0L;
+    for (int k = 2; k <= n; ++k) {
+        const LD p2 = ((2.0L * k - 1.0L) * x * p1 - (k - 1.0L) * p0) / k;
+        const LD d2 = x * d1 + k * p1;
+        p0 = p1;
+        p1 = p2;
+        d1 = d2;
+    }
+    *p = p1;
+    *dp = d1;
+}
+
+// Gauss-Legendre nodes (ascending) and weights in long double: Newton from the double ones.
+void gauss_legendre_ld(int n, LD* x, LD* w) {
+    std::vector<double> xd(n), wd(n);
+    gauss_legendre(n, xd.data(), wd.data());
+    for (int i = 0; i < n; ++i) {
+        LD z = xd[i], p, dp;
+        for (int it = 0; it < 4; ++it) {
+            legendre_pd(n, z, &p, &dp);
+            z -= p / dp;
+        }
+        legendre_pd(n, z, &p, &dp);
+        x[i] = z;
+        w[i] = 2.0L / ((1.0L - z * z) * dp * dp);
+    }
+}
+
+// The graded basis of P_p used to build the nodal operators: P_a(2r - 1) P_b(2s - 1) for
+// a + b = 0, 1, ..., p (b ascending within a degree), with its derivatives.
+void tri_basis(int p, LD r, LD s, LD* phi, LD* dr, LD* ds) {
+    int m = 0;
+    for (int deg = 0; deg <= p; ++deg)
+        for (int b = 0; b <= deg; ++b) {
+            const int a = deg - b;
+            LD pa, dpa, pb, dpb;
+            legendre_pd(a, 2.0L * r - 1.0L, &pa, &dpa);
+            legendre_pd(b, 2.0L * s - 1.0L, &pb, &dpb);
+            phi[m] = pa * pb;
+            if (dr) dr[m] = 2.0L * dpa * pb;
+            if (ds) ds[m] = 2.0L * pa * dpb;
+            ++m;
+        }
+}
+
+// X = A^-1 B for A n x n, B n x m (row-major), Gauss elimination with partial pivoting.
+bool solve_dense(int n, std::vector<LD> A, int m, std::vector<LD>& B) {
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::fabs(A[r * n + c]) > std::fabs(A[piv * n + c])) piv = r;
+        if (!(std::fabs(A[piv * n + c]) > 0.0L)) return false;
+        if (piv != c) {
+            for (int k = 0; k < n; ++k) std::swap(A[c * n + k], A[piv * n + k]);
+            for (int k = 0; k < m; ++k) std::swap(B[c * m + k], B[piv * m + k]);
+        }
+        for (int r = 0; r < n; ++r) {
+            if (r == c) continue;
+            const LD f = A[r * n + c] / A[c * n + c];
+            if (f == 0.0L) continue;
+            for (int k = c; k < n; ++k) A[r * n + k] -= f * A[c * n + k];
+            for (int k = 0; k < m; ++k) B[r * m + k] -= f * B[c * m + k];
+        }
+    }
+    for (int r = 0; r < n; ++r)
+        for (int k = 0; k < m; ++k) B[r * m + k] /= A[r * n + r];
+    return true;
+}
+
+struct TriOps {
+    int p = 0, nu = 0, nf = 0;
+    std::vector<double> upt, fpt, nh, wf, M0, D0, D1, Lift, Vinv, W;
+    std::vector<uint8_t> top;
+};
+
+// The order-p triangle of §3.1 with the reading of its solution points (the interior
+// lattice ((i + 1/3), (j + 1/3)) / (p + 1), j outer, i inner), Gauss-Legendre flux points on
+// each edge in the edge's direction, and DG correction functions: Lift = M^-1 E with the mass
+// matrix M = int l_i l_j (by a collapsed Gauss rule, exact for the degree-2p products) and
+// E[i][f] = w_f l_i(x_f). The modal transform of the sensor takes the orthonormal basis of
+// the graded basis above (Cholesky of its Gram matrix); its degree-p modes are the top ones.
+bool tri_operators(int p, TriOps* T) {
+    const int n = p + 1, nu = (p + 1) * (p + 2) / 2, nf = 3 * n;
+    T->p = p;
+    T->nu = nu;
+    T->nf = nf;
+    std::vector<LD> upt(2 * nu), fpt(2 * nf), nh(2 * nf), wf(nf);
+    int i = 0;
+    for (int j = 0; j <= p; ++j)
+        for (int a = 0; a <= p - j; ++a, ++i) {
+            upt[2 * i] = (a + 1.0L / 3.0L) / (p + 1);
+            upt[2 * i + 1] = (j + 1.0L / 3.0L) / (p + 1);
+        }
+    std::vector<LD> xg(n), wg(n);
+    gauss_legendre_ld(n, xg.data(), wg.data());
+    const LD vx[3] = {0.0L, 1.0L, 0.0L}, vy[3] = {0.0L, 0.0L, 1.0L};
+    for (int e = 0; e < 3; ++e) {
+        const int a = e, b = (e + 1) % 3;
+        const LD tx = vx[b] - vx[a], ty = vy[b] - vy[a];
+        const LD L = std::sqrt(tx * tx + ty * ty);
+        for (int t = 0; t < n; ++t) {
+            const int f = e * n + t;
+            fpt[2 * f] = vx[a] + 0.5L * (1.0L + xg[t]) * tx;
+            fpt[2 * f + 1] = vy[a] + 0.5L * (1.0L + xg[t]) * ty;
+            nh[2 * f] = ty / L;           // outward for the counter-clockwise walk
+            nh[2 * f + 1] = -tx / L;
+            wf[f] = 0.5L * L * wg[t];
+        }
+    }
+    // Vandermonde V[i][m] = phi_m(x_i); the nodal operators are (basis values) V^-1
+    std::vector<LD> V(nu * nu), Vr(nu * nu), Vs(nu * nu), Vf(nf * nu);
+    for (int q = 0; q < nu; ++q)
+        tri_basis(p, upt[2 * q], upt[2 * q + 1], &V[q * nu], &Vr[q * nu], &Vs[q * nu]);
+    for (int f = 0; f < nf; ++f) tri_basis(p, fpt[2 * f], fpt[2 * f + 1], &Vf[f * nu], nullptr, nullptr);
+    std::vector<LD> Vi(nu * nu, 0.0L);
+    for (int q = 0; q < nu; ++q) Vi[q * nu + q] = 1.0L;
+    if (!solve_dense(nu, V, nu, Vi)) return false;
+    auto matmul = [](int r, int k, int c, const LD* A, const LD* B, LD* C) {
+        for (int x = 0; x < r; ++x)
+            for (int y = 0; y < c; ++y) {
+                LD acc = 0.0L;
+                for (int z = 0; z < k; ++z) acc += A[x * k + z] * B[z * c + y];
+                C[x * c + y] = acc;
+            }
+    };
+    std::vector<LD> M0(nf * nu), D0(nu * nu), D1(nu * nu);
+    matmul(nf, nu, nu, Vf.data(), Vi.data(), M0.data());
+    matmul(nu, nu, nu, Vr.data(), Vi.data(), D0.data());
+    matmul(nu, nu, nu, Vs.data(), Vi.data(), D1.data());
+    // Gram matrix of the basis and its integrals by the collapsed rule: (u, v) in [0, 1]^2 ->
+    // (u, v (1 - u)), Jacobian 1 - u, p + 2 Gauss points each way (exact for degree 2p)
+    const int nq = p + 2;
+    std::vector<LD> xq(nq), wq(nq), ph(nu);
+    gauss_legendre_ld(nq, xq.data(), wq.data());
+    std::vector<LD> Gm(nu * nu, 0.0L), gi(nu, 0.0L);
+    for (int a = 0; a < nq; ++a)
+        for (int b = 0; b < nq; ++b) {
+            const LD u = 0.5L * (xq[a] + 1.0L), v = 0.5L * (xq[b] + 1.0L);
+            const LD w = 0.25L * wq[a] * wq[b] * (1.0L - u);
+            tri_basis(p, u, v * (1.0L - u), ph.data(), nullptr, nullptr);
+            for (int x = 0; x < nu; ++x) {
+                gi[x] += w * ph[x];
+                for (int y = 0; y < nu; ++y) Gm[x * nu + y] += w * ph[x] * ph[y];
+            }
+        }
+    // nodal mass matrix M = V^-T G V^-1 and weights W = V^-T g
+    std::vector<LD> ViT(nu * nu), tmp(nu * nu), Mn(nu * nu), W(nu);
+    for (int x = 0; x < nu; ++x)
+        for (int y = 0; y < nu; ++y) ViT[x * nu + y] = Vi[y * nu + x];
+    matmul(nu, nu, nu, ViT.data(), Gm.data(), tmp.data());
+    matmul(nu, nu, nu, tmp.data(), Vi.data(), Mn.data());
+    matmul(nu, nu, 1, ViT.data(), gi.data(), W.data());
+    // Lift = M^-1 E, E[i][f] = w_f M0[f][i]
+    std::vector<LD> Em(nu * nf);
+    for (int x = 0; x < nu; ++x)
+        for (int f = 0; f < nf; ++f) Em[x * nf + f] = wf[f] * M0[f * nu + x];
+    if (!solve_dense(nu, Mn, nf, Em)) return false;
+    // orthonormal modes psi = L^-1 phi (G = L L^T): Vinv = L^T V^-1
+    std::vector<LD> Lc(nu * nu, 0.0L);
+    for (int x = 0; x < nu; ++x)
+        for (int y = 0; y <= x; ++y) {
+            LD acc = Gm[x * nu + y];
+            for (int z = 0; z < y; ++z) acc -= Lc[x * nu + z] * Lc[y * nu + z];
+            if (x == y) {
+                if (!(acc > 0.0L)) return false;
+                Lc[x * nu + x] = std::sqrt(acc);
+            } else {
+                Lc[x * nu + y] = acc / Lc[y * nu + y];
+            }
+        }
+    std::vector<LD> LT(nu * nu), Vinv(nu * nu);
+    for (int x = 0; x < nu; ++x)
+        for (int y = 0; y < nu; ++y) LT[x * nu + y] = Lc[y * nu + x];
+    matmul(nu, nu, nu, LT.data(), Vi.data(), Vinv.data());
+    auto rd = [](const std::vector<LD>& v) { return std::vector<double>(v.begin(), v.end()); };
+    T->upt = rd(upt);
+    T->fpt = rd(fpt);
+    T->nh = rd(nh);
+    T->wf = rd(wf);
+    T->M0 = rd(M0);
+    T->D0 = rd(D0);
+    T->D1 = rd(D1);
+    T->Lift = rd(Em);
+    T->Vinv = rd(Vinv);
+    T->W = rd(W);
+    T->top.resize(nu);
+    int m = 0;
+    for (int deg = 0; deg <= p; ++deg)
+        for (int b = 0; b <= deg; ++b, ++m) T->top[m] = deg == p ? 1 : 0;
+    return true;
 }
 
 }  // namespace
@@ -133,6 +342,37 @@ pcpf_status pcpf_line_operators(int32_t order, double* nodes, double* weights, d
     return out_of_memory(nullptr);
 }
 
+pcpf_status pcpf_triangle_operators(int32_t order, double* upt_ref, double* fpt_ref,
+                                    double* M0, double* D, double* LiftN, double* Lift,
+                                    double* Vinv, uint8_t* topmask, double* W,
+                                    double* ref_fnorm) try {
+    if (order < 1 || order > TRI_MAX_ORDER)
+        return fail(nullptr, PCPF_EINVAL, "pcpf_triangle_operators: order out of range 1..5");
+    if (!upt_ref || !fpt_ref || !M0 || !D || !LiftN || !Lift || !Vinv || !topmask || !W || !ref_fnorm)
+        return fail(nullptr, PCPF_EINVAL, "pcpf_triangle_operators: null output");
+    TriOps T;
+    if (!tri_operators(order, &T))
+        return fail(nullptr, PCPF_EINVAL, "pcpf_triangle_operators: singular construction");
+    const int nu = T.nu, nf = T.nf;
+    std::copy(T.upt.begin(), T.upt.end(), upt_ref);
+    std::copy(T.fpt.begin(), T.fpt.end(), fpt_ref);
+    std::copy(T.M0.begin(), T.M0.end(), M0);
+    std::copy(T.D0.begin(), T.D0.end(), D);
+    std::copy(T.D1.begin(), T.D1.end(), D + nu * nu);
+    std::copy(T.Lift.begin(), T.Lift.end(), Lift);
+    for (int k = 0; k < 2; ++k)
+        for (int i = 0; i < nu; ++i)
+            for (int f = 0; f < nf; ++f)
+                LiftN[(k * nu + i) * nf + f] = T.Lift[i * nf + f] * T.nh[2 * f + k];
+    std::copy(T.Vinv.begin(), T.Vinv.end(), Vinv);
+    std::copy(T.top.begin(), T.top.end(), topmask);
+    std::copy(T.W.begin(), T.W.end(), W);
+    std::copy(T.nh.begin(), T.nh.end(), ref_fnorm);
+    return PCPF_OK;
+} catch (...) {
+    return out_of_memory(nullptr);
+}
+
 }  // extern "C"
 
 namespace {
@@ -140,6 +380,10 @@ namespace {
 struct MeshInfo {
     int d, p, n, nu, nfa;
     int64_t E;
+    int shape = PCPF_SHAPE_TENSOR;
+    int nf = 0;    // flux points per element
+    int ntr = 0;   // trace slots per element: the + faces (tensor, pushed by the neighbours)
+                   // or every flux point (triangle, written by the element itself)
 };
 
 pcpf_status check_mesh(const pcpf_mesh* m, MeshInfo* mi, std::string* err) {
@@ -159,6 +403,8 @@ pcpf_status check_mesh(const pcpf_mesh* m, MeshInfo* mi, std::string* err) {
     mi->n = m->order + 1;
     mi->nu = ipow(mi->n, mi->d);
     mi->nfa = ipow(mi->n, mi->d - 1);
+    mi->nf = 2 * mi->d * mi->nfa;
+    mi->ntr = mi->d * mi->nfa;
     mi->E = m->nelem;
     // the kernels address every per-element array with 32-bit byte offsets
     const int64_t geo = mi->d + 2 * mi->d * mi->d + 1;
@@ -270,7 +516,7 @@ Layout layout(const MeshInfo& mi, int precision) {
     const size_t r = precision != PCPF_FP64 ? 4 : 8;
     const size_t E = (size_t)mi.E;
     const size_t state = 2 * E * mi.nu * r;              // two variables
-    const size_t face = 2 * E * mi.d * mi.nfa * r;
+    const bool tri = mi.shape == PCPF_SHAPE_TRIANGLE;
     const int geo = mi.d + 2 * mi.d * mi.d + 1;
     Layout L{};
     size_t off = 0;
@@ -283,15 +529,18 @@ Layout layout(const MeshInfo& mi, int precision) {
     L.us = take(state);
     L.acc = take(state);
     L.P = take(state);
-    L.Fp = take(2 * face);   // [V][2D][E][NFA]: + face fluxes, then boundary - face fluxes
-    L.Tp = take(face);       // [V][D][E][NFA]
+    // common fluxes, per variable E N_f slots: tensor [2D][E][NFA] (+ face fluxes, then
+    // boundary - face fluxes), triangle [E][N_f]
+    L.Fp = take(2 * E * mi.nf * r);
+    // traces, per variable E ntr: tensor [D][E][NFA] (pushed), triangle [E][N_f] (own)
+    L.Tp = take(2 * E * mi.ntr * r);
     L.sgn = take(E * mi.nu * r);
     L.geo = take(E * geo * r);
-    L.vtab = take(E * mi.d * (mi.n + 2) * 2 * r);   // velocity tables (axis-aligned meshes)
+    L.vtab = take(tri ? 0 : E * mi.d * (mi.n + 2) * 2 * r);   // velocity tables (axis-aligned)
     L.det64 = take(E * 8);
-    L.w64 = take(mi.n * 8);
-    L.nbr = take(E * 2 * mi.d * 4);
-    L.ops = take(ops_size(mi.n) * r);
+    L.w64 = take((tri ? mi.nu : mi.n) * 8);
+    L.nbr = take(E * (tri ? mi.nf : 2 * mi.d) * 4);
+    L.ops = take((tri ? tri_ops_size(mi.p) : ops_size(mi.n)) * r);
     L.flag = take(4);
     L.partial = take(REDUCE_BLOCKS * 8);
     L.red = take(8);
@@ -355,12 +604,13 @@ struct Ctx {
     R* plane(size_t off, int v) const {
         return reinterpret_cast<R*>(c->ws + off) + (size_t)v * c->mi.E * c->mi.nu;
     }
+    // variable v of the trace buffer
     R* fplane(size_t off, int v) const {
-        return reinterpret_cast<R*>(c->ws + off) + (size_t)v * c->mi.E * c->mi.d * c->mi.nfa;
+        return reinterpret_cast<R*>(c->ws + off) + (size_t)v * c->mi.E * c->mi.ntr;
     }
-    // variable v of the common-flux buffer (2D planes of E N_fa per variable)
+    // variable v of the common-flux buffer (E N_f slots per variable)
     R* flux(int v) const {
-        return reinterpret_cast<R*>(c->ws + c->L.Fp) + (size_t)v * 2 * c->mi.E * c->mi.d * c->mi.nfa;
+        return reinterpret_cast<R*>(c->ws + c->L.Fp) + (size_t)v * c->mi.E * c->mi.nf;
     }
     template <typename T>
     T* at(size_t off) const {
@@ -1278,8 +1528,6 @@ bool same_operator(const double* given, size_t count, F expected) {
 pcpf_status dense_to_line(const pcpf_dense_mesh* dm, DenseLine* h) {
     if (!dm) return fail(nullptr, PCPF_EINVAL, "dense mesh is NULL");
     if (dm->ndims != 2 && dm->ndims != 3) return fail(nullptr, PCPF_EINVAL, "ndims must be 2 or 3");
-    if (dm->shape == PCPF_SHAPE_TRIANGLE)
-        return fail(nullptr, PCPF_EUNSUPPORTED, "triangular elements are not built");
     if (dm->shape != PCPF_SHAPE_TENSOR) return fail(nullptr, PCPF_EINVAL, "unknown element shape");
     const int d = dm->ndims, p = dm->order;
     const int pmax = d == 2 ? PCPF_MAX_ORDER : 5;
@@ -1491,6 +1739,233 @@ pcpf_status dense_to_line(const pcpf_dense_mesh* dm, DenseLine* h) {
 }  // namespace
 
 // ------------------------------------------------------------------------------------
+// dense description of a triangle mesh
+// ------------------------------------------------------------------------------------
+struct TriHolder {
+    TriOps T;
+    int64_t E = 0;
+    std::vector<double> x0, jac;
+    std::vector<int32_t> code;   // 2 s' + owner, -1 on a boundary
+};
+
+pcpf_status dense_to_tri(const pcpf_dense_mesh* dm, TriHolder* h) {
+    const int p = dm->order;
+    if (dm->ndims != 2) return fail(nullptr, PCPF_EINVAL, "triangles are two-dimensional");
+    if (p < 1 || p > TRI_MAX_ORDER) return fail(nullptr, PCPF_EUNSUPPORTED, "triangle orders 1..5 are built");
+    const int nu = tri_nupts(p), nf = tri_nfpts(p);
+    if (dm->nupts != nu || dm->nfpts != nf)
+        return fail(nullptr, PCPF_EINVAL, "nupts / nfpts do not match the triangle of order p");
+    const int64_t E = dm->nelem;
+    if (E < 1 || E * nf >= ((int64_t)1 << 30)) return fail(nullptr, PCPF_EINVAL, "nelem out of range");
+    if (!dm->M0 || !dm->D || !dm->LiftN || !dm->Lift || !dm->Vinv || !dm->topmask || !dm->W ||
+        !dm->ref_fnorm || !dm->jinv || !dm->detj || !dm->fnorm || !dm->fscale || !dm->xorig ||
+        !dm->nbr_slot || !dm->owner)
+        return fail(nullptr, PCPF_EINVAL, "dense mesh has a NULL array");
+    TriOps& T = h->T;
+    if (!tri_operators(p, &T)) return fail(nullptr, PCPF_EINVAL, "triangle operators: singular construction");
+    const char* bad = nullptr;
+    if (!same_operator(dm->M0, (size_t)nf * nu, [&](size_t q) { return T.M0[q]; }))
+        bad = "M0";
+    else if (!same_operator(dm->D, (size_t)2 * nu * nu, [&](size_t q) {
+                 return q < (size_t)nu * nu ? T.D0[q] : T.D1[q - (size_t)nu * nu];
+             }))
+        bad = "D";
+    else if (!same_operator(dm->Lift, (size_t)nu * nf, [&](size_t q) { return T.Lift[q]; }))
+        bad = "Lift";
+    else if (!same_operator(dm->LiftN, (size_t)2 * nu * nf, [&](size_t q) {
+                 const size_t k = q / ((size_t)nu * nf), r = q % ((size_t)nu * nf);
+                 return T.Lift[r] * T.nh[2 * (r % nf) + k];
+             }))
+        bad = "LiftN";
+    else if (!same_operator(dm->Vinv, (size_t)nu * nu, [&](size_t q) { return T.Vinv[q]; }))
+        bad = "Vinv";
+    else if (!same_operator(dm->W, (size_t)nu, [&](size_t q) { return T.W[q]; }))
+        bad = "W";
+    else if (!same_operator(dm->ref_fnorm, (size_t)2 * nf, [&](size_t q) { return T.nh[q]; }))
+        bad = "ref_fnorm";
+    if (bad)
+        return fail(nullptr, PCPF_EUNSUPPORTED,
+                    std::string("dense operator ") + bad +
+                        " is not that of the library's triangle (interior lattice solution "
+                        "points, Gauss-Legendre edge points, DG correction functions)");
+    for (int j = 0; j < nu; ++j)
+        if ((dm->topmask[j] != 0) != (T.top[j] != 0))
+            return fail(nullptr, PCPF_EUNSUPPORTED, "topmask does not select the degree-p modes");
+    h->E = E;
+    h->x0.assign(dm->xorig, dm->xorig + E * 2);
+    h->jac.resize((size_t)E * 4);
+    std::vector<double> Jm(4), Ji(4);
+    double hmin = 1e300;
+    for (int64_t e = 0; e < E; ++e) {
+        const double* gi = dm->jinv + e * 4;
+        double det;
+        if (dm->jac) {
+            std::copy(dm->jac + e * 4, dm->jac + (e + 1) * 4, Jm.begin());
+            inv_det(2, Jm.data(), Ji.data(), &det);
+            double sc = 0.0;
+            for (int q = 0; q < 4; ++q) sc = std::max(sc, std::fabs(gi[q]));
+            for (int q = 0; q < 4; ++q)
+                if (!(std::fabs(Ji[q] - gi[q]) <= 1e-12 * sc))
+                    return fail(nullptr, PCPF_EINVAL, "jinv is not the inverse of jac");
+        } else {
+            double idet;
+            inv_det(2, gi, Jm.data(), &idet);
+            det = 1.0 / idet;
+        }
+        if (!(det > 0.0)) return fail(nullptr, PCPF_EINVAL, "element with det J <= 0");
+        if (!(std::fabs(det - dm->detj[e]) <= 1e-12 * det))
+            return fail(nullptr, PCPF_EINVAL, "detj disagrees with the Jacobian");
+        hmin = std::min(hmin, std::sqrt(det));
+        for (int f = 0; f < nf; ++f) {
+            double nr[2];
+            for (int i = 0; i < 2; ++i) nr[i] = gi[0 * 2 + i] * T.nh[2 * f] + gi[1 * 2 + i] * T.nh[2 * f + 1];
+            const double mag = std::sqrt(nr[0] * nr[0] + nr[1] * nr[1]);
+            for (int i = 0; i < 2; ++i)
+                if (!(std::fabs(dm->fnorm[(e * nf + f) * 2 + i] - nr[i] / mag) <= 1e-12))
+                    return fail(nullptr, PCPF_EINVAL, "fnorm disagrees with the Jacobian");
+            if (!(std::fabs(dm->fscale[e * nf + f] - det * mag) <= 1e-12 * det * mag))
+                return fail(nullptr, PCPF_EINVAL, "fscale disagrees with the Jacobian");
+        }
+        std::copy(Jm.begin(), Jm.end(), h->jac.begin() + e * 4);
+    }
+    // pairing: reciprocal, one owner per pair, coincident points up to the periods
+    const int64_t S = E * nf;
+    const double tol = 1e-8 * hmin;
+    h->code.assign((size_t)S, -1);
+    auto point = [&](int64_t sl, double* x) {
+        const int64_t e = sl / nf;
+        const int f = (int)(sl % nf);
+        const double* J = &h->jac[e * 4];
+        for (int i = 0; i < 2; ++i)
+            x[i] = h->x0[e * 2 + i] + J[i * 2 + 0] * T.fpt[2 * f] + J[i * 2 + 1] * T.fpt[2 * f + 1];
+    };
+    for (int64_t sl = 0; sl < S; ++sl) {
+        const int32_t ns = dm->nbr_slot[sl];
+        if (ns < -1 || ns >= S) return fail(nullptr, PCPF_EINVAL, "nbr_slot out of range");
+        if (dm->owner[sl] > 1) return fail(nullptr, PCPF_EINVAL, "owner flags must be 0 or 1");
+        if (ns < 0) {
+            if (dm->owner[sl] != 1) return fail(nullptr, PCPF_EINVAL, "a boundary flux point must be owned");
+            continue;
+        }
+        if (dm->nbr_slot[ns] != sl) return fail(nullptr, PCPF_EINVAL, "nbr_slot pairs are not reciprocal");
+        if (dm->owner[sl] + dm->owner[ns] != 1)
+            return fail(nullptr, PCPF_EINVAL, "each flux-point pair needs exactly one owner");
+        double xa[2], xb[2];
+        point(sl, xa);
+        point(ns, xb);
+        for (int q = 0; q < 2; ++q) {
+            double dq = xb[q] - xa[q];
+            if (dm->period[q] > 0.0) dq -= std::round(dq / dm->period[q]) * dm->period[q];
+            if (std::fabs(dq) > tol)
+                return fail(nullptr, PCPF_EINVAL,
+                            "paired flux points do not coincide (up to the periods)");
+        }
+        h->code[sl] = 2 * ns + dm->owner[sl];
+    }
+    return PCPF_OK;
+}
+
+template <typename R>
+pcpf_status upload_tri(pcpf_ctx* c, const TriHolder& h) {
+    const TriOps& T = h.T;
+    const int nu = T.nu, nf = T.nf, G = 11;
+    const int64_t E = h.E;
+    std::vector<R> geo((size_t)E * G);
+    std::vector<double> det64(E), ji(4);
+    for (int64_t e = 0; e < E; ++e) {
+        double det;
+        const double* J = &h.jac[e * 4];
+        inv_det(2, J, ji.data(), &det);
+        R* g = geo.data() + e * G;
+        for (int k = 0; k < 2; ++k) g[k] = (R)h.x0[e * 2 + k];
+        for (int k = 0; k < 4; ++k) g[2 + k] = (R)J[k];
+        for (int k = 0; k < 4; ++k) g[6 + k] = (R)ji[k];
+        g[10] = (R)det;
+        det64[e] = det;
+    }
+    std::vector<R> ops(tri_ops_size(T.p));
+    size_t o = 0;
+    auto put = [&](const std::vector<double>& v) {
+        for (double x : v) ops[o++] = (R)x;
+    };
+    put(T.M0);
+    put(T.D0);
+    put(T.D1);
+    put(T.Lift);
+    put(T.Vinv);
+    for (int j = 0; j < nu; ++j) ops[o++] = (R)T.top[j];
+    put(T.upt);
+    put(T.fpt);
+    put(T.nh);
+    (void)nf;
+    Ctx<R> C{c};
+    HIPCHK(c, hipMemcpyAsync(C.template at<R>(c->L.geo), geo.data(), geo.size() * sizeof(R),
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(C.template at<double>(c->L.det64), det64.data(), E * 8,
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(C.template at<double>(c->L.w64), T.W.data(), nu * 8,
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(C.template at<int32_t>(c->L.nbr), h.code.data(), h.code.size() * 4,
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(C.template at<R>(c->L.ops), ops.data(), ops.size() * sizeof(R),
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->ws + c->L.Fp, 0, c->L.sgn - c->L.Fp, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PCPF_OK;
+}
+
+MeshInfo tri_info(int p, int64_t E) {
+    MeshInfo mi{};
+    mi.d = 2;
+    mi.p = p;
+    mi.n = p + 1;
+    mi.nu = tri_nupts(p);
+    mi.nfa = p + 1;
+    mi.E = E;
+    mi.shape = PCPF_SHAPE_TRIANGLE;
+    mi.nf = tri_nfpts(p);
+    mi.ntr = mi.nf;
+    return mi;
+}
+
+pcpf_status create_tri(const TriHolder& h, const pcpf_params* p, void* d_ws, size_t ws_bytes,
+                       void* stream, pcpf_ctx** out) {
+    pcpf_status st = check_params(p, nullptr);
+    if (st != PCPF_OK) return st;
+    if (p->precision == PCPF_BF16)
+        return fail(nullptr, PCPF_EUNSUPPORTED, "the BF16 form is built for tensor elements");
+    const MeshInfo mi = tri_info(h.T.p, h.E);
+    if (mi.E * std::max(mi.nu, mi.nf) * 8 >= ((int64_t)1 << 32))
+        return fail(nullptr, PCPF_EUNSUPPORTED, "mesh too large: per-element arrays above 4 GiB");
+    Layout L = layout(mi, p->precision);
+    if (!d_ws || ws_bytes < L.total)
+        return fail(nullptr, PCPF_EINVAL, "workspace missing or smaller than pcpf_workspace_bytes");
+    if (reinterpret_cast<uintptr_t>(d_ws) % 256 != 0)
+        return fail(nullptr, PCPF_EINVAL, "workspace must be 256-byte aligned");
+    std::unique_ptr<pcpf_ctx> hold(new pcpf_ctx());
+    pcpf_ctx* c = hold.get();
+    c->mi = mi;
+    c->prm = *p;
+    c->stream = static_cast<hipStream_t>(stream);
+    if (hipGetDevice(&c->device) != hipSuccess)
+        return fail(nullptr, PCPF_EDEVICE, "hipGetDevice failed");
+    c->ws = static_cast<char*>(d_ws);
+    c->L = L;
+    c->axis = false;
+    c->bnd_minus = false;
+    const bool ok = p->precision != PCPF_FP64 ? get_tri_launchers<float>(mi.p, &c->L32)
+                                              : get_tri_launchers<double>(mi.p, &c->L64);
+    if (!ok) return fail(nullptr, PCPF_EUNSUPPORTED, "no triangle kernels built for this order");
+    st = p->precision != PCPF_FP64 ? upload_tri<float>(c, h) : upload_tri<double>(c, h);
+    if (st != PCPF_OK) {
+        g_err = c->err;
+        return st;
+    }
+    *out = hold.release();
+    return PCPF_OK;
+}
+
+// ------------------------------------------------------------------------------------
 // static adjoint scratch (pcpf_adjoint_static): one array per GPU the library runs on,
 // held until the process ends. In host code `scratch` names a host-side stand-in, not
 // device memory: its device address on each GPU comes from hipGetSymbolAddress, taken
@@ -1613,6 +2088,18 @@ pcpf_status pcpf_create(const pcpf_mesh* m, const pcpf_params* p, void* d_ws, si
 
 pcpf_status pcpf_workspace_bytes_dense(const pcpf_dense_mesh* dm, const pcpf_params* p,
                                        size_t* nbytes) try {
+    if (dm && dm->shape == PCPF_SHAPE_TRIANGLE) {
+        TriHolder th;
+        pcpf_status st = dense_to_tri(dm, &th);
+        if (st != PCPF_OK) return st;
+        st = check_params(p, nullptr);
+        if (st != PCPF_OK) return st;
+        if (p->precision == PCPF_BF16)
+            return fail(nullptr, PCPF_EUNSUPPORTED, "the BF16 form is built for tensor elements");
+        if (!nbytes) return fail(nullptr, PCPF_EINVAL, "nbytes is NULL");
+        *nbytes = layout(tri_info(th.T.p, th.E), p->precision).total;
+        return PCPF_OK;
+    }
     DenseLine h;
     pcpf_status st = dense_to_line(dm, &h);
     if (st != PCPF_OK) return st;
@@ -1625,6 +2112,12 @@ pcpf_status pcpf_create_dense(const pcpf_dense_mesh* dm, const pcpf_params* p, v
                               size_t ws_bytes, void* stream, pcpf_ctx** out) try {
     if (!out) return fail(nullptr, PCPF_EINVAL, "out is NULL");
     *out = nullptr;
+    if (dm && dm->shape == PCPF_SHAPE_TRIANGLE) {
+        TriHolder th;
+        pcpf_status st = dense_to_tri(dm, &th);
+        if (st != PCPF_OK) return st;
+        return create_tri(th, p, d_ws, ws_bytes, stream, out);
+    }
     DenseLine h;
     pcpf_status st = dense_to_line(dm, &h);
     if (st != PCPF_OK) return st;
@@ -1812,6 +2305,8 @@ pcpf_status pcpf_ckpt_bytes(const pcpf_ctx* c, int64_t nsteps, int64_t every, si
 pcpf_status pcpf_forward_ckpt(pcpf_ctx* c, double dt, int64_t nsteps, int64_t every, void* d_ckpt,
                               size_t ckpt_bytes) try {
     if (check_ctx(c) != PCPF_OK) return PCPF_EINVAL;
+    if (c->mi.shape != PCPF_SHAPE_TENSOR)
+        return fail(&c->err, PCPF_EUNSUPPORTED, "the adjoint is built for quadrilaterals and hexahedra");
     if (c->prm.precision == PCPF_BF16)
         return fail(&c->err, PCPF_EUNSUPPORTED, "no adjoint of the PCPF_BF16 form");
     if (c->prm.normal_mode == PCPF_NORMAL_PHI)
@@ -1837,6 +2332,8 @@ pcpf_status pcpf_forward_ckpt(pcpf_ctx* c, double dt, int64_t nsteps, int64_t ev
 pcpf_status pcpf_adjoint_bytes(const pcpf_ctx* c, int64_t every, size_t* nbytes) try {
     if (!c || !nbytes) return fail(nullptr, PCPF_EINVAL, "adjoint_bytes: NULL argument");
     if (every < 1) return fail(nullptr, PCPF_EINVAL, "every must be >= 1");
+    if (c->mi.shape != PCPF_SHAPE_TENSOR)
+        return fail(nullptr, PCPF_EUNSUPPORTED, "the adjoint is built for quadrilaterals and hexahedra");
     *nbytes = adj_layout(c, every).total;
     return PCPF_OK;
 } catch (...) {

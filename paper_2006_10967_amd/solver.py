@@ -39,6 +39,21 @@ def line_operators(order: int) -> dict:
     return out
 
 
+def triangle_operators(order: int) -> dict:
+    """Dense operators of the library's order-p triangle element (host)."""
+    lib = _lib.load()
+    nu, nf = (order + 1) * (order + 2) // 2, 3 * (order + 1)
+    out = {"upt_ref": np.zeros((nu, 2)), "fpt_ref": np.zeros((nf, 2)), "M0": np.zeros((nf, nu)),
+           "D": np.zeros((2, nu, nu)), "LiftN": np.zeros((2, nu, nf)), "Lift": np.zeros((nu, nf)),
+           "Vinv": np.zeros((nu, nu)), "topmask": np.zeros(nu, dtype=np.uint8), "W": np.zeros(nu),
+           "ref_fnorm": np.zeros((nf, 2))}
+    check(lib.pcpf_triangle_operators(
+        order, *[_dptr(out[k]) for k in ("upt_ref", "fpt_ref", "M0", "D", "LiftN", "Lift", "Vinv")],
+        out["topmask"].ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), _dptr(out["W"]),
+        _dptr(out["ref_fnorm"])))
+    return out
+
+
 class MeshArgs:
     """A pcpf_mesh whose host arrays stay alive as long as this object."""
 

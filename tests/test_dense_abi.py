@@ -159,8 +159,10 @@ def test_dense_description_rejected(cid, d, p, kw):
     dm = _dense(d, p, mesh, arr, ops)
     dm.c.nupts += 1
     assert _status_of(lambda: dm.workspace_bytes(prm)) == _lib.PCPF_EINVAL
+    # a tensor-element description labelled as triangles: its point counts are not those of
+    # the triangle of order p (and a 3D one is no triangle mesh at all)
     dm = _dense(d, p, mesh, arr, ops, shape=_lib.PCPF_SHAPE_TRIANGLE)
-    assert _status_of(lambda: dm.workspace_bytes(prm)) == _lib.PCPF_EUNSUPPORTED
+    assert _status_of(lambda: dm.workspace_bytes(prm)) == _lib.PCPF_EINVAL
 
 
 @pytest.mark.gpu

@@ -1,0 +1,205 @@
+"""GPU parity of the triangle element (dense per-element operators, called through
+pcpf_create_dense) against the FP64 CPU oracle's triangle discretisation.
+
+Meshes are split-Cartesian triangle meshes from ``workloads`` (periodic, wall-bounded,
+mixed, with perturbed grid lines: general affine triangles); the dense description is the
+library's own triangle operators with geometry from the element maps and owners by the LDG
+switch vector. Bars as for the tensor elements: FP64 residuals <= 1e-12 relative (L_inf
+over max|R_oracle|), trajectories <= 1e-10 relative, mass conserved to 1e-12; FP32
+residuals <= 2e-4 relative (the FP32 bar of the tensor elements, same arithmetic per point).
+"""
+import zlib
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import Oracle
+from oracle import residual as ores
+from tri_dense import tri_dense
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _rel(a, b):
+    a = a.detach().double().cpu() if torch.is_tensor(a) else torch.as_tensor(a)
+    b = b.detach().double().cpu() if torch.is_tensor(b) else torch.as_tensor(b)
+    den = float(b.abs().max())
+    return float((a - b).abs().max()) / (den if den > 0 else 1.0)
+
+
+CASES = [
+    # (id, p, n cells per side, split_tri_mesh kwargs, velocity parameters)
+    ("tri_p1_uniform", 1, 7, dict(), dict(vel_u0=(0.6, 0.3))),
+    ("tri_p2_perturbed_vortex", 2, 6, dict(perturb=0.2), dict(vel_kind=W.VEL_SINGLE_VORTEX)),
+    ("tri_p3_copybc_rotation", 3, 5, dict(periodic=False), dict(vel_kind=W.VEL_ROTATION,
+                                                                 vel_u0=(0.5, 0.5, 0.0))),
+    ("tri_p3_mixed_bc", 3, 4, dict(periodic=(True, False)), dict(vel_u0=(0.7, -0.3))),
+    ("tri_p4_perturbed", 4, 4, dict(perturb=0.15, seed=5), dict(vel_u0=(-0.4, 0.8))),
+    ("tri_p4_copybc_vortex", 4, 3, dict(periodic=False, perturb=0.1),
+     dict(vel_kind=W.VEL_SINGLE_VORTEX)),
+    ("tri_p5", 5, 3, dict(), dict(vel_u0=(0.3, -0.9))),
+    ("tri_single_cell", 2, 1, dict(), dict(vel_u0=(1.0, 0.25))),
+]
+
+
+def _case(p, n, mkw, vkw, **over):
+    mesh = W.split_tri_mesh(n, **mkw)
+    prm = W.default_params(2, p, 1.0 / n, **vkw, **over)
+    return mesh, prm
+
+
+def _solver(p, mesh, prm, precision="fp64"):
+    from paper_2006_10967_amd import Solver
+    dm, _ = tri_dense(p, mesh)
+    return Solver.from_dense(dm, prm, precision=precision)
+
+
+def _states(o, rng, kind):
+    x = o.coords()
+    E, Nu = x.shape[:2]
+    if kind == "random":
+        return (torch.tensor(rng.uniform(0, 1, (E, Nu))), torch.tensor(rng.standard_normal((E, Nu))))
+    c = 0.5 + rng.uniform(-0.1, 0.1, 2)
+    phi = torch.tensor(W.ic_phi(x, c, 0.27, 0.05))
+    psi = torch.tensor(W.signed_distance_ball(x, c, 0.27) + 1e-3 * rng.standard_normal((E, Nu)))
+    return phi, psi
+
+
+@pytest.mark.parametrize("cid,p,n,mkw,vkw", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("kind", ["smooth", "random"])
+def test_triangle_physical_residual_parity(cid, p, n, mkw, vkw, kind):
+    mesh, prm = _case(p, n, mkw, vkw)
+    o = Oracle(2, p, mesh, prm)
+    s = _solver(p, mesh, prm)
+    rng = np.random.default_rng(zlib.crc32(f"{cid}:{kind}".encode()))
+    phi, psi = _states(o, rng, kind)
+    for t in (0.0, 0.37):
+        Rp, Rs = o.residual(phi, psi, t)
+        gp, gs = s.residual(phi, psi, t)
+        assert _rel(gp, Rp) <= TOL, (cid, kind, t, _rel(gp, Rp))
+        assert _rel(gs, Rs) <= TOL, (cid, kind, t, _rel(gs, Rs))
+
+
+NPHI = [c for c in CASES if c[0] in ("tri_p2_perturbed_vortex", "tri_p4_copybc_vortex")]
+
+
+@pytest.mark.parametrize("cid,p,n,mkw,vkw", NPHI, ids=[c[0] for c in NPHI])
+def test_triangle_unpreconditioned_residual_parity(cid, p, n, mkw, vkw):
+    mesh, prm = _case(p, n, mkw, vkw, normal_mode=W.NORMAL_PHI)
+    o = Oracle(2, p, mesh, prm)
+    s = _solver(p, mesh, prm)
+    for kind in ("smooth", "random"):
+        rng = np.random.default_rng(zlib.crc32(f"nphi:{cid}:{kind}".encode()))
+        phi, psi = _states(o, rng, kind)
+        Rp, Rs = o.residual(phi, psi, 0.3)
+        gp, gs = s.residual(phi, psi, 0.3)
+        assert _rel(gp, Rp) <= TOL, (cid, kind, _rel(gp, Rp))
+        assert _rel(gs, Rs) <= TOL, (cid, kind, _rel(gs, Rs))
+
+
+PC = [c for c in CASES if c[0] in ("tri_p2_perturbed_vortex", "tri_p3_copybc_rotation",
+                                   "tri_p3_mixed_bc", "tri_p4_perturbed", "tri_p5",
+                                   "tri_single_cell")]
+
+
+@pytest.mark.parametrize("cid,p,n,mkw,vkw", PC, ids=[c[0] for c in PC])
+def test_triangle_reset_sign_sensor_and_precond_residual_parity(cid, p, n, mkw, vkw):
+    mesh, prm = _case(p, n, mkw, vkw)
+    o = Oracle(2, p, mesh, prm)
+    s = _solver(p, mesh, prm)
+    rng = np.random.default_rng(zlib.crc32(f"pc:{cid}".encode()))
+    phi, psi = _states(o, rng, "smooth")
+    s.set_state(phi)
+    s.precondition(0)
+    psi0 = o.reset_psi(phi)
+    sgn = ores.smeared_sign(o.disc, prm, psi0)
+    assert _rel(s.sign(), sgn) <= TOL
+    _, gpsi0, _, _ = s.get_state()
+    assert float((gpsi0.cpu() - psi0).abs().max()) == 0.0
+    for amp in (0.0, 1e-4, 1e-2, 1.0):
+        field = psi + amp * torch.tensor(rng.standard_normal(psi.shape))
+        nu_o = o.sensor(field)
+        nu_g = s.sensor(field)
+        assert float((nu_g.cpu() - nu_o).abs().max()) <= TOL * prm.nu_max, (cid, amp)
+    for amp in (1e-3, 1e-1):
+        field = psi + amp * torch.tensor(rng.standard_normal(psi.shape))
+        R = o.precond_residual(field, sgn)
+        _, gR = s.residual(None, field, 0.0, mode=1)
+        assert _rel(gR, R) <= TOL, (cid, amp, _rel(gR, R))
+
+
+def test_triangle_preconditioning_parity():
+    """Reset + 10 pseudo-time RK4 iterations on a perturbed periodic p=3 mesh."""
+    mesh, prm = _case(3, 6, dict(perturb=0.2, seed=2), dict(vel_u0=(0.5, 0.5)))
+    o = Oracle(2, 3, mesh, prm)
+    s = _solver(3, mesh, prm)
+    phi = torch.tensor(W.ic_phi(o.coords(), np.array([0.47, 0.52]), 0.3, prm.eps_w))
+    psi_o, _ = o.precondition(phi)
+    s.set_state(phi)
+    s.precondition()
+    _, psi_g, _, _ = s.get_state()
+    assert _rel(psi_g, psi_o) <= 1e-12
+
+
+@pytest.mark.parametrize("p,n,mkw,vkw", [
+    (3, 6, dict(perturb=0.2, seed=4), dict(vel_kind=W.VEL_SINGLE_VORTEX)),
+    (2, 5, dict(periodic=False), dict(vel_kind=W.VEL_ROTATION, vel_u0=(0.5, 0.5, 0.0))),
+    (4, 4, dict(periodic=(False, True), perturb=0.1), dict(vel_u0=(0.4, -0.6))),
+], ids=["p3_perturbed_vortex", "p2_walls_rotation", "p4_mixed_bc"])
+def test_triangle_trajectory_parity(p, n, mkw, vkw):
+    """Reset + 3 pseudo iterations, 20 RK4 steps with a reset at step 12: phi and psi match
+    the oracle to 1e-10; the GPU's quadrature equals the oracle's, and it conserves mass
+    to round-off where no flux crosses the boundary (periodic, or the single vortex, whose
+    velocity is tangential on the walls)."""
+    mesh, prm = _case(p, n, mkw, vkw, precond_iters=3, reset_every=12)
+    o = Oracle(2, p, mesh, prm)
+    s = _solver(p, mesh, prm)
+    phi0 = torch.tensor(W.ic_phi(o.coords(), np.array([0.45, 0.5]), 0.25, 0.06))
+    dt = 0.05 / (n * (2 * p + 1))
+    phi_o, psi_o, _ = o.run(phi0, None, 0.0, dt, 20)
+    s.set_state(phi0)
+    s.step(dt, 20)
+    phi_g, psi_g, t, nst = s.get_state()
+    assert nst == 20 and abs(t - 20 * dt) < 1e-12
+    assert _rel(phi_g, phi_o) <= 1e-10
+    assert _rel(psi_g, psi_o) <= 1e-10
+    m0 = s.mass(phi0)
+    assert abs(m0 - float(o.mass(phi0))) <= 1e-14 * abs(m0)
+    if mkw.get("periodic", True) is True or vkw.get("vel_kind") == W.VEL_SINGLE_VORTEX:
+        assert abs(s.mass() - m0) / m0 <= 1e-12
+    assert abs(s.l1(phi0) - float(o.l1(phi_g.cpu(), phi0))) <= 1e-13
+
+
+FP32 = [c for c in CASES if c[0] in ("tri_p2_perturbed_vortex", "tri_p3_copybc_rotation",
+                                     "tri_p4_perturbed")]
+
+
+@pytest.mark.parametrize("cid,p,n,mkw,vkw", FP32, ids=[c[0] for c in FP32])
+def test_triangle_fp32_residual(cid, p, n, mkw, vkw):
+    mesh, prm = _case(p, n, mkw, vkw)
+    o = Oracle(2, p, mesh, prm)
+    s = _solver(p, mesh, prm, "fp32")
+    rng = np.random.default_rng(zlib.crc32(f"fp32:{cid}".encode()))
+    phi, psi = _states(o, rng, "smooth")
+    Rp, Rs = o.residual(phi, psi, 0.2)
+    gp, gs = s.residual(phi.float(), psi.float(), 0.2)
+    assert _rel(gp, Rp) <= 2e-4, (cid, _rel(gp, Rp))
+    assert _rel(gs, Rs) <= 2e-4, (cid, _rel(gs, Rs))
+
+
+def test_triangle_adjoint_and_bf16_refused():
+    from paper_2006_10967_amd import PcpfError, _lib
+    mesh, prm = _case(2, 3, dict(), dict(vel_u0=(0.5, 0.5)))
+    s = _solver(2, mesh, prm)
+    o = Oracle(2, 2, mesh, prm)
+    s.set_state(torch.tensor(W.ic_phi(o.coords(), np.array([0.5, 0.5]), 0.3, 0.1)))
+    with pytest.raises(PcpfError) as ei:
+        s.forward_ckpt(1e-3, 4)
+    assert ei.value.status == _lib.PCPF_EUNSUPPORTED
+    with pytest.raises(PcpfError) as ei:
+        _solver(2, mesh, prm, "bf16")
+    assert ei.value.status == _lib.PCPF_EUNSUPPORTED

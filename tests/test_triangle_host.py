@@ -1,0 +1,74 @@
+"""The library's own triangle element (host builder: a Legendre-product basis, a collapsed
+Gauss mass matrix and Cholesky modes) against the oracle's independent construction
+(centred monomials, closed-form moments): the same operators to rounding, for p = 1..5;
+and the dense description of a split triangle mesh accepted, with each kind of wrong input
+getting its status (CPU only)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.triangle import TriangleOperators
+from tri_dense import tri_dense
+
+P = pytest.importorskip("paper_2006_10967_amd")
+from paper_2006_10967_amd import DenseMeshArgs, PcpfError, _lib, triangle_operators  # noqa: E402
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
+def test_library_triangle_matches_oracle(p):
+    lib = triangle_operators(p)
+    ora = TriangleOperators(p)
+    pairs = [("upt_ref", ora.upt_ref), ("fpt_ref", ora.fpt_ref), ("M0", ora.M0),
+             ("D", np.stack(ora.D)), ("LiftN", np.stack(ora.LiftN)), ("Lift", ora.LiftDiv),
+             ("Vinv", ora.Vt_inv), ("W", ora.W), ("ref_fnorm", ora.nhat)]
+    for name, ref in pairs:
+        scale = max(1.0, float(np.abs(ref).max()))
+        err = float(np.abs(lib[name] - ref).max()) / scale
+        assert err < 1e-12, (p, name, err)
+    assert np.array_equal(lib["topmask"] > 0, ora.topmask > 0)
+
+
+def _status(fn):
+    try:
+        fn()
+    except PcpfError as e:
+        return e.status
+    return 0
+
+
+@pytest.mark.parametrize("p", [2, 4])
+def test_triangle_dense_description(p):
+    mesh = W.split_tri_mesh(5, perturb=0.15)
+    prm = W.default_params(2, p, 0.2)
+    dm, arr = tri_dense(p, mesh)
+    assert dm.workspace_bytes(prm) > 0
+    dm2, _ = tri_dense(p, W.split_tri_mesh(4, periodic=False))
+    assert dm2.workspace_bytes(prm) > 0
+
+    def with_(**kw):
+        a = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in arr.items()}
+        for k, f in kw.items():
+            f(a[k])
+        return DenseMeshArgs(2, p, mesh.nelem, a["W"].size, a["M0"].shape[0], a,
+                             [1.0, 1.0], shape=_lib.PCPF_SHAPE_TRIANGLE)
+
+    ns = arr["nbr_slot"]
+    s0 = int(np.nonzero(ns >= 0)[0][0])
+    cases = [
+        ("D entry", _lib.PCPF_EUNSUPPORTED, dict(D=lambda a: a.__setitem__((0, 1, 2), a[0, 1, 2] + 1e-6))),
+        ("Lift sign", _lib.PCPF_EUNSUPPORTED, dict(Lift=lambda a: a.__imul__(-1.0))),
+        ("detj", _lib.PCPF_EINVAL, dict(detj=lambda a: a.__setitem__(0, 1.01 * a[0]))),
+        ("fnorm", _lib.PCPF_EINVAL, dict(fnorm=lambda a: a.__imul__(-1.0))),
+        ("two owners", _lib.PCPF_EINVAL, dict(owner=lambda a: a.__setitem__(ns[s0], a[s0]))),
+        ("non-reciprocal", _lib.PCPF_EINVAL, dict(nbr_slot=lambda a: a.__setitem__(ns[s0], -1))),
+        # pairing the flux points of an edge in the same (not the reversed) order
+        ("unmatched points", _lib.PCPF_EINVAL,
+         dict(nbr_slot=lambda a: (a.__setitem__(s0, ns[s0 + 1]), a.__setitem__(s0 + 1, ns[s0]),
+                                  a.__setitem__(ns[s0], s0 + 1), a.__setitem__(ns[s0 + 1], s0)))),
+    ]
+    for name, want, kw in cases:
+        got = _status(lambda: with_(**kw).workspace_bytes(prm))
+        assert got == want, (name, got, want)
+    # the BF16 form is built for tensor elements only; FP32 is
+    assert _status(lambda: dm.workspace_bytes(prm, "bf16")) == _lib.PCPF_EUNSUPPORTED
+    assert dm.workspace_bytes(prm, "fp32") > 0
