@@ -159,9 +159,12 @@ __device__ __forceinline__ void velocity_lin(const Phys<R>& ph, const R (&x)[D],
 // max(sqrt(x), g) for x >= 0 and g > 0: the flux multiplier max(gamma, |v|) of §2. The root is
 // taken only where x > g^2, which keeps its argument away from the tiny and huge ranges a
 // general square root has to rescale. There the hardware reciprocal-root estimate y is
-// refined by one coupled Newton step for the pair (sqrt(x), 1/(2 sqrt(x))), started from
-// (x y, y / 2), and one correction by the residual x - s^2 (within an ulp or two of the
-// rounded root). NaN gives g, as max(sqrt(NaN), g) does.
+// refined by one step of Goldschmidt's coupled iteration for the pair
+// (s, h) ~ (sqrt(x), 1/(2 sqrt(x))), started from (x y, y / 2): r = 1/2 - s h,
+// s += s r, h += h r (quadratic convergence), then one Newton correction by the residual,
+// s + h (x - s^2). With an estimate of relative error up to 2^-20 the result is within one
+// ulp of the correctly rounded root (checked by exact emulation of every fused
+// multiply-add on the CPU). NaN gives g, as max(sqrt(NaN), g) does.
 __device__ __forceinline__ double max_sqrt(double x, double g) {
     if (!(x > g * g)) return g;
     const double y = __builtin_amdgcn_rsq(x);
