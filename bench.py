@@ -23,9 +23,11 @@ Prints ONE JSON line:
                second timed region) against HBM: algorithmic bytes per stage
                (5 V N_u + 2 V N_f words per element) over the stage's kernel time, with
                the two-launch implementation's bytes and the counter-measured bytes beside;
-  legs         the same measurements on the 64^3 p = 3 deformation workload and the
-               128^2 p = 4 single-vortex workload (cache-resident), and the adjoint
-               workload (64^2 p = 3, checkpoints every 32 of 512 steps);
+  legs         the same measurements on the 64^3 p = 3 deformation workload, the
+               128^2 p = 4 single-vortex workload (cache-resident) and the single vortex
+               on 1024^2 split-Cartesian cells of triangles (p = 4, 2.1 M elements; dense
+               per-element operators), and the adjoint workload (64^2 p = 3, checkpoints
+               every 32 of 512 steps);
   cpu_baseline the FP64 oracle on the host cores on an 8^3 sub-mesh of the same kind
                (the full mesh does not fit a bounded CPU run).
 """
@@ -59,7 +61,7 @@ def sync():
     torch.cuda.synchronize()
 
 
-def stage_words(d, p):
+def stage_words(d, p, element="tensor"):
     """Words per element of one RK stage.
 
     alg:  5 V N_u + 2 V N_f (read the stage input and u_n, read and write the accumulator,
@@ -70,8 +72,22 @@ def stage_words(d, p):
           of its + faces (its own slot and the neighbour's); update reads those, u_n and the
           accumulator and writes the accumulator, the next stage input and its - face traces.
     """
-    n = p + 1
     V = 2
+    if element == "triangle":
+        # every flux point has its own trace and flux slot: grad_flux reads u, the own and
+        # the partner's traces, geometry and the slot table (one 4-byte code per point, half
+        # a word), writes P and the common flux of the owned half of its points (all of its
+        # boundary points); update reads P, the flux of every point (own or partner slot),
+        # u_n, the accumulator, geometry and the slot table, writes the accumulator, the
+        # next stage input and its own traces
+        nu, nf = (p + 1) * (p + 2) // 2, 3 * (p + 1)
+        geo = 11
+        alg = 5 * V * nu + 2 * V * nf
+        gf = V * nu + 2 * V * nf + geo + 0.5 * nf + V * nu + 0.5 * V * nf
+        up = (V * nu + V * nf + geo + 0.5 * nf + V * nu + 0.75 * V * nu + 0.75 * V * nu
+              + V * nu + V * nf)
+        return {"alg": alg, "impl": gf + up, "grad_flux": gf, "update": up}
+    n = p + 1
     nu, nfa = n ** d, n ** (d - 1)
     nf = 2 * d * nfa
     npf = d * nfa
@@ -93,13 +109,19 @@ def kernel_source_hash():
 
 def make_solver(cfg, mesh, precision, prm=None):
     from paper_2006_10967_amd import Solver
+    if cfg.element == "triangle":
+        return Solver.from_triangles(mesh, cfg.order, prm or cfg.params, precision=precision,
+                                     device="cuda:0")
     return Solver.from_box(mesh, cfg.order, prm or cfg.params, precision=precision,
                            device="cuda:0")
 
 
 def initial_state(cfg, mesh):
     import workloads as W
-    from paper_2006_10967_amd import MeshArgs
+    from paper_2006_10967_amd import DenseMeshArgs, MeshArgs
+    if cfg.element == "triangle":
+        x = DenseMeshArgs.from_triangles(mesh, cfg.order).solution_coords()
+        return W.ic_phi(x, cfg.centre, cfg.radius, cfg.params.eps_w)
     period = [float(mesh.period[k]) if mesh.periodic[k] else 0.0 for k in range(cfg.ndims)]
     x = MeshArgs(cfg.ndims, cfg.order, mesh.x0, mesh.jac, mesh.nbr, period).solution_coords()
     return W.ic_phi(x, cfg.centre, cfg.radius, cfg.params.eps_w)
@@ -176,7 +198,7 @@ def workload_leg(name, forms, K, Wm, acc_steps, hsh):
     cfg = W.config(name)
     mesh = cfg.mesh()
     phi0 = initial_state(cfg, mesh)
-    words = stage_words(cfg.ndims, cfg.order)
+    words = stage_words(cfg.ndims, cfg.order, cfg.element)
     log(f"[bench] {cfg.name}: E={cfg.nelem} N_u={cfg.nupts} DOF={cfg.dof} K={K} warmup={Wm}")
     out = {"workload": cfg.name, "description": cfg.description, "elements": cfg.nelem,
            "order": cfg.order, "dof": cfg.dof, "dt": cfg.dt(mesh),
@@ -644,7 +666,7 @@ def pseudo_sweep_leg():
     return out
 
 
-LEG_MIN_STEPS = {"C3": 50, "C2": 1000, "C1": 200, "C4": 200}
+LEG_MIN_STEPS = {"C3": 50, "C2": 1000, "C1": 200, "C4": 200, "T1": 1000, "T2": 20}
 
 
 def main():
@@ -658,7 +680,7 @@ def main():
     ap.add_argument("--forms", default="fp64,fp32,bf16")
     ap.add_argument("--acc-steps", type=int, default=100,
                     help="steps of the per-form interface comparison run (0: skip)")
-    ap.add_argument("--legs", default="C3,C2",
+    ap.add_argument("--legs", default="C3,C2,T2",
                     help="further workloads measured the same way (comma list, '' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,

@@ -84,6 +84,14 @@ class MeshArgs:
         return xs
 
 
+# LDG switch vector of the triangle meshes: on an interior edge the owner (beta = +1/2, the
+# side that takes the neighbour's trace in the common solution and computes the common flux)
+# is the side whose outward normal has a positive component along it. Any fixed vector
+# not parallel to an edge of the mesh gives a valid LDG orientation; this one is parallel to
+# no edge of a split-Cartesian mesh (axis-aligned and diagonal edges).
+TRI_SWITCH = np.array([1.0, 1.0 / np.sqrt(2.0)])
+
+
 class DenseMeshArgs:
     """A pcpf_dense_mesh (the dense operators, per-element geometry and per-flux-point
     connectivity of the method's statement) whose host arrays stay alive as long as this
@@ -118,6 +126,37 @@ class DenseMeshArgs:
         c.period = (ctypes.c_double * 3)(*[float(x) for x in (list(period) + [0.0] * 3)[:3]])
         self.c = c
         self.ndims, self.order, self.nelem, self.nupts = int(ndims), int(order), int(nelem), int(nupts)
+
+    @classmethod
+    def from_triangles(cls, mesh, order: int, ops: dict | None = None) -> "DenseMeshArgs":
+        """The dense description of a triangle mesh (x0 [E, 2], jac [E, 2, 2] of the maps
+        x = x0 + J (r, s), the flux-point pairing of ``mesh.slot_pairs(order + 1)``, periods):
+        the library's triangle operators (or given ones), J^-1, det J, unit normals
+        J^-T nhat / |J^-T nhat| and face scales det J |J^-T nhat| per flux point, owners by
+        TRI_SWITCH (boundary points owned)."""
+        ops = ops or triangle_operators(order)
+        nu, nf = ops["W"].size, ops["M0"].shape[0]
+        jac = np.asarray(mesh.jac, dtype=np.float64)
+        jinv = np.linalg.inv(jac)
+        det = np.linalg.det(jac)
+        nr = np.einsum("eki,fk->efi", jinv, ops["ref_fnorm"])
+        mag = np.linalg.norm(nr, axis=-1)
+        fnorm = nr / mag[..., None]
+        nbr_slot = np.asarray(mesh.slot_pairs(order + 1))
+        owner = np.where(nbr_slot >= 0, (fnorm.reshape(-1, 2) @ TRI_SWITCH) > 0, True)
+        arr = dict(ops, jinv=jinv, detj=det, fnorm=fnorm, fscale=det[:, None] * mag,
+                   xorig=np.asarray(mesh.x0, dtype=np.float64), jac=jac, nbr_slot=nbr_slot,
+                   owner=owner)
+        period = [float(mesh.period[k]) if mesh.periodic[k] else 0.0 for k in range(2)]
+        return cls(2, order, jac.shape[0], nu, nf, arr, period, shape=_lib.PCPF_SHAPE_TRIANGLE)
+
+    def solution_coords(self) -> np.ndarray:
+        """Physical coordinates [E, N_u, d] of the solution points of a triangle description
+        (x = xorig + J (r, s) at the reference points of pcpf_triangle_operators)."""
+        if self.c.shape != _lib.PCPF_SHAPE_TRIANGLE or "jac" not in self.keep:
+            raise ValueError("coordinates are given for triangle descriptions with jac")
+        upt = triangle_operators(self.order)["upt_ref"]
+        return self.keep["xorig"][:, None, :] + np.einsum("eik,uk->eui", self.keep["jac"], upt)
 
     def workspace_bytes(self, params, precision="fp64") -> int:
         lib = _lib.load()
@@ -230,8 +269,14 @@ class Solver:
     # -- the C ABI ------------------------------------------------------------------------
     def solution_coords(self) -> np.ndarray:
         if self.mesh is None:
-            raise ValueError("a context made from a dense description has no line-factor mesh")
+            return self.dense.solution_coords()
         return self.mesh.solution_coords()
+
+    @classmethod
+    def from_triangles(cls, mesh, order, params, precision="fp64", device="cuda"):
+        """A context on a triangle mesh (see DenseMeshArgs.from_triangles)."""
+        return cls.from_dense(DenseMeshArgs.from_triangles(mesh, order), params, precision,
+                              device)
 
     def set_state(self, phi, psi=None, t=0.0, step=0):
         self._phi_in = self._field(phi)

@@ -40,3 +40,23 @@ def test_stage_impl_words(d, p):
     # 96^3 p=4 FP64: 13.1 GB of algorithmic bytes per stage
     if (d, p) == (3, 4):
         assert abs(w["alg"] * 8 * 96 ** 3 / 1e9 - 13.095) < 1e-3
+
+
+@pytest.mark.parametrize("p", [3, 4, 5])
+def test_triangle_stage_words(p):
+    """Triangles: N_u = (p+1)(p+2)/2 and N_f = 3(p+1) in the same B_alg formula; the
+    launches' words counted from their arrays (each flux point has its own trace and flux
+    slot, the slot table is one 4-byte code per point)."""
+    nu, nf = (p + 1) * (p + 2) // 2, 3 * (p + 1)
+    w = bench.stage_words(2, p, "triangle")
+    assert w["alg"] == 10 * nu + 4 * nf
+    # grad_flux: u, own + partner traces, geometry (11), codes; writes P and the owned half
+    # of the common fluxes
+    gf = 2 * nu + 2 * 2 * nf + 11 + nf / 2 + 2 * nu + nf
+    # update: P, the flux of every point, geometry, codes, u_n, acc (3 of 4 stages);
+    # writes acc (3 of 4), the next stage input, the own traces
+    up = 2 * nu + 2 * nf + 11 + nf / 2 + 2 * nu + 1.5 * nu + 1.5 * nu + 2 * nu + 2 * nf
+    assert w["grad_flux"] == gf and w["update"] == up
+    if p == 4:
+        # 1024^2 cells, 2 097 152 triangles: FP64 B_alg per stage
+        assert abs(w["alg"] * 8 * 2 * 1024 ** 2 / 1e9 - (210 * 8 * 2 * 1024 ** 2) / 1e9) < 1e-9

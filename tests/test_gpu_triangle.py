@@ -203,3 +203,60 @@ def test_triangle_adjoint_and_bf16_refused():
     with pytest.raises(PcpfError) as ei:
         _solver(2, mesh, prm, "bf16")
     assert ei.value.status == _lib.PCPF_EUNSUPPORTED
+
+
+def _tri_sub_block(mesh, lo, m):
+    """The m x m cells from cell (lo) as a copy-boundary split mesh on the full mesh's own
+    grid lines, the full-mesh index of each of its triangles, and which of them lie off its
+    outer cell layer. A triangle's residual depends on its own state, its edge neighbours'
+    traces and the common fluxes their owners compute from their own gradients, which need
+    the owners' neighbours: every triangle within two edge hops, all inside the 3 x 3 cells
+    around its own; so the inner triangles of the sub-block reproduce the full mesh."""
+    n = mesh.shape[0]
+    planes = [np.asarray(mesh.planes[k])[lo[k]:lo[k] + m + 1] for k in range(2)]
+    sub = W.split_tri_mesh(m, periodic=False, planes=planes)
+    e = np.arange(sub.nelem)
+    cell = e // 2
+    ci, cj = cell % m, cell // m
+    full = 2 * ((ci + lo[0]) + n * (cj + lo[1])) + e % 2
+    inner = (ci >= 1) & (ci <= m - 2) & (cj >= 1) & (cj <= m - 2)
+    return sub, full, inner
+
+
+def test_full_size_sampled_residuals_triangles():
+    """The 1024^2-cell triangle mesh (2.1 M triangles, p = 4) in the launch configuration
+    the benchmark times: residuals of two 8 x 8-cell sub-blocks (across the circle's
+    interface, and at the high-index corner, where a second small circle gives an interface)
+    against the oracle <= 1e-12, and mass conservation of the whole residual."""
+    from paper_2006_10967_amd import Solver
+    cfg = W.config("T2")
+    mesh = cfg.mesh()
+    p, prm = cfg.order, cfg.params
+    s = Solver.from_triangles(mesh, p, prm)
+    x = s.solution_coords()
+    n = mesh.shape[0]
+    h = 1.0 / n
+    c2, r2 = np.array([1.0 - 4 * h, 1.0 - 4 * h]), 2.5 * h
+    dist = np.maximum(W.signed_distance_ball(x, cfg.centre, cfg.radius),
+                      W.signed_distance_ball(x, c2, r2))
+    phi = torch.tensor(W.tanh_profile(dist, prm.eps_w))
+    psi = torch.tensor(dist)
+    del x
+    gp, gs = s.residual(phi, psi, 0.3)
+    gp, gs = gp.cpu(), gs.cpu()
+    # the circle (0.5, 0.75), r = 0.15, crosses x = 0.35 at y = 0.75
+    for lo in ((int(0.35 * n) - 4, int(0.75 * n) - 4), (n - 8, n - 8)):
+        sub, full, inner = _tri_sub_block(mesh, lo, 8)
+        o = Oracle(2, p, sub, prm)
+        Rp, Rs = o.residual(phi[full], psi[full], 0.3)
+        sel = torch.as_tensor(inner)
+        assert float(phi[full][sel].min()) < 0.1 and float(phi[full][sel].max()) > 0.9, lo
+        assert _rel(gp[full][sel], Rp[sel]) <= TOL, (lo, _rel(gp[full][sel], Rp[sel]))
+        assert _rel(gs[full][sel], Rs[sel]) <= TOL, (lo, _rel(gs[full][sel], Rs[sel]))
+    assert int(full.max()) == mesh.nelem - 1
+    # sum |J| W R_phi = 0 on the periodic mesh (each common flux is shared by its two sides)
+    dm = s.dense
+    w = torch.as_tensor(dm.keep["detj"])[:, None] * torch.as_tensor(dm.keep["W"])[None, :]
+    tot = float((w * gp).sum())
+    scale = float((w * gp.abs()).sum())
+    assert abs(tot) <= 1e-13 * scale, (tot, scale)

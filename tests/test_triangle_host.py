@@ -72,3 +72,22 @@ def test_triangle_dense_description(p):
     # the BF16 form is built for tensor elements only; FP32 is
     assert _status(lambda: dm.workspace_bytes(prm, "bf16")) == _lib.PCPF_EUNSUPPORTED
     assert dm.workspace_bytes(prm, "fp32") > 0
+
+
+@pytest.mark.parametrize("p,n,kw", [(3, 4, dict(perturb=0.2)), (2, 3, dict(periodic=False)),
+                                    (4, 2, dict(periodic=(True, False)))])
+def test_binding_description_matches(p, n, kw):
+    """The binding's DenseMeshArgs.from_triangles gives the arrays of the tests' own
+    builder (owners by the oracle's switch vector) and the oracle's solution points."""
+    from oracle.mesh import pair_by_coordinates  # noqa: F401
+    from oracle.triangle import SWITCH, TriangleDiscretisation
+    mesh = W.split_tri_mesh(n, **kw)
+    dm = DenseMeshArgs.from_triangles(mesh, p)
+    _, arr = tri_dense(p, mesh)
+    for k in ("jinv", "detj", "fnorm", "fscale", "xorig", "nbr_slot", "owner", "M0", "Lift"):
+        assert np.array_equal(np.asarray(dm.keep[k]).reshape(-1),
+                              np.asarray(arr[k]).reshape(-1).astype(dm.keep[k].dtype)), k
+    from paper_2006_10967_amd.solver import TRI_SWITCH
+    assert np.array_equal(TRI_SWITCH, SWITCH)
+    disc = TriangleDiscretisation.from_mesh(TriangleOperators(p), mesh)
+    assert np.abs(dm.solution_coords() - disc.xs).max() < 1e-15

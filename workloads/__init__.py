@@ -227,6 +227,7 @@ class TriMesh:
     jac: np.ndarray           # [E, 2, 2]
     nbr: np.ndarray           # [E, 3, 2] int32: neighbour element and its edge
     period: np.ndarray
+    planes: tuple = None      # the grid lines of the split cells (x, y)
     element: str = "triangle"
 
     @property
@@ -249,57 +250,61 @@ class TriMesh:
 
 
 def split_tri_mesh(n: int, periodic=True, lo: float = 0.0, hi: float = 1.0,
-                   perturb: float = 0.0, seed: int = 1) -> TriMesh:
+                   perturb: float = 0.0, seed: int = 1, planes=None) -> TriMesh:
     """n x n grid cells of [lo, hi]^2, each split along its lower-left to upper-right
     diagonal into the triangles A = (c00, c10, c11) and B = (c00, c11, c01). Cell (i, j),
     triangle A = element 2 (i + n j), B = element 2 (i + n j) + 1. ``perturb`` shifts the
-    interior grid lines by U(-perturb h, perturb h) (seeded), keeping every triangle affine."""
-    rng = np.random.default_rng(seed)
-    planes = [perturbed_planes(n, perturb, rng, lo, hi) if perturb > 0 else uniform_planes(n, lo, hi)
-              for _ in range(2)]
+    interior grid lines by U(-perturb h, perturb h) (seeded), keeping every triangle affine.
+    ``planes`` (two arrays of n + 1 grid lines) replaces the generated ones."""
+    if planes is None:
+        rng = np.random.default_rng(seed)
+        planes = [perturbed_planes(n, perturb, rng, lo, hi) if perturb > 0
+                  else uniform_planes(n, lo, hi) for _ in range(2)]
+    else:
+        planes = [np.asarray(q, dtype=np.float64) for q in planes]
+        assert all(q.shape == (n + 1,) for q in planes)
+        lo, hi = float(planes[0][0]), float(planes[0][-1])
     per = periodic if isinstance(periodic, (list, tuple)) else (periodic, periodic)
     E = 2 * n * n
+    px, py = (np.asarray(q, dtype=np.float64) for q in planes)
+    jj, ii = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")   # cell (i, j), i fastest
+    ii, jj = ii.reshape(-1), jj.reshape(-1)
+    c00 = np.stack([px[ii], py[jj]], 1)
+    c10 = np.stack([px[ii + 1], py[jj]], 1)
+    c11 = np.stack([px[ii + 1], py[jj + 1]], 1)
+    c01 = np.stack([px[ii], py[jj + 1]], 1)
+    A, B = 2 * (ii + n * jj), 2 * (ii + n * jj) + 1
     x0 = np.zeros((E, 2))
     jac = np.zeros((E, 2, 2))
+    x0[A], jac[A] = c00, np.stack([c10 - c00, c11 - c00], 2)
+    x0[B], jac[B] = c00, np.stack([c11 - c00, c01 - c00], 2)
     nbr = np.full((E, 3, 2), -1, dtype=np.int32)
-    px, py = planes
 
     def cell(i, j):
+        # neighbouring cell index (wrapped in periodic directions), -1 outside the mesh
         if per[0]:
-            i %= n
+            i = i % n
         if per[1]:
-            j %= n
-        return (i, j) if (0 <= i < n and 0 <= j < n) else None
+            j = j % n
+        ok = (i >= 0) & (i < n) & (j >= 0) & (j < n)
+        return np.where(ok, i + n * j, -1)
 
-    for j in range(n):
-        for i in range(n):
-            c00 = np.array([px[i], py[j]])
-            c10 = np.array([px[i + 1], py[j]])
-            c11 = np.array([px[i + 1], py[j + 1]])
-            c01 = np.array([px[i], py[j + 1]])
-            a, b = 2 * (i + n * j), 2 * (i + n * j) + 1
-            x0[a], jac[a] = c00, np.stack([c10 - c00, c11 - c00], 1)
-            x0[b], jac[b] = c00, np.stack([c11 - c00, c01 - c00], 1)
-            # A: edge 0 (c00 -> c10) bottom, edge 1 (c10 -> c11) right, edge 2 (c11 -> c00)
-            # diagonal; B: edge 0 (c00 -> c11) diagonal, edge 1 (c11 -> c01) top, edge 2
-            # (c01 -> c00) left
-            nbr[a, 2] = (b, 0)
-            nbr[b, 0] = (a, 2)
-            down = cell(i, j - 1)
-            if down is not None:
-                nbr[a, 0] = (2 * (down[0] + n * down[1]) + 1, 1)
-            right = cell(i + 1, j)
-            if right is not None:
-                nbr[a, 1] = (2 * (right[0] + n * right[1]) + 1, 2)
-            up = cell(i, j + 1)
-            if up is not None:
-                nbr[b, 1] = (2 * (up[0] + n * up[1]), 0)
-            left = cell(i - 1, j)
-            if left is not None:
-                nbr[b, 2] = (2 * (left[0] + n * left[1]), 1)
-    period = np.array([hi - lo, hi - lo])
+    # A: edge 0 (c00 -> c10) bottom, edge 1 (c10 -> c11) right, edge 2 (c11 -> c00) diagonal;
+    # B: edge 0 (c00 -> c11) diagonal, edge 1 (c11 -> c01) top, edge 2 (c01 -> c00) left
+    def link(el, edge, other_cell, other_off, other_edge):
+        ok = other_cell >= 0
+        nbr[el[ok], edge, 0] = 2 * other_cell[ok] + other_off
+        nbr[el[ok], edge, 1] = other_edge
+
+    link(A, 2, (A // 2), 1, 0)
+    link(B, 0, (B // 2), 0, 2)
+    link(A, 0, cell(ii, jj - 1), 1, 1)
+    link(A, 1, cell(ii + 1, jj), 1, 2)
+    link(B, 1, cell(ii, jj + 1), 0, 0)
+    link(B, 2, cell(ii - 1, jj), 0, 1)
+    period = np.array([float(q[-1] - q[0]) for q in planes])
     return TriMesh(ndims=2, shape=(n, n), periodic=tuple(bool(x) for x in per), x0=x0,
-                   jac=jac, nbr=nbr, period=period)
+                   jac=jac, nbr=nbr, period=period, planes=tuple(planes))
 
 
 # --------------------------------------------------------------------------------------
@@ -430,6 +435,7 @@ class Config:
     description: str = ""
     length: float = 1.0          # the domain is [0, length]^d
     slot: Optional[tuple] = None  # (half width, top) of a slotted disc (§4.1)
+    element: str = "tensor"      # "tensor" (quads / hexes) or "triangle" (split n x n cells)
 
     @property
     def h(self) -> float:
@@ -437,17 +443,28 @@ class Config:
 
     @property
     def nelem(self) -> int:
-        return self.n ** self.ndims
+        return 2 * self.n * self.n if self.element == "triangle" else self.n ** self.ndims
 
     @property
     def nupts(self) -> int:
+        if self.element == "triangle":
+            return (self.order + 1) * (self.order + 2) // 2
         return (self.order + 1) ** self.ndims
+
+    @property
+    def nfpts(self) -> int:
+        if self.element == "triangle":
+            return 3 * (self.order + 1)
+        return 2 * self.ndims * (self.order + 1) ** (self.ndims - 1)
 
     @property
     def dof(self) -> int:
         return self.nelem * self.nupts
 
-    def mesh(self) -> BoxMesh:
+    def mesh(self):
+        if self.element == "triangle":
+            return split_tri_mesh(self.n, self.periodic, hi=self.length, perturb=self.perturb,
+                                  seed=self.perturb_seed)
         rng = np.random.default_rng(self.perturb_seed)
         planes = []
         for _ in range(self.ndims):
@@ -467,8 +484,11 @@ class Config:
         """Eq. initialCond at the points x[..., d] with beta = 1/(2 eps_w)."""
         return tanh_profile(self.distance(x), self.params.eps_w)
 
-    def hmin(self, mesh: Optional[BoxMesh] = None) -> float:
+    def hmin(self, mesh=None) -> float:
+        """Shortest grid spacing (quads / hexes), or shortest triangle leg."""
         mesh = mesh or self.mesh()
+        if self.element == "triangle":
+            return float(np.min(np.linalg.norm(mesh.jac, axis=1)))
         return float(min(np.min(np.diff(p)) for p in mesh.planes))
 
     def dt(self, mesh: Optional[BoxMesh] = None) -> float:
@@ -523,6 +543,29 @@ def _cfg_c5() -> Config:
                   centre=(0.35, 0.35, 0.35), cfl=0.03, steps=100, params=prm, vmax=2.0,
                   description="3D 96^3 hexes, interior planes perturbed +-20% h, p=4, "
                               "LeVeque deformation, 100 RK4 steps")
+
+
+def _vortex_tri(n: int, order: int) -> Config:
+    h = 1.0 / n
+    prm = default_params(2, order, h, dtau_coeff=0.008, vel_kind=VEL_SINGLE_VORTEX,
+                         vel_period=8.0)
+    return Config(f"vortex2d_tri{n}_p{order}", 2, order, n, centre=(0.5, 0.75), cfl=0.02,
+                  steps=100, params=prm, vmax=1.0, element="triangle",
+                  description=f"2D periodic unit square, {n}x{n} cells split into "
+                              f"{2 * n * n} triangles, p={order}, time-reversing single vortex "
+                              "T=8, circle r=0.15 at (0.5,0.75)")
+
+
+def _cfg_t1() -> Config:
+    """The single vortex on the split triangle mesh of 128 x 128 cells, p = 4 (the largest
+    of the triangle meshes of §4.2, at an order of its table)."""
+    return _vortex_tri(128, 4)
+
+
+def _cfg_t2() -> Config:
+    """The same flow on 1024 x 1024 cells (2.1 M triangles, 31 M DOF): a single-GPU-sized
+    triangle mesh whose state does not fit in the caches."""
+    return _vortex_tri(1024, 4)
 
 
 ROTATION_CFL = {2: 0.05, 3: 0.05, 4: 0.05, 5: 0.03}
@@ -597,7 +640,8 @@ def rotation_dt(cfg: Config) -> float:
     return 2.0 * math.pi / cfg.steps
 
 
-CONFIGS = {"C1": _cfg_c1, "C2": _cfg_c2, "C3": _cfg_c3, "C4": _cfg_c4, "C5": _cfg_c5}
+CONFIGS = {"C1": _cfg_c1, "C2": _cfg_c2, "C3": _cfg_c3, "C4": _cfg_c4, "C5": _cfg_c5,
+           "T1": _cfg_t1, "T2": _cfg_t2}
 
 
 def config(name: str) -> Config:
