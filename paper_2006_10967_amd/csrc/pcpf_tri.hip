@@ -277,6 +277,237 @@ __global__ __launch_bounds__(256) void k_tri_grad_flux(GFArgs<R> a) {
     }
 }
 
+// ------------------------------------------------------------------------------------
+// grad_flux on triangles, physical mode, on the matrix cores (p <= 4: N_u, N_f <= 16).
+//
+// Every operator product of the element is a dense (16 x 16) x (16 x 16) product of the
+// zero-padded operator with the values of 16 elements (one column per element): one wave
+// takes 16 elements and applies each operator with four 16x16x4 MFMAs (K = 16 in four
+// steps of 4), in the precision of the form (v_mfma_f64_16x16x4f64 / _f32_16x16x4f32).
+// A field of the 16 elements lives in registers: lane l = 16 g + c holds, in register r,
+// the value at row(g, r) of element c (row = point or flux-point index). The result rows
+// of the instruction come out in that same order, so the product of one operator is the
+// input of the next without any exchange between lanes, provided the operator's columns
+// are fed in the matching order: in step s, lane (m, g) supplies entry (m, row(g, s)).
+// row(g, r) = g + 4 r for the f64 instruction and 4 g + r for the f32 one (the result
+// layouts of the two instructions). The wave runs the whole of Steps 1-5 and the volume
+// part of Step 6 of its 16 elements without LDS or barriers; the pointwise work (fluxes,
+// common fluxes) is done by each lane on the points it holds.
+// ------------------------------------------------------------------------------------
+template <typename R>
+struct MfTile;
+template <>
+struct MfTile<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    __device__ static v4 mma(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ static constexpr int row(int g, int r) { return g + 4 * r; }
+};
+template <>
+struct MfTile<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    __device__ static v4 mma(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static constexpr int row(int g, int r) { return 4 * g + r; }
+};
+
+// tiles of 16 elements per wave; a grid-stride loop over tiles keeps the operators in
+// registers across the wave's tiles
+constexpr int TRI_MF_WAVES = 4;
+constexpr int64_t TRI_MF_MAX_BLOCKS = 2048;
+
+template <typename R, int P, bool NPHI>
+__global__ __launch_bounds__(64 * TRI_MF_WAVES) void k_tri_grad_flux_mf(GFArgs<R> a) {
+    using S = TriShape<P>;
+    using T = MfTile<R>;
+    using v4 = typename T::v4;
+    using M = Math<R>;
+    constexpr int NU = S::NU, NF = S::NF, G = S::G;
+    constexpr int NV = NPHI ? 0 : 1;
+    static_assert(NU <= 16 && NF <= 16, "one 16 x 16 tile per operator");
+    const int lane = threadIdx.x & 63;
+    const int c = lane & 15, g = lane >> 4;
+
+    // A operands in LDS, lane (m, g) of step s holding Op[m][row(g, s)] (operator o at
+    // s_op[o][s][lane]: conflict-free reads), and the per-lane constants of the rows a lane
+    // holds (reference point coordinates, flux point coordinates and normals). Kept in LDS
+    // and read where used, they leave the registers to the 16-element fields.
+    enum { O_M0, O_D0, O_D1, O_L };
+    enum { C_UR0, C_UR1, C_FR0, C_FR1, C_NH0, C_NH1 };
+    __shared__ R s_op[4][4][64];
+    __shared__ R s_cst[6][4][64];
+    for (int t = threadIdx.x; t < 4 * 4 * 64; t += 64 * TRI_MF_WAVES) {
+        const int o = t >> 8, st = (t >> 6) & 3, l = t & 63;
+        const int m = l & 15, k = MfTile<R>::row(l >> 4, st);
+        R val = R(0);
+        if (o == O_M0) val = (m < NF && k < NU) ? a.ops[S::OM0 + m * NU + k] : R(0);
+        else if (o == O_D0) val = (m < NU && k < NU) ? a.ops[S::OD0 + m * NU + k] : R(0);
+        else if (o == O_D1) val = (m < NU && k < NU) ? a.ops[S::OD1 + m * NU + k] : R(0);
+        else val = (m < NU && k < NF) ? a.ops[S::OL + m * NF + k] : R(0);
+        s_op[o][st][l] = val;
+    }
+    for (int t = threadIdx.x; t < 4 * 64; t += 64 * TRI_MF_WAVES) {
+        const int r = t >> 6, l = t & 63;
+        const int j = MfTile<R>::row(l >> 4, r);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            s_cst[C_UR0 + i][r][l] = j < NU ? a.ops[S::OUR + 2 * j + i] : R(0);
+            s_cst[C_FR0 + i][r][l] = j < NF ? a.ops[S::OFR + 2 * j + i] : R(0);
+            s_cst[C_NH0 + i][r][l] = j < NF ? a.ops[S::ONH + 2 * j + i] : R(0);
+        }
+    }
+    __syncthreads();
+    auto apply = [&](int o, const v4& x, v4 acc) {
+#pragma unroll
+        for (int st = 0; st < 4; ++st) acc = T::mma(s_op[o][st][lane], x[st], acc);
+        return acc;
+    };
+    auto cst = [&](int which, int r) { return s_cst[which][r][lane]; };
+
+    const int64_t ntiles = (a.E + 15) / 16;
+    const int64_t wstride = (int64_t)gridDim.x * TRI_MF_WAVES;
+    for (int64_t tile = (int64_t)blockIdx.x * TRI_MF_WAVES + (threadIdx.x >> 6); tile < ntiles;
+         tile += wstride) {
+        // keeps the LDS reads of the operators and constants inside the loop
+        asm volatile("" ::: "memory");
+        const int64_t e = tile * 16 + c;
+        const bool ev = e < a.E;
+        const uint32_t ue = (uint32_t)(ev ? e : 0);
+        // ---- loads: state, slot codes, partner traces, geometry ----------------------------
+        v4 u[2];
+        int code[4];
+        R ptr[2][4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = T::row(g, r);
+#pragma unroll
+            for (int v = 0; v < 2; ++v) u[v][r] = (ev && j < NU) ? gld(a.u[v], ue * NU + j) : R(0);
+            code[r] = (ev && j < NF) ? gld(a.nbr, ue * NF + j) : -2;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int v = 0; v < 2; ++v)
+                ptr[v][r] = code[r] >= 0 ? gld(a.Tp[v], (uint32_t)(code[r] >> 1)) : R(0);
+        R gg[G];
+#pragma unroll
+        for (int q = 0; q < G; ++q) gg[q] = ev ? gld(a.geo, ue * G + q) : (q == 10 ? R(1) : R(0));
+        const R det = gg[10];
+        const R* Ji = gg + 6;                       // Jinv[k][i] = Ji[k * 2 + i]
+
+        // ---- Steps 1-3: own traces, LDG jumps, corrected gradient --------------------------
+        const v4 z = {R(0), R(0), R(0), R(0)};
+        v4 tf[2], q[2][2];
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            tf[v] = apply(O_M0, u[v], z);
+            v4 qt[2];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                v4 jn;
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    jn[r] = (code[r] >= 0 && (code[r] & 1)) ? cst(C_NH0 + k, r) * (ptr[v][r] - tf[v][r]) : R(0);
+                qt[k] = apply(k == 0 ? O_D0 : O_D1, u[v], z);
+                qt[k] = apply(O_L, jn, qt[k]);
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) q[v][i][r] = Ji[0 * 2 + i] * qt[0][r] + Ji[1 * 2 + i] * qt[1][r];
+        }
+
+        // ---- Step 5: common normal flux at the owned and boundary flux points ------------
+        {
+            v4 qf[2][2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                qf[0][i] = apply(O_M0, q[0][i], z);
+                if constexpr (!NPHI) qf[1][i] = apply(O_M0, q[1][i], z);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (!(code[r] == -1 || (code[r] >= 0 && (code[r] & 1)))) continue;
+                const R n0 = cst(C_NH0, r), n1 = cst(C_NH1, r);
+                R nr[2];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) nr[i] = Ji[0 * 2 + i] * n0 + Ji[1 * 2 + i] * n1;
+                const R rmag = M::rsqrt_(nr[0] * nr[0] + nr[1] * nr[1]);
+                nr[0] *= rmag;
+                nr[1] *= rmag;
+                R x[2], vel[2];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) x[i] = gg[i] + gg[2 + i * 2 + 0] * cst(C_FR0, r) + gg[2 + i * 2 + 1] * cst(C_FR1, r);
+                velocity<R, 2>(a.ph, x, vel);
+                const R v2 = vel[0] * vel[0] + vel[1] * vel[1];
+                const R vn = vel[0] * nr[0] + vel[1] * nr[1];
+                const R mm = max_sqrt(v2, a.ph.gamma);
+                const R qn0 = qf[0][0][r] * nr[0] + qf[0][1][r] * nr[1];
+                const R qnn = qf[NV][0][r] * nr[0] + qf[NV][1][r] * nr[1];
+                const R g2 = qf[NV][0][r] * qf[NV][0][r] + qf[NV][1][r] * qf[NV][1][r];
+                const R rn = M::rsqrt_(g2 + a.ph.delta_n * a.ph.delta_n);
+                const R pL = tf[0][r], sL = tf[1][r];
+                const R pR = code[r] >= 0 ? ptr[0][r] : pL, sR = code[r] >= 0 ? ptr[1][r] : sL;
+                const R fvn = mm * (a.ph.eps * qn0 - a.ph.gamma * pL * (R(1) - pL) * qnn * rn);
+                const R F0 = R(0.5) * (pL + pR) * vn - fvn + a.ph.tau * (pL - pR);
+                const R F1 = R(0.5) * (sL + sR) * vn + a.ph.tau * (sL - sR);
+                const uint32_t slot = ue * NF + T::row(g, r);
+                gst(a.Fp[0], slot, F0);
+                gst(a.Fp[1], slot, F1);
+            }
+        }
+
+        // ---- Step 4: transformed fluxes at the solution points -----------------------------
+        v4 ft[2][2];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const bool pv = T::row(g, r) < NU;
+            R x[2], vel[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) x[i] = gg[i] + gg[2 + i * 2 + 0] * cst(C_UR0, r) + gg[2 + i * 2 + 1] * cst(C_UR1, r);
+            velocity<R, 2>(a.ph, x, vel);
+            const R v2 = vel[0] * vel[0] + vel[1] * vel[1];
+            const R g2 = q[NV][0][r] * q[NV][0][r] + q[NV][1][r] * q[NV][1][r];
+            const R mm = max_sqrt(v2, a.ph.gamma);
+            const R rn = M::rsqrt_(g2 + a.ph.delta_n * a.ph.delta_n);
+            const R phi = u[0][r], psi = u[1][r];
+            const R sharp = a.ph.gamma * phi * (R(1) - phi) * rn;
+            R f0[2], f1[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const R fvis = mm * (a.ph.eps * q[0][i][r] - sharp * q[NV][i][r]);
+                f0[i] = phi * vel[i] - fvis;
+                f1[i] = psi * vel[i];
+            }
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                ft[0][k][r] = pv ? det * (Ji[k * 2 + 0] * f0[0] + Ji[k * 2 + 1] * f0[1]) : R(0);
+                ft[1][k][r] = pv ? det * (Ji[k * 2 + 0] * f1[0] + Ji[k * 2 + 1] * f1[1]) : R(0);
+            }
+        }
+
+        // ---- Step 6, volume part: P = D_0 f~_0 + D_1 f~_1 - Lift (nhat . M0 f~) ------------
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            const v4 a0 = apply(O_M0, ft[v][0], z);
+            const v4 a1 = apply(O_M0, ft[v][1], z);
+            v4 mfp;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) mfp[r] = -(cst(C_NH0, r) * a0[r] + cst(C_NH1, r) * a1[r]);
+            v4 pacc = apply(O_D0, ft[v][0], z);
+            pacc = apply(O_D1, ft[v][1], pacc);
+            pacc = apply(O_L, mfp, pacc);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = T::row(g, r);
+                if (ev && j < NU) gst(a.P[v], ue * NU + j, pacc[r]);
+            }
+        }
+    }
+}
+
 // update on triangles: Step 6 face part and the RK4 combine, then the own traces of the next
 // stage input (UP_RK), or the residual (UP_RESID).
 template <typename R, int P, int V, int KIND>
@@ -433,8 +664,16 @@ struct TriImpl {
     static unsigned grid(int64_t E) { return (unsigned)((E + S::EPB - 1) / S::EPB); }
     template <int MODE, bool NPHI>
     static void gf(const GFArgs<R>& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-        hipExtLaunchKernelGGL((k_tri_grad_flux<R, P, MODE, NPHI>), dim3(grid(a.E)), dim3(256), 0,
-                              st, e0, e1, 0, a);
+        if constexpr (MODE == GF_PHYS && P <= 4) {
+            const int64_t waves = (a.E + 15) / 16;
+            const int64_t blocks = (waves + TRI_MF_WAVES - 1) / TRI_MF_WAVES;
+            hipExtLaunchKernelGGL((k_tri_grad_flux_mf<R, P, NPHI>),
+                                  dim3((unsigned)(blocks < TRI_MF_MAX_BLOCKS ? blocks : TRI_MF_MAX_BLOCKS)),
+                                  dim3(64 * TRI_MF_WAVES), 0, st, e0, e1, 0, a);
+        } else {
+            hipExtLaunchKernelGGL((k_tri_grad_flux<R, P, MODE, NPHI>), dim3(grid(a.E)), dim3(256),
+                                  0, st, e0, e1, 0, a);
+        }
     }
     static void grad_flux(int mode, int nvar, const GFArgs<R>& a, hipStream_t st, hipEvent_t e0,
                           hipEvent_t e1) {
