@@ -101,7 +101,7 @@ def stage_words(d, p, element="tensor"):
 def kernel_source_hash():
     h = hashlib.sha256()
     for f in ("pcpf_kernels.hip", "pcpf_kernels_impl.h", "pcpf_internal.h", "pcpf_device.h",
-              "pcpf_mfma.h"):
+              "pcpf_mfma.h", "pcpf_tri.hip", "pcpf_tri.h"):
         with open(os.path.join(ROOT, "paper_2006_10967_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
