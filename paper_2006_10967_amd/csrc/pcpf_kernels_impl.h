@@ -60,8 +60,9 @@ using namespace dev;
 
 // MF: the line operators of the gradient (DT, and lp for the own traces) and of the
 // divergence (DH) run on the matrix cores with bf16 operands and fp32 accumulation (the
-// BF16 form; R = float); the pointwise flux math, the face interpolations and the sensor
-// stay in fp32 on the vector units.
+// BF16 form; R = float), each line taken as deviations from its mean with hi / lo bf16
+// splits of operator and data (three MFMAs per product); the pointwise flux math, the face
+// interpolations and the sensor stay in fp32 on the vector units.
 // NPHI (physical mode): the interface normal of the sharpening flux comes from phi instead
 // of psi, the unpreconditioned conservative phase field of §2.
 template <typename R, int D, int P, int MODE, bool AXIS, bool MF = false, bool NPHI = false>
@@ -328,7 +329,7 @@ void k_grad_flux(GFArgs<R> a) {
             }
         };
         if constexpr (MF) {
-            const bf16x4 aG = mfma_rows<N + 1, N>(
+            const RowsSplit aG = mfma_rows_split<N + 1, N>(
                 [&](int i, int k) { return i < N ? s_ops[op_dt(N) + i * N + k] : s_ops[op_lp(N) + k]; },
                 lane);
             mf_lines([&](auto KC, bool ok, int el, int t, int item) {
@@ -337,7 +338,7 @@ void k_grad_flux(GFArgs<R> a) {
                 const int base = el * NU + face_base<D, N>(K, t);
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
-                    const f32x4 r = mfma_lines<N>(aG, s_u[v], ok, base, SK, lane);
+                    const f32x4 r = mfma_lines_split<N>(aG, s_u[v], ok, base, SK, lane);
 #pragma unroll
                     for (int jj = 0; jj < 4; ++jj) {
                         const int row = 4 * (lane >> 4) + jj;
@@ -645,7 +646,7 @@ void k_grad_flux(GFArgs<R> a) {
             // DH along the lines of every direction on the matrix cores, in place (the
             // direction-K field of s_f is touched only by the direction-K lines), then the
             // directions summed per point
-            const bf16x4 aH = mfma_rows<N, N>(
+            const RowsSplit aH = mfma_rows_split<N, N>(
                 [&](int i, int k) { return s_ops[op_dh(N) + i * N + k]; }, lane);
             mf_lines([&](auto KC, bool ok, int el, int t, int item) {
                 (void)item;
@@ -655,7 +656,7 @@ void k_grad_flux(GFArgs<R> a) {
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
                     R* fk = &s_f[(v * D + K) * XST];
-                    const f32x4 r = mfma_lines<N>(aH, fk, ok, base, SK, lane);
+                    const f32x4 r = mfma_lines_split<N>(aH, fk, ok, base, SK, lane);
 #pragma unroll
                     for (int jj = 0; jj < 4; ++jj) {
                         const int row = 4 * (lane >> 4) + jj;
