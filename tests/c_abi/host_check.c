@@ -3,7 +3,12 @@
  * (weights sum to the reference length, the derivative of a constant is 0 and of xi is 1,
  * the end interpolations reproduce xi at +-1, the DG correction divergences equal
  * l(+-1)/w), the solution coordinates of an affine box element, the workspace size query
- * and the error path. Prints one line per check and returns the number of failures. */
+ * and the error path; then the order-2 triangle operators against facts of the triangle
+ * (weights sum to the area 1/2, interpolation and derivatives exact on r and s, the
+ * lifting's weighted column sums are the edge quadrature weights, whose total is the
+ * perimeter 2 + sqrt 2) and the dense description of a one-cell periodic split mesh (two
+ * triangles) accepted, and refused with two owners on a pair. Prints one line per check
+ * and returns the number of failures. */
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
@@ -77,5 +82,80 @@ int main(void) {
     check(pcpf_workspace_bytes(&m, &prm, &nb) == PCPF_EINVAL &&
               strlen(pcpf_last_error(NULL)) > 0,
           "invalid parameters refused with a message");
+    prm.kappa = 5.0;
+
+    /* the order-2 triangle */
+    enum { TP = 2, TN = TP + 1, TU = (TP + 1) * (TP + 2) / 2, TF = 3 * TN };
+    double upt[TU * 2], fpt[TF * 2], M0[TF * TU], TD[2 * TU * TU], LN[2 * TU * TF];
+    double L[TU * TF], TV[TU * TU], TW[TU], NH[TF * 2];
+    uint8_t top[TU];
+    check(pcpf_triangle_operators(TP, upt, fpt, M0, TD, LN, L, TV, top, TW, NH) == PCPF_OK,
+          "triangle operators");
+    double area = 0.0, wi = 0.0, wd = 0.0, perim = 0.0;
+    int ntop = 0;
+    for (int i = 0; i < TU; ++i) {
+        area += TW[i];
+        ntop += top[i] != 0;
+        for (int k = 0; k < 2; ++k) {
+            double dr = 0.0, ds = 0.0;
+            for (int b = 0; b < TU; ++b) {
+                dr += TD[(k * TU + i) * TU + b] * upt[2 * b];
+                ds += TD[(k * TU + i) * TU + b] * upt[2 * b + 1];
+            }
+            wd = fmax(wd, fabs(dr - (k == 0)) + fabs(ds - (k == 1)));
+        }
+    }
+    for (int f = 0; f < TF; ++f) {
+        double r = 0.0, sv = 0.0, col = 0.0;
+        for (int b = 0; b < TU; ++b) {
+            r += M0[f * TU + b] * upt[2 * b];
+            sv += M0[f * TU + b] * upt[2 * b + 1];
+            col += TW[b] * L[b * TF + f];
+        }
+        wi = fmax(wi, fabs(r - fpt[2 * f]) + fabs(sv - fpt[2 * f + 1]));
+        perim += col;
+    }
+    check(fabs(area - 0.5) < 1e-14 && ntop == TP + 1, "triangle weights and top modes");
+    check(wi < 1e-14 && wd < 1e-13, "triangle interpolation and derivatives exact on r, s");
+    check(fabs(perim - (2.0 + sqrt(2.0))) < 1e-12, "triangle lifting: edge weights");
+
+    /* one periodic cell of [0, 1]^2 split along its diagonal: A = (c00, c10, c11),
+     * B = (c00, c11, c01); A's edges 0, 1, 2 (bottom, right, diagonal) meet B's edges 1
+     * (top, across the period), 2 (left, across the period) and 0 (diagonal), each walked
+     * the other way */
+    const double tjac[2][4] = {{1.0, 1.0, 0.0, 1.0}, {1.0, 0.0, 1.0, 1.0}};
+    const double tjinv[2][4] = {{1.0, -1.0, 0.0, 1.0}, {1.0, 0.0, -1.0, 1.0}};
+    const double tdet[2] = {1.0, 1.0}, txo[4] = {0.0, 0.0, 0.0, 0.0};
+    const int pair_edge[2][3] = {{1, 2, 0}, {2, 0, 1}};
+    double tfn[2 * TF * 2], tfs[2 * TF];
+    int32_t slot[2 * TF];
+    uint8_t own[2 * TF];
+    for (int e = 0; e < 2; ++e)
+        for (int f = 0; f < TF; ++f) {
+            const int edge = f / TN, t = f % TN;
+            double nr[2];
+            for (int i = 0; i < 2; ++i)
+                nr[i] = tjinv[e][0 * 2 + i] * NH[2 * f] + tjinv[e][1 * 2 + i] * NH[2 * f + 1];
+            const double mag = sqrt(nr[0] * nr[0] + nr[1] * nr[1]);
+            tfn[(e * TF + f) * 2] = nr[0] / mag;
+            tfn[(e * TF + f) * 2 + 1] = nr[1] / mag;
+            tfs[e * TF + f] = tdet[e] * mag;
+            slot[e * TF + f] = (1 - e) * TF + pair_edge[e][edge] * TN + (TN - 1 - t);
+            own[e * TF + f] = (nr[0] + nr[1] / sqrt(2.0)) > 0.0;
+        }
+    pcpf_dense_mesh dm;
+    memset(&dm, 0, sizeof dm);
+    dm.ndims = 2; dm.order = TP; dm.shape = PCPF_SHAPE_TRIANGLE; dm.nupts = TU; dm.nfpts = TF;
+    dm.nelem = 2;
+    dm.M0 = M0; dm.D = TD; dm.LiftN = LN; dm.Lift = L; dm.Vinv = TV; dm.topmask = top;
+    dm.W = TW; dm.ref_fnorm = NH; dm.jinv = &tjinv[0][0]; dm.detj = tdet; dm.fnorm = tfn;
+    dm.fscale = tfs; dm.xorig = txo; dm.jac = &tjac[0][0]; dm.nbr_slot = slot; dm.owner = own;
+    dm.period[0] = dm.period[1] = 1.0;
+    check(pcpf_workspace_bytes_dense(&dm, &prm, &nb) == PCPF_OK && nb >= 5 * 2 * 2 * TU * 8,
+          "dense triangle description accepted");
+    own[slot[0]] = own[0];
+    check(pcpf_workspace_bytes_dense(&dm, &prm, &nb) == PCPF_EINVAL &&
+              strlen(pcpf_last_error(NULL)) > 0,
+          "two owners on a flux-point pair refused");
     return fails;
 }

@@ -23,4 +23,4 @@ def test_host_calls_from_c(tmp_path):
     r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
     print(r.stdout)
     assert r.returncode == 0, r.stdout + r.stderr
-    assert r.stdout.count("ok  ") == 10
+    assert r.stdout.count("ok  ") == 16
