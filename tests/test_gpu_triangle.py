@@ -260,3 +260,56 @@ def test_full_size_sampled_residuals_triangles():
     tot = float((w * gp).sum())
     scale = float((w * gp.abs()).sum())
     assert abs(tot) <= 1e-13 * scale, (tot, scale)
+
+
+TRI_RMS_CASES = [
+    # (id, p, n, eps_w of the IC, sign mode): the RMS stop rule ends after 5, 10, 13 and 18
+    # iterations, every iteration's RMS at least 3.8e-3 from 1/2 (oracle), so rounding
+    # cannot move the decision
+    ("p2_psi0", 2, 6, 0.05, W.SGN_PSI0),
+    ("p2_current", 2, 6, 0.04, W.SGN_CURRENT),
+    ("p3_psi0", 3, 6, 0.04, W.SGN_PSI0),
+    ("p2_current_18", 2, 8, 0.03, W.SGN_CURRENT),
+]
+
+
+@pytest.mark.parametrize("cid,p,n,ew,sgn", TRI_RMS_CASES, ids=[c[0] for c in TRI_RMS_CASES])
+def test_triangle_rms_stop_rule_parity(cid, p, n, ew, sgn):
+    """The printed stop rule (and, in two cases, the printed sign) on triangles: the same
+    iteration count as the oracle, its last RMS to 1e-10, psi to 1e-12."""
+    mesh, prm = _case(p, n, dict(), dict(vel_u0=(0.6, 0.3)), stop_mode=W.STOP_RMS,
+                      precond_iters=20, sgn_mode=sgn)
+    o = Oracle(2, p, mesh, prm)
+    s = _solver(p, mesh, prm)
+    phi = torch.tensor(W.ic_phi(o.coords(), (0.5, 0.5), 0.3, ew))
+    psi_o, _ = o.precondition(phi)
+    s.set_state(phi)
+    s.precondition()
+    k, rms = s.precond_info()
+    _, psi_g, _, _ = s.get_state()
+    assert 1 < o.last_iters < 20
+    assert k == o.last_iters, (k, o.last_iters)
+    assert abs(rms - o.last_rms) <= 1e-10 * o.last_rms
+    assert _rel(psi_g, psi_o) <= TOL
+
+
+@pytest.mark.parametrize("reset", [W.RESET_LINEAR, W.RESET_LOGIT], ids=["linear", "logit"])
+def test_triangle_printed_forms_and_logit_trajectory(reset):
+    """Printed sign and RMS stop rule, with the linear or the logit reset, over 40 steps
+    with resets every 16 on a perturbed p = 3 mesh under the single vortex: phi and psi
+    match the oracle to 1e-10 (the stop decisions at the three resets are at least 3.5e-3
+    from the threshold in the oracle run)."""
+    mesh, prm = _case(3, 5, dict(perturb=0.1, seed=3), dict(vel_kind=W.VEL_SINGLE_VORTEX),
+                      stop_mode=W.STOP_RMS, precond_iters=20, sgn_mode=W.SGN_CURRENT,
+                      reset_mode=reset, reset_every=16)
+    o = Oracle(2, 3, mesh, prm)
+    s = _solver(3, mesh, prm)
+    phi0 = torch.tensor(W.ic_phi(o.coords(), np.array([0.45, 0.5]), 0.25, 0.06))
+    dt = 0.05 / (5 * 7)
+    phi_o, psi_o, _ = o.run(phi0, None, 0.0, dt, 40)
+    s.set_state(phi0)
+    s.step(dt, 40)
+    phi_g, psi_g, _, _ = s.get_state()
+    assert s.precond_info()[0] == o.last_iters
+    assert _rel(phi_g, phi_o) <= 1e-10
+    assert _rel(psi_g, psi_o) <= 1e-10
