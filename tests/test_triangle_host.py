@@ -91,3 +91,25 @@ def test_binding_description_matches(p, n, kw):
     assert np.array_equal(TRI_SWITCH, SWITCH)
     disc = TriangleDiscretisation.from_mesh(TriangleOperators(p), mesh)
     assert np.abs(dm.solution_coords() - disc.xs).max() < 1e-15
+
+
+def test_triangle_description_sizes_refused():
+    """No elements, or more flux points than 32-bit slot codes address (E N_f >= 2^30),
+    are refused with EINVAL before any array is read."""
+    p = 3
+    mesh = W.split_tri_mesh(2)
+    prm = W.default_params(2, p, 0.5)
+    dm, arr = tri_dense(p, mesh)
+    nu, nf = arr["W"].size, arr["M0"].shape[0]
+    for nelem in (0, (1 << 30) // nf + 1):
+        bad = DenseMeshArgs(2, p, nelem, nu, nf, arr, [1.0, 1.0],
+                            shape=_lib.PCPF_SHAPE_TRIANGLE)
+        assert _status(lambda: bad.workspace_bytes(prm)) == _lib.PCPF_EINVAL, nelem
+    # point counts that are not those of the order-p triangle
+    bad = DenseMeshArgs(2, p, mesh.nelem, nu + 1, nf, arr, [1.0, 1.0],
+                        shape=_lib.PCPF_SHAPE_TRIANGLE)
+    assert _status(lambda: bad.workspace_bytes(prm)) == _lib.PCPF_EINVAL
+    # orders outside the built range
+    bad = DenseMeshArgs(2, 6, mesh.nelem, 28, 21, arr, [1.0, 1.0],
+                        shape=_lib.PCPF_SHAPE_TRIANGLE)
+    assert _status(lambda: bad.workspace_bytes(prm)) == _lib.PCPF_EUNSUPPORTED
