@@ -52,6 +52,20 @@ template <typename T>
 __device__ __forceinline__ void gst(T* base, uint32_t i, T v) {
     *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (uint32_t)sizeof(T)) = v;
 }
+// The same with the non-temporal hint (NT = true): for arrays a launch reads or writes once
+// and that are too large to be found in the caches by the next launch.
+template <bool NT, typename T>
+__device__ __forceinline__ T gld_s(const T* base, uint32_t i) {
+    const T* p = reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + i * (uint32_t)sizeof(T));
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void gst_s(T* base, uint32_t i, T v) {
+    T* p = reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (uint32_t)sizeof(T));
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
 
 // Element chunk of this block. Consecutive workgroups are placed round-robin on the 8
 // XCDs. When a state plane is small enough for the chunks of one XCD to stay in its L2 and

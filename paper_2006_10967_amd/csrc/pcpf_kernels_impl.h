@@ -744,7 +744,9 @@ void k_grad_flux(GFArgs<R> a) {
 // blocks' load, LDS and arithmetic phases better (96^3 p4: 2382 us at 4, 2141 at 5, 2066 at
 // 6; 64^3 p3: 281 at 5, 268 at 6, 257 at 7). The float32 form fits 8 waves anyway.
 constexpr int lines_waves(int p) { return p <= 3 ? 7 : 6; }
-template <typename R, int D, int P, bool AXIS, bool NPHI>
+// STREAM: the state planes exceed the caches; the state loads and the P stores (each value
+// read or written once per launch) go with the non-temporal hint.
+template <typename R, int D, int P, bool AXIS, bool NPHI, bool STREAM>
 __global__ __launch_bounds__((Shape<D, P>::NT))
 __attribute__((amdgpu_waves_per_eu(lines_waves(P))))
 void k_grad_flux_lines(GFArgs<R> a) {
@@ -799,7 +801,10 @@ void k_grad_flux_lines(GFArgs<R> a) {
 #pragma unroll
     for (int v = 0; v < V; ++v)
 #pragma unroll
-        for (int j = 0; j < I_U; ++j) r_u[v][j] = gld_in(a.u[v] + e0 * NU, tid + j * NT, nel * NU);
+        for (int j = 0; j < I_U; ++j) {
+            const int i = tid + j * NT;
+            r_u[v][j] = gld_s<STREAM>(a.u[v] + e0 * NU, (uint32_t)(i < nel * NU ? i : nel * NU - 1));
+        }
     R r_ji[D], r_det = R(1);
     const bool fn_thread = !AXIS && tid < nel * D;
     if constexpr (!AXIS) {
@@ -1227,7 +1232,7 @@ void k_grad_flux_lines(GFArgs<R> a) {
             R acc = R(0);
 #pragma unroll
             for (int k = 0; k < D; ++k) acc += s_x[(v * D + k) * XST + tid];
-            gst(a.P[v] + e0 * NU, tid, acc);
+            gst_s<STREAM>(a.P[v] + e0 * NU, (uint32_t)tid, acc);
         }
     }
 }
@@ -1294,7 +1299,10 @@ __device__ __forceinline__ void push_traces(R* const* Tp, const R* lm, const R* 
 //   or the classic RK4 registers are advanced and the - face traces of the next stage
 //   input are written (UP_RK).
 // ------------------------------------------------------------------------------------
-template <typename R, int D, int P, int V, int KIND>
+// STREAM: the state planes are larger than the caches (more than XCD_MAP_MAX_PLANE_BYTES
+// each); the registers read and written once per stage (P, u_n, the accumulator, the next
+// stage input) then go with the non-temporal hint.
+template <typename R, int D, int P, int V, int KIND, bool STREAM>
 __global__ __launch_bounds__((Shape<D, P, update_tpb(D, P)>::NT)) void k_update(UPArgs<R> a) {
     using S = Shape<D, P, update_tpb(D, P)>;
     constexpr int N = S::N, NU = S::NU, NFA = S::NFA, EPB = S::EPB, NT = S::NT, G = S::GEO;
@@ -1324,10 +1332,10 @@ __global__ __launch_bounds__((Shape<D, P, update_tpb(D, P)>::NT)) void k_update(
     const R det = gld(a.geo + e0 * G, (tp / NU) * G + D + 2 * D * D);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-        rP[v] = gld(a.P[v] + so, tp);
+        rP[v] = gld_s<STREAM>(a.P[v] + so, (uint32_t)tp);
         if constexpr (KIND == UP_RK) {
-            rU[v] = gld(a.un[v] + so, tp);
-            rA[v] = a.first ? R(0) : gld(a.acc[v] + so, tp);
+            rU[v] = gld_s<STREAM>(a.un[v] + so, (uint32_t)tp);
+            rA[v] = a.first ? R(0) : gld_s<STREAM>(a.acc[v] + so, (uint32_t)tp);
         }
     }
     R r_c[3];
@@ -1402,20 +1410,20 @@ __global__ __launch_bounds__((Shape<D, P, update_tpb(D, P)>::NT)) void k_update(
             }
             const R res = -acc * rdet;
             if constexpr (KIND == UP_RESID) {
-                gst(a.res[v] + so, tid, res);
+                gst_s<STREAM>(a.res[v] + so, (uint32_t)tid, res);
             } else {
                 // explicit fused multiply-adds: one rounding per register update, whatever
                 // the surrounding code lets the compiler contract
                 using M = Math<R>;
                 R nx;
                 if (!a.last) {
-                    gst(a.acc[v] + so, tid, M::fma_(a.bcoef, res, rA[v]));
+                    gst_s<STREAM>(a.acc[v] + so, (uint32_t)tid, M::fma_(a.bcoef, res, rA[v]));
                     nx = M::fma_(a.ccoef, res, rU[v]);
-                    gst(a.us[v] + so, tid, nx);
+                    gst_s<STREAM>(a.us[v] + so, (uint32_t)tid, nx);
                 } else {
                     nx = M::fma_(a.ccoef, M::fma_(a.bcoef, res, rA[v]), rU[v]);
-                    gst(a.un[v] + so, tid, nx);
-                    if (a.uo[0]) gst(a.uo[v] + so, tid, nx);
+                    gst_s<STREAM>(a.un[v] + so, (uint32_t)tid, nx);
+                    if (a.uo[0]) gst_s<STREAM>(a.uo[v] + so, (uint32_t)tid, nx);
                 }
                 s_u[v][tid] = nx;
                 const R lim = (v == 0 && V == 2) ? R(10) : R(1e30);
@@ -1524,8 +1532,12 @@ struct Impl {
         // the line kernel: 3D, and 2D in FP32 (128^2 p4: FP32 grad_flux 6.9 -> 6.2 us; FP64
         // 9.8 against 10.0 us with the point kernel)
         if constexpr (MODE == GF_PHYS && !MF && (D == 3 || sizeof(R) == 4)) {
-            hipExtLaunchKernelGGL((k_grad_flux_lines<R, D, P, AXIS, NPHI>), dim3(grid(a.E)),
-                                  dim3(S::NT), 0, st, e0, e1, 0, a);
+            if (a.E * S::NU * (int64_t)sizeof(R) > XCD_MAP_MAX_PLANE_BYTES)
+                hipExtLaunchKernelGGL((k_grad_flux_lines<R, D, P, AXIS, NPHI, true>), dim3(grid(a.E)),
+                                      dim3(S::NT), 0, st, e0, e1, 0, a);
+            else
+                hipExtLaunchKernelGGL((k_grad_flux_lines<R, D, P, AXIS, NPHI, false>), dim3(grid(a.E)),
+                                      dim3(S::NT), 0, st, e0, e1, 0, a);
         } else {
             hipExtLaunchKernelGGL((k_grad_flux<R, D, P, MODE, AXIS, MF, NPHI>), dim3(grid(a.E)),
                                   dim3(S::NT), 0, st, e0, e1, 0, a);
@@ -1573,13 +1585,19 @@ struct Impl {
                        hipEvent_t e1) {
         using U = Shape<D, P, update_tpb(D, P)>;
         const dim3 g((unsigned)((a.E + U::EPB - 1) / U::EPB)), b(U::NT);
-        if (nvar == 2) {
-            if (kind == UP_RK) hipExtLaunchKernelGGL((k_update<R, D, P, 2, UP_RK>), g, b, 0, st, e0, e1, 0, a);
-            else hipExtLaunchKernelGGL((k_update<R, D, P, 2, UP_RESID>), g, b, 0, st, e0, e1, 0, a);
-        } else {
-            if (kind == UP_RK) hipExtLaunchKernelGGL((k_update<R, D, P, 1, UP_RK>), g, b, 0, st, e0, e1, 0, a);
-            else hipExtLaunchKernelGGL((k_update<R, D, P, 1, UP_RESID>), g, b, 0, st, e0, e1, 0, a);
-        }
+        const bool stream = a.E * S::NU * (int64_t)sizeof(R) > XCD_MAP_MAX_PLANE_BYTES;
+        auto go = [&](auto STC) {
+            constexpr bool ST = decltype(STC)::value;
+            if (nvar == 2) {
+                if (kind == UP_RK) hipExtLaunchKernelGGL((k_update<R, D, P, 2, UP_RK, ST>), g, b, 0, st, e0, e1, 0, a);
+                else hipExtLaunchKernelGGL((k_update<R, D, P, 2, UP_RESID, ST>), g, b, 0, st, e0, e1, 0, a);
+            } else {
+                if (kind == UP_RK) hipExtLaunchKernelGGL((k_update<R, D, P, 1, UP_RK, ST>), g, b, 0, st, e0, e1, 0, a);
+                else hipExtLaunchKernelGGL((k_update<R, D, P, 1, UP_RESID, ST>), g, b, 0, st, e0, e1, 0, a);
+            }
+        };
+        if (stream) go(std::true_type{});
+        else go(std::false_type{});
     }
     static void trace(int nvar, const TRArgs<R>& a, hipStream_t st) {
         const dim3 g(grid(a.E)), b(S::NT);
