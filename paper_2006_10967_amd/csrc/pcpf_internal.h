@@ -33,11 +33,13 @@ struct Shape {
     static constexpr int GEO = D + 2 * D * D + 1;   // x0[D], J[D][D], Jinv[D][D], detJ
 };
 
-// Threads per block of the update kernel: 512 for the 3D elements of 125 or more points
-// (four elements per block instead of two, so that the runs a block reads and writes in
-// each face plane span four elements: 96^3 p4 2274 -> 2206 us; no gain at 64 points),
-// 256 otherwise.
-constexpr int update_tpb(int d, int p) { return (d == 3 && p >= 4) ? 512 : 256; }
+// Threads per block of the update kernel: for the 3D elements of 125 or more points, 1024
+// in FP64 (eight elements per block, so that the runs a block reads and writes in each face
+// plane span eight elements: 96^3 p4 2274 us at 256, 2206 at 512, 2056 at 1024) and 512 in
+// FP32 (1144 us; 1196 at 1024); 256 otherwise (no gain at 64 points).
+constexpr int update_tpb(int d, int p, int word) {
+    return (d == 3 && p >= 4) ? (word == 8 ? 1024 : 512) : 256;
+}
 
 // Lane utilisation (per mille) of nt-thread blocks holding whole elements of nu points.
 constexpr int lane_util(int nu, int nt) { return nt >= nu ? (nt / nu) * nu * 1000 / nt : 0; }

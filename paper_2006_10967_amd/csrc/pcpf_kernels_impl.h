@@ -1303,8 +1303,9 @@ __device__ __forceinline__ void push_traces(R* const* Tp, const R* lm, const R* 
 // each); the registers read and written once per stage (P, u_n, the accumulator, the next
 // stage input) then go with the non-temporal hint.
 template <typename R, int D, int P, int V, int KIND, bool STREAM>
-__global__ __launch_bounds__((Shape<D, P, update_tpb(D, P)>::NT)) void k_update(UPArgs<R> a) {
-    using S = Shape<D, P, update_tpb(D, P)>;
+__global__ __launch_bounds__((Shape<D, P, update_tpb(D, P, sizeof(R))>::NT))
+void k_update(UPArgs<R> a) {
+    using S = Shape<D, P, update_tpb(D, P, sizeof(R))>;
     constexpr int N = S::N, NU = S::NU, NFA = S::NFA, EPB = S::EPB, NT = S::NT, G = S::GEO;
     constexpr int NFE = 2 * D * NFA;
     __shared__ R s_c[3 * N];                 // cm, cp, lm
@@ -1583,7 +1584,7 @@ struct Impl {
     }
     static void update(int kind, int nvar, const UPArgs<R>& a, hipStream_t st, hipEvent_t e0,
                        hipEvent_t e1) {
-        using U = Shape<D, P, update_tpb(D, P)>;
+        using U = Shape<D, P, update_tpb(D, P, sizeof(R))>;
         const dim3 g((unsigned)((a.E + U::EPB - 1) / U::EPB)), b(U::NT);
         const bool stream = a.E * S::NU * (int64_t)sizeof(R) > XCD_MAP_MAX_PLANE_BYTES;
         auto go = [&](auto STC) {
