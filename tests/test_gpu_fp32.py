@@ -77,6 +77,26 @@ def test_fp32_residual_within_stated_tolerance(cid, d, p, shape, kw):
     assert ep <= RES_TOL and es <= RES_TOL, (cid, ep, es)
 
 
+NPHI_CASES = [c for c in CASES if c[0] in ("2d_p4_vortex", "2d_p3_sheared", "3d_p3_skew")]
+
+
+@pytest.mark.parametrize("cid,d,p,shape,kw", NPHI_CASES, ids=[c[0] for c in NPHI_CASES])
+def test_fp32_unpreconditioned_residual(cid, d, p, shape, kw):
+    """The unpreconditioned form (normal from phi) in FP32, against the oracle in the same
+    mode: the FP32 residual bar (2D: the line kernel of the FP32 form; 3D skewed hexes:
+    the general-J line kernel)."""
+    import dataclasses
+    mesh, prm = W.small_case(d, p, shape, **kw)
+    prm = dataclasses.replace(prm, normal_mode=W.NORMAL_PHI)
+    o = Oracle(d, p, mesh, prm)
+    s = _solver(mesh, p, prm, "fp32")
+    phi, psi = _smooth_state(o, "nphi:" + cid)
+    Rp, Rs = o.residual(phi, psi, 0.37)
+    gp, gs = s.residual(phi, psi, 0.37)
+    ep, es = _rel(gp, Rp), _rel(gs, Rs)
+    assert ep <= RES_TOL and es <= RES_TOL, (cid, ep, es)
+
+
 @pytest.mark.parametrize("cid,d,p,shape,kw", CASES[:4], ids=[c[0] for c in CASES[:4]])
 def test_fp32_precond_residual_within_stated_tolerance(cid, d, p, shape, kw):
     mesh, prm = W.small_case(d, p, shape, **kw)

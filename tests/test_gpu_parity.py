@@ -244,7 +244,8 @@ def test_nonfinite_is_reported():
 
 NPHI_CASES = [c for c in CASES if c[0] in ("2d_p4_vortex_ragged", "2d_p3_copybc_rotation",
                                            "2d_p2_sheared", "3d_p3_leveque_ragged",
-                                           "3d_p4_perturbed")]
+                                           "3d_p4_perturbed", "3d_p3_skew",
+                                           "3d_p4_skew_copybc")]
 
 
 @pytest.mark.parametrize("cid,d,p,shape,kw", NPHI_CASES, ids=[c[0] for c in NPHI_CASES])
