@@ -713,6 +713,7 @@ UPArgs<R> up_args(const Ctx<R>& C) {
     a.ops = C.template at<R>(c->L.ops);
     a.flag = C.template at<int>(c->L.flag);
     a.E = c->mi.E;
+    a.mf = c->prm.precision == PCPF_BF16 ? 1 : 0;
     return a;
 }
 

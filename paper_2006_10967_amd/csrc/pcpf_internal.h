@@ -148,6 +148,8 @@ struct UPArgs {
     R bcoef;             // weight of R in the accumulator
     R ccoef;             // step of the next stage input (a_{s+1} dt), or dt on the last stage
     int first, last;
+    int mf;              // as GFArgs::mf: selects which grad_flux kernel produced P (the line
+                         // kernel also lifts the + face fluxes into P)
 };
 
 template <typename R>

@@ -734,8 +734,10 @@ void k_grad_flux(GFArgs<R> a) {
 //   B2  line threads: the common flux of the + face point (Step 5), reading only the other
 //       gradient components at the face; all threads: the flux at their solution point
 //       (Step 4) to LDS.
-//   E1  line threads: DH_K applied along the line (volume part of Step 6), to LDS.
-//   E2  all threads: P = the sum over the directions (fixed order), to global.
+//   E1  line threads: DH_K applied along the line (volume part of Step 6) plus the lifting
+//       of the line's + face common flux from B2, to LDS.
+//   E2  all threads: P = the sum over the directions (fixed order), to global; the update
+//       adds the lifting of the - face fluxes.
 // On axis-aligned meshes the LDS holds the physical gradient (one metric factor per
 // component); otherwise the reference components, transformed where they are used.
 // ------------------------------------------------------------------------------------
@@ -1049,8 +1051,15 @@ void k_grad_flux_lines(GFArgs<R> a) {
         const R F0 = R(0.5) * (pL + pR) * vn - fvn + a.ph.tau * (pL - pR);
         const R F1 = R(0.5) * (sL + sR) * vn + a.ph.tau * (sL - sR);
         const uint32_t fo = (((uint32_t)(SD ? K : D + K)) * Eu + (uint32_t)(e0 + el)) * NFA + t;
-        gst(a.Fp[0], fo, sc * F0);
-        gst(a.Fp[1], fo, sc * F1);
+        const R Fs0 = sc * F0, Fs1 = sc * F1;
+        gst(a.Fp[0], fo, Fs0);
+        gst(a.Fp[1], fo, Fs1);
+        if constexpr (SD == 1) {
+            // kept for the lifting of the + face in E1, in the slot of the neighbour trace
+            // (read into registers in B1): the same thread writes and later reads it
+            s_nb[0][el * NPF + K * NFA + t] = Fs0;
+            s_nb[1][el * NPF + K * NFA + t] = Fs1;
+        }
         (void)en;
     };
     // physical gradient at a face point from its interpolated reference (non-axis) or
@@ -1197,29 +1206,34 @@ void k_grad_flux_lines(GFArgs<R> a) {
     }
     __syncthreads();
 
-    // ---- E1: DH_K f~_K along each line (volume part of Step 6), in place ------------------
+    // ---- E1: DH_K f~_K along each line (volume part of Step 6), in place, plus the
+    // lifting cp F~ of the line's + face common flux (the face part of Step 6 on the faces
+    // this element owns; the update adds the - faces') ----------------------------------
     const R* DH = &s_ops[op_dh(N)];
     for_units([&](auto KC, int j, int el, int t) {
         (void)j;
         constexpr int K = decltype(KC)::value;
         constexpr int SK = st<N>(K);
         const int base = el * NU + face_base<D, N>(K, t);
-        R fl[V][N];
+        R fl[V][N], fp[V];
 #pragma unroll
-        for (int v = 0; v < V; ++v)
+        for (int v = 0; v < V; ++v) {
 #pragma unroll
             for (int b = 0; b < N; ++b) fl[v][b] = s_x[(v * D + K) * XST + base + b * SK];
+            fp[v] = s_nb[v][el * NPF + K * NFA + t];
+        }
 #pragma unroll
         for (int q = 0; q < N; ++q) {
             R row[N];
 #pragma unroll
             for (int b = 0; b < N; ++b) row[b] = DH[q * N + b];
+            const R c = cpv[q];
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 R acc = R(0);
 #pragma unroll
                 for (int b = 0; b < N; ++b) acc += row[b] * fl[v][b];
-                s_x[(v * D + K) * XST + base + q * SK] = acc;
+                s_x[(v * D + K) * XST + base + q * SK] = acc + c * fp[v];
             }
         }
     });
@@ -1302,12 +1316,15 @@ __device__ __forceinline__ void push_traces(R* const* Tp, const R* lm, const R* 
 // STREAM: the state planes are larger than the caches (more than XCD_MAP_MAX_PLANE_BYTES
 // each); the registers read and written once per stage (P, u_n, the accumulator, the next
 // stage input) then go with the non-temporal hint.
-template <typename R, int D, int P, int V, int KIND, bool STREAM>
+// PF: P already holds the lifting of the element's + face fluxes (the line kernel adds it,
+// from the fluxes it has just computed); only the - face fluxes are read here.
+template <typename R, int D, int P, int V, int KIND, bool STREAM, bool PF>
 __global__ __launch_bounds__((Shape<D, P, update_tpb(D, P, sizeof(R))>::NT))
 void k_update(UPArgs<R> a) {
     using S = Shape<D, P, update_tpb(D, P, sizeof(R))>;
     constexpr int N = S::N, NU = S::NU, NFA = S::NFA, EPB = S::EPB, NT = S::NT, G = S::GEO;
-    constexpr int NFE = 2 * D * NFA;
+    constexpr int NFS = PF ? D : 2 * D;      // faces whose fluxes are read, per element
+    constexpr int NFE = NFS * NFA;
     __shared__ R s_c[3 * N];                 // cm, cp, lm
     __shared__ R s_F[V][EPB * NFE];
     __shared__ R s_u[V][KIND == UP_RK ? EPB * NU : 1];
@@ -1343,10 +1360,10 @@ void k_update(UPArgs<R> a) {
     r_c[0] = gld_in(a.ops + op_cm(N), tid, N);
     r_c[1] = gld_in(a.ops + op_cp(N), tid, N);
     r_c[2] = gld_in(a.ops + op_lm(N), tid, N);
-    // lanes run over [face f = 2k + s][el NFA + t]: the + face fluxes of the block are
-    // contiguous in plane k; the - face flux is minus the owner's + face flux in plane k
-    // (the owners e - stride_k of consecutive elements are consecutive), or on a boundary
-    // the element's own, in plane D + k
+    // lanes run over [face f][el NFA + t], f = 2k + s (f = k, the - faces only, with PF):
+    // the + face fluxes of the block are contiguous in plane k; the - face flux is minus the
+    // owner's + face flux in plane k (the owners e - stride_k of consecutive elements are
+    // consecutive), or on a boundary the element's own, in plane D + k
     constexpr int KSEG = S::KSEG;
     const uint32_t Eu = (uint32_t)a.E;
     R r_F[I_F][V];
@@ -1357,11 +1374,11 @@ void k_update(UPArgs<R> a) {
         const int it = tid + j * NT;
         int f = it / KSEG;
         int r = it - f * KSEG;
-        const bool ok = f < 2 * D && r < nel * NFA;
-        f = f < 2 * D ? f : 2 * D - 1;
+        const bool ok = f < NFS && r < nel * NFA;
+        f = f < NFS ? f : NFS - 1;
         r = r < nel * NFA ? r : nel * NFA - 1;
         const int el = r / NFA, t = r - el * NFA;
-        const int k = f >> 1, sd = f & 1;
+        const int k = PF ? f : f >> 1, sd = PF ? 0 : f & 1;
         f_pos[j] = ok ? el * NFE + f * NFA + t : -1;
         uint32_t gi;
         bool neg = false;
@@ -1406,8 +1423,11 @@ void k_update(UPArgs<R> a) {
 #pragma unroll
             for (int k = 0; k < D; ++k) {
                 const int tk = tang_index<D, N>(k, mi);
-                acc += s_c[N + mi[k]] * s_F[v][le * NFE + (2 * k + 1) * NFA + tk]
-                     + s_c[mi[k]] * s_F[v][le * NFE + (2 * k) * NFA + tk];
+                if constexpr (PF)
+                    acc += s_c[mi[k]] * s_F[v][le * NFE + k * NFA + tk];
+                else
+                    acc += s_c[N + mi[k]] * s_F[v][le * NFE + (2 * k + 1) * NFA + tk]
+                         + s_c[mi[k]] * s_F[v][le * NFE + (2 * k) * NFA + tk];
             }
             const R res = -acc * rdet;
             if constexpr (KIND == UP_RESID) {
@@ -1527,12 +1547,15 @@ template <typename R, int D, int P>
 struct Impl {
     using S = Shape<D, P>;
     static unsigned grid(int64_t E) { return (unsigned)((E + S::EPB - 1) / S::EPB); }
+    // the line kernel runs the physical mode, outside the BF16 form, in 3D, and in 2D in
+    // FP32 (128^2 p4: FP32 grad_flux 6.9 -> 6.2 us; FP64 9.8 against 10.0 us with the point
+    // kernel)
+    static constexpr bool LINES_DIM = D == 3 || sizeof(R) == 4;
+    static constexpr bool lines(int mode, bool mf) { return mode == GF_PHYS && !mf && LINES_DIM; }
 
     template <int MODE, bool AXIS, bool MF, bool NPHI>
     static void gf_launch(const GFArgs<R>& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-        // the line kernel: 3D, and 2D in FP32 (128^2 p4: FP32 grad_flux 6.9 -> 6.2 us; FP64
-        // 9.8 against 10.0 us with the point kernel)
-        if constexpr (MODE == GF_PHYS && !MF && (D == 3 || sizeof(R) == 4)) {
+        if constexpr (lines(MODE, MF)) {
             if (a.E * S::NU * (int64_t)sizeof(R) > XCD_MAP_MAX_PLANE_BYTES)
                 hipExtLaunchKernelGGL((k_grad_flux_lines<R, D, P, AXIS, NPHI, true>), dim3(grid(a.E)),
                                       dim3(S::NT), 0, st, e0, e1, 0, a);
@@ -1587,18 +1610,30 @@ struct Impl {
         using U = Shape<D, P, update_tpb(D, P, sizeof(R))>;
         const dim3 g((unsigned)((a.E + U::EPB - 1) / U::EPB)), b(U::NT);
         const bool stream = a.E * S::NU * (int64_t)sizeof(R) > XCD_MAP_MAX_PLANE_BYTES;
-        auto go = [&](auto STC) {
-            constexpr bool ST = decltype(STC)::value;
+        // two variables: the physical mode, whose grad_flux may be the line kernel (which
+        // has lifted the + face fluxes into P already); one variable: preconditioning
+        const bool pf = nvar == 2 && lines(GF_PHYS, a.mf != 0);
+        auto go = [&](auto STC, auto PFC) {
+            constexpr bool ST = decltype(STC)::value, PF = decltype(PFC)::value;
             if (nvar == 2) {
-                if (kind == UP_RK) hipExtLaunchKernelGGL((k_update<R, D, P, 2, UP_RK, ST>), g, b, 0, st, e0, e1, 0, a);
-                else hipExtLaunchKernelGGL((k_update<R, D, P, 2, UP_RESID, ST>), g, b, 0, st, e0, e1, 0, a);
-            } else {
-                if (kind == UP_RK) hipExtLaunchKernelGGL((k_update<R, D, P, 1, UP_RK, ST>), g, b, 0, st, e0, e1, 0, a);
-                else hipExtLaunchKernelGGL((k_update<R, D, P, 1, UP_RESID, ST>), g, b, 0, st, e0, e1, 0, a);
+                if (kind == UP_RK) hipExtLaunchKernelGGL((k_update<R, D, P, 2, UP_RK, ST, PF>), g, b, 0, st, e0, e1, 0, a);
+                else hipExtLaunchKernelGGL((k_update<R, D, P, 2, UP_RESID, ST, PF>), g, b, 0, st, e0, e1, 0, a);
+            } else if constexpr (!PF) {
+                if (kind == UP_RK) hipExtLaunchKernelGGL((k_update<R, D, P, 1, UP_RK, ST, false>), g, b, 0, st, e0, e1, 0, a);
+                else hipExtLaunchKernelGGL((k_update<R, D, P, 1, UP_RESID, ST, false>), g, b, 0, st, e0, e1, 0, a);
             }
         };
-        if (stream) go(std::true_type{});
-        else go(std::false_type{});
+        auto go_pf = [&](auto STC) {
+            if constexpr (LINES_DIM) {
+                if (pf) {
+                    go(STC, std::true_type{});
+                    return;
+                }
+            }
+            go(STC, std::false_type{});
+        };
+        if (stream) go_pf(std::true_type{});
+        else go_pf(std::false_type{});
     }
     static void trace(int nvar, const TRArgs<R>& a, hipStream_t st) {
         const dim3 g(grid(a.E)), b(S::NT);
