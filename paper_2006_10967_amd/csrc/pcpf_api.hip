@@ -160,7 +160,7 @@ bool solve_dense(int n, std::vector<LD> A, int m, std::vector<LD>& B) {
 
 struct TriOps {
     int p = 0, nu = 0, nf = 0;
-    std::vector<double> upt, fpt, nh, wf, M0, D0, D1, Lift, Vinv, W;
+    std::vector<double> upt, fpt, nh, wf, M0, D0, D1, Lift, Vinv, W, DH0, DH1;
     std::vector<uint8_t> top;
 };
 
@@ -246,6 +246,16 @@ bool tri_operators(int p, TriOps* T) {
     for (int x = 0; x < nu; ++x)
         for (int f = 0; f < nf; ++f) Em[x * nf + f] = wf[f] * M0[f * nu + x];
     if (!solve_dense(nu, Mn, nf, Em)) return false;
+    // the volume operators of Step 6 with the lifting of the interpolated normal flux folded
+    // in: DH_k = D_k - Lift diag(nhat_k) M0, so that the volume part is DH_0 f~_0 + DH_1 f~_1
+    std::vector<LD> DH0(D0), DH1(D1);
+    for (int x = 0; x < nu; ++x)
+        for (int y = 0; y < nu; ++y)
+            for (int f = 0; f < nf; ++f) {
+                const LD t = Em[x * nf + f] * M0[f * nu + y];
+                DH0[x * nu + y] -= t * nh[2 * f];
+                DH1[x * nu + y] -= t * nh[2 * f + 1];
+            }
     // orthonormal modes psi = L^-1 phi (G = L L^T): Vinv = L^T V^-1
     std::vector<LD> Lc(nu * nu, 0.0L);
     for (int x = 0; x < nu; ++x)
@@ -274,6 +284,8 @@ bool tri_operators(int p, TriOps* T) {
     T->Lift = rd(Em);
     T->Vinv = rd(Vinv);
     T->W = rd(W);
+    T->DH0 = rd(DH0);
+    T->DH1 = rd(DH1);
     T->top.resize(nu);
     int m = 0;
     for (int deg = 0; deg <= p; ++deg)
@@ -1898,6 +1910,8 @@ pcpf_status upload_tri(pcpf_ctx* c, const TriHolder& h) {
     put(T.upt);
     put(T.fpt);
     put(T.nh);
+    put(T.DH0);
+    put(T.DH1);
     (void)nf;
     Ctx<R> C{c};
     HIPCHK(c, hipMemcpyAsync(C.template at<R>(c->L.geo), geo.data(), geo.size() * sizeof(R),

@@ -25,13 +25,15 @@ struct TriShape {
     static constexpr int OUR = OTOP + NU;            // solution points [N_u][2]
     static constexpr int OFR = OUR + 2 * NU;         // flux points [N_f][2]
     static constexpr int ONH = OFR + 2 * NF;         // reference outward unit normals [N_f][2]
-    static constexpr int NOPS = ONH + 2 * NF;
+    static constexpr int ODH0 = ONH + 2 * NF;        // DH_k = D_k - Lift diag(nhat_k) M0,
+    static constexpr int ODH1 = ODH0 + NU * NU;      //   [N_u][N_u] each (Step 6 volume part)
+    static constexpr int NOPS = ODH1 + NU * NU;
 };
 
 constexpr int tri_nupts(int p) { return (p + 1) * (p + 2) / 2; }
 constexpr int tri_nfpts(int p) { return 3 * (p + 1); }
 constexpr int tri_ops_size(int p) {
-    return tri_nfpts(p) * tri_nupts(p) * 2 + 3 * tri_nupts(p) * tri_nupts(p) + tri_nupts(p) +
+    return tri_nfpts(p) * tri_nupts(p) * 2 + 5 * tri_nupts(p) * tri_nupts(p) + tri_nupts(p) +
            2 * tri_nupts(p) + 4 * tri_nfpts(p);
 }
 constexpr int TRI_MAX_ORDER = 5;

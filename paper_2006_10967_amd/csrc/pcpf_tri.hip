@@ -38,7 +38,7 @@ __global__ __launch_bounds__(256) void k_tri_grad_flux(GFArgs<R> a) {
     constexpr int NU = S::NU, NF = S::NF, EPB = S::EPB, G = S::G;
     constexpr int V = (MODE == GF_PHYS) ? 2 : 1;
     constexpr int NV = NPHI ? 0 : V - 1;
-    constexpr int NOPS = S::NOPS;
+    constexpr int NOPS = S::ODH0;             // the operators up to the normals (no DH_k)
     constexpr bool FLUX = (MODE == GF_PHYS || MODE == GF_PRECOND);
     constexpr bool SENS = (MODE == GF_PRECOND || MODE == GF_SENSOR);
     constexpr bool GRAD = (MODE != GF_SENSOR);
@@ -334,18 +334,20 @@ __global__ __launch_bounds__(64 * TRI_MF_WAVES) void k_tri_grad_flux_mf(GFArgs<R
     // s_op[o][s][lane]: conflict-free reads), and the per-lane constants of the rows a lane
     // holds (reference point coordinates, flux point coordinates and normals). Kept in LDS
     // and read where used, they leave the registers to the 16-element fields.
-    enum { O_M0, O_D0, O_D1, O_L };
+    enum { O_M0, O_D0, O_D1, O_L, O_DH0, O_DH1, NOP };
     enum { C_UR0, C_UR1, C_FR0, C_FR1, C_NH0, C_NH1 };
-    __shared__ R s_op[4][4][64];
+    __shared__ R s_op[NOP][4][64];
     __shared__ R s_cst[6][4][64];
-    for (int t = threadIdx.x; t < 4 * 4 * 64; t += 64 * TRI_MF_WAVES) {
+    for (int t = threadIdx.x; t < NOP * 4 * 64; t += 64 * TRI_MF_WAVES) {
         const int o = t >> 8, st = (t >> 6) & 3, l = t & 63;
         const int m = l & 15, k = MfTile<R>::row(l >> 4, st);
         R val = R(0);
         if (o == O_M0) val = (m < NF && k < NU) ? a.ops[S::OM0 + m * NU + k] : R(0);
         else if (o == O_D0) val = (m < NU && k < NU) ? a.ops[S::OD0 + m * NU + k] : R(0);
         else if (o == O_D1) val = (m < NU && k < NU) ? a.ops[S::OD1 + m * NU + k] : R(0);
-        else val = (m < NU && k < NF) ? a.ops[S::OL + m * NF + k] : R(0);
+        else if (o == O_L) val = (m < NU && k < NF) ? a.ops[S::OL + m * NF + k] : R(0);
+        else if (o == O_DH0) val = (m < NU && k < NU) ? a.ops[S::ODH0 + m * NU + k] : R(0);
+        else val = (m < NU && k < NU) ? a.ops[S::ODH1 + m * NU + k] : R(0);
         s_op[o][st][l] = val;
     }
     for (int t = threadIdx.x; t < 4 * 64; t += 64 * TRI_MF_WAVES) {
@@ -488,17 +490,13 @@ __global__ __launch_bounds__(64 * TRI_MF_WAVES) void k_tri_grad_flux_mf(GFArgs<R
             }
         }
 
-        // ---- Step 6, volume part: P = D_0 f~_0 + D_1 f~_1 - Lift (nhat . M0 f~) ------------
+        // ---- Step 6, volume part: P = D_0 f~_0 + D_1 f~_1 - Lift (nhat . M0 f~)
+        // = DH_0 f~_0 + DH_1 f~_1, the lifting folded into DH_k = D_k - Lift diag(nhat_k) M0
+        // (two products per variable instead of five) -----------------------------------
 #pragma unroll
         for (int v = 0; v < 2; ++v) {
-            const v4 a0 = apply(O_M0, ft[v][0], z);
-            const v4 a1 = apply(O_M0, ft[v][1], z);
-            v4 mfp;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) mfp[r] = -(cst(C_NH0, r) * a0[r] + cst(C_NH1, r) * a1[r]);
-            v4 pacc = apply(O_D0, ft[v][0], z);
-            pacc = apply(O_D1, ft[v][1], pacc);
-            pacc = apply(O_L, mfp, pacc);
+            v4 pacc = apply(O_DH0, ft[v][0], z);
+            pacc = apply(O_DH1, ft[v][1], pacc);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int j = T::row(g, r);
