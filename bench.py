@@ -61,16 +61,21 @@ def sync():
     torch.cuda.synchronize()
 
 
-def stage_words(d, p, element="tensor"):
+def stage_words(d, p, element="tensor", lifted=False, tables=False):
     """Words per element of one RK stage.
 
     alg:  5 V N_u + 2 V N_f (read the stage input and u_n, read and write the accumulator,
           write the next stage input; write and read the face traces and common fluxes);
-    impl: what the two launches of a stage read and write, averaged over the four stages
-          (the accumulator is not read on stage 1 nor written on stage 4): grad_flux reads
-          u and the pushed traces and writes the partial divergence and the common fluxes
-          of its + faces (its own slot and the neighbour's); update reads those, u_n and the
-          accumulator and writes the accumulator, the next stage input and its - face traces.
+    impl: what the two launches of a stage read and write, each array once, averaged over
+          the four stages (the accumulator is not read on stage 1 nor written on stage 4).
+          Tensor elements: grad_flux reads u, the pushed + face traces, geometry and the
+          adjacency (2 d int32 per element), and with tables the per-element velocity tables
+          (2 values at the n nodes and both ends of each axis), and writes the partial
+          divergence P and the common flux of each + face point (one slot); update reads P,
+          the fluxes of both faces of each direction (only the - faces when lifted: the line
+          kernel has added the + faces' lifting to P), |J|, the adjacency, u_n and the
+          accumulator, and writes the accumulator, the next stage input and the - face
+          traces pushed to the owners.
     """
     V = 2
     if element == "triangle":
@@ -92,10 +97,23 @@ def stage_words(d, p, element="tensor"):
     nf = 2 * d * nfa
     npf = d * nfa
     geo = d + 2 * d * d + 1
+    adj = d                                   # 2 d int32 neighbours per element
+    tab = 2 * d * (n + 2) if tables else 0
     alg = 5 * V * nu + 2 * V * nf
-    gf = V * nu + V * npf + geo + V * nu + 2 * V * npf
-    up = V * nu + 2 * V * npf + 1 + V * nu + 0.75 * V * nu + 0.75 * V * nu + V * nu + V * npf
+    gf = V * nu + V * npf + geo + adj + tab + V * nu + V * npf
+    up = (V * nu + (1 if lifted else 2) * V * npf + 1 + adj + V * nu + 0.75 * V * nu
+          + 0.75 * V * nu + V * nu + V * npf)
     return {"alg": alg, "impl": gf + up, "grad_flux": gf, "update": up}
+
+
+def stage_words_of(cfg, form):
+    """stage_words for a workload and form: the line kernel (3D; 2D in FP32; not the BF16
+    form) lifts the + face fluxes into P; the trigonometric fields on the workloads' box
+    meshes (axis-aligned elements) read the per-element velocity tables."""
+    import workloads as W
+    lifted = cfg.element == "tensor" and form != "bf16" and (cfg.ndims == 3 or form == "fp32")
+    tables = cfg.element == "tensor" and cfg.params.vel_kind in (W.VEL_SINGLE_VORTEX, W.VEL_LEVEQUE3D)
+    return stage_words(cfg.ndims, cfg.order, cfg.element, lifted, tables)
 
 
 def kernel_source_hash():
@@ -198,7 +216,6 @@ def workload_leg(name, forms, K, Wm, acc_steps, hsh):
     cfg = W.config(name)
     mesh = cfg.mesh()
     phi0 = initial_state(cfg, mesh)
-    words = stage_words(cfg.ndims, cfg.order, cfg.element)
     log(f"[bench] {cfg.name}: E={cfg.nelem} N_u={cfg.nupts} DOF={cfg.dof} K={K} warmup={Wm}")
     out = {"workload": cfg.name, "description": cfg.description, "elements": cfg.nelem,
            "order": cfg.order, "dof": cfg.dof, "dt": cfg.dt(mesh),
@@ -214,6 +231,7 @@ def workload_leg(name, forms, K, Wm, acc_steps, hsh):
         gf_us = gf_ms / gf_n * 1e3
         up_us = up_ms / up_n * 1e3
         stage_us = gf_us + up_us
+        words = stage_words_of(cfg, form)
         alg = words["alg"] * word * cfg.nelem
         impl = words["impl"] * word * cfg.nelem
         achieved = alg / (stage_us * 1e-6) / 1e9

@@ -23,23 +23,41 @@ def test_stage_alg_words_per_dof(d, p, values):
 
 
 @pytest.mark.parametrize("d,p", [(2, 3), (2, 4), (3, 3), (3, 4)])
-def test_stage_impl_words(d, p):
+@pytest.mark.parametrize("lifted", [False, True])
+@pytest.mark.parametrize("tables", [False, True])
+def test_stage_impl_words(d, p, lifted, tables):
     n = p + 1
     nu, nfa = n ** d, n ** (d - 1)
     geo = d + 2 * d * d + 1          # x0, J, J^-1, |J|
-    # grad_flux: reads u (2 planes), the + face traces (2 d planes of nfa) and geo;
-    # writes P (2 planes) and the + face common fluxes into its own and the neighbour's
-    # slots (2 x 2 d nfa)
-    gf = 2 * nu + 2 * d * nfa + geo + 2 * nu + 2 * 2 * d * nfa
-    # update, averaged over the 4 stages: reads P, Fp, Fm, |J|, u_n and acc (not on stage
-    # 1); writes acc (not on stage 4), the next stage input and the pushed traces
-    up = 2 * nu + 2 * (2 * d * nfa) + 1 + 2 * nu + 0.75 * 2 * nu + 0.75 * 2 * nu + 2 * nu \
-        + 2 * d * nfa
-    w = bench.stage_words(d, p)
+    adj = 2 * d / 2                  # 2 d int32 neighbour indices per element, in words
+    tab = 2 * d * (n + 2) if tables else 0   # (sin^2, sin 2x) at n nodes + 2 ends per axis
+    # grad_flux: reads u (2 planes), the + face traces (2 d planes of nfa), geo, the
+    # adjacency and the velocity tables; writes P (2 planes) and the + face common fluxes
+    # (one slot per + face point, 2 d planes of nfa)
+    gf = 2 * nu + 2 * d * nfa + geo + adj + tab + 2 * nu + 2 * d * nfa
+    # update, averaged over the 4 stages: reads P, the - face fluxes (and the + face ones
+    # unless the line kernel lifted them into P), |J|, the adjacency, u_n and acc (not on
+    # stage 1); writes acc (not on stage 4), the next stage input and the pushed traces
+    up = 2 * nu + (1 if lifted else 2) * 2 * d * nfa + 1 + adj + 2 * nu + 0.75 * 2 * nu \
+        + 0.75 * 2 * nu + 2 * nu + 2 * d * nfa
+    w = bench.stage_words(d, p, lifted=lifted, tables=tables)
     assert w["grad_flux"] == gf and w["update"] == up and w["impl"] == gf + up
     # 96^3 p=4 FP64: 13.1 GB of algorithmic bytes per stage
     if (d, p) == (3, 4):
         assert abs(w["alg"] * 8 * 96 ** 3 / 1e9 - 13.095) < 1e-3
+
+
+def test_stage_words_of_forms():
+    """Which kernels run: the line kernel (3D in FP64 and FP32, 2D in FP32) lifts the + face
+    fluxes; the BF16 form and 2D FP64 do not; the box workloads with trigonometric fields
+    read the velocity tables, the uniform-velocity one does not."""
+    import workloads as W
+    c5, c2, c1 = W.config("C5"), W.config("C2"), W.config("C1")
+    assert bench.stage_words_of(c5, "fp64") == bench.stage_words(3, 4, lifted=True, tables=True)
+    assert bench.stage_words_of(c5, "bf16") == bench.stage_words(3, 4, lifted=False, tables=True)
+    assert bench.stage_words_of(c2, "fp64") == bench.stage_words(2, 4, lifted=False, tables=True)
+    assert bench.stage_words_of(c2, "fp32") == bench.stage_words(2, 4, lifted=True, tables=True)
+    assert bench.stage_words_of(c1, "fp64") == bench.stage_words(2, 3, lifted=False, tables=False)
 
 
 @pytest.mark.parametrize("p", [3, 4, 5])
