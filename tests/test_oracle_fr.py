@@ -9,7 +9,9 @@ P7  mass conservation of every residual to round-off (periodic).
 P8  p+1 convergence on smooth advection (upwind penalty tau = |v.n|/2).
 P9  stationarity of the 1D tanh equilibrium at zero velocity.
 P17 energy stability of the linear part (catches penalty/lifting sign errors).
+P18 the sharpening flux with the regularised interface normal, exact on polynomials.
 """
+import dataclasses
 import math
 
 import numpy as np
@@ -396,3 +398,26 @@ def test_unpreconditioned_normal_reduces_to_psi_equal_phi():
     # and it differs from the preconditioned residual with the given psi
     Rpp, _ = o0.residual(phi, psi, 0.2)
     assert float((Rpp - Rp1).abs().max()) > 1e-3 * float(Rp1.abs().max())
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_sharpening_flux_regularised_normal(p):
+    """The sharpening part of the phi flux, max(gamma, |v|) gamma phi (1 - phi) n with the
+    regularised normal n = grad psi / sqrt(|grad psi|^2 + delta_n^2) (§2; the regularisation
+    is the reading recorded for |grad psi| -> 0). At rest (v = 0, so the multiplier is gamma)
+    with eps = 0, psi = x and phi = a + b x on a non-periodic mesh (copy boundaries), every
+    flux is a polynomial of degree <= p that FR differentiates exactly, so
+    R_phi = -gamma^2 b (1 - 2a - 2b x) / sqrt(1 + delta_n^2). delta_n = 1 makes the
+    regularisation visible (the factor 1/sqrt 2)."""
+    mesh, prm = W.small_case(2, p, (3, 2), periodic=False, vel_u0=(0.0, 0.0, 0.0))
+    prm = dataclasses.replace(prm, eps=0.0, delta_n=1.0)
+    o = Oracle(2, p, mesh, prm)
+    x = o.coords()
+    a, b = 0.3, 0.2
+    phi = torch.as_tensor(a + b * x[..., 0], dtype=torch.float64)
+    psi = torch.as_tensor(x[..., 0], dtype=torch.float64)
+    Rphi, Rpsi = o.residual(phi, psi, 0.0)
+    g = prm.gamma
+    expect = -g * g * b * (1.0 - 2.0 * a - 2.0 * b * x[..., 0]) / np.sqrt(2.0)
+    assert np.abs(Rphi.numpy() - expect).max() < 1e-12
+    assert float(torch.max(torch.abs(Rpsi))) < 1e-13

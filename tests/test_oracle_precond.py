@@ -192,3 +192,36 @@ def test_rms_stop_is_first_crossing(sgn_mode):
     fixed = Oracle(2, 3, mesh, dataclasses.replace(prm, stop_mode=W.STOP_FIXED))
     psi_k, _ = fixed.precondition(phi, iters=k)
     assert torch.equal(psi_k, psi)
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_precond_penalty_flux_closed_form(p):
+    """The common flux of the preconditioning system carries the penalty tau (psi_L - psi_R)
+    (§3.2, with the interface flux of §3.1 Step 5). With psi constant in each element the
+    sensor gives nu = 0 (no degree-p modes), the volume flux -nu grad psi vanishes, and with
+    sgn = 0 the residual is the lifting of the penalty alone. On a periodic 2 x 2 mesh of
+    squares of side h with psi = +1 in the left column and -1 in the right one, every x face
+    of an element sees the jump 2 psi_e and every y face none, so at point (a, b)
+    R = -(2 / h) (2 tau psi_e) (l_a(-1) / w_a + l_a(+1) / w_a),
+    with the Gauss-Legendre nodes and weights and the Lagrange basis l_a computed here."""
+    mesh, prm = W.small_case(2, p, (2, 2))
+    prm = dataclasses.replace(prm, tau=0.37)
+    o = Oracle(2, p, mesh, prm)
+    x = o.coords()                                     # [E, Nu, 2]
+    sign = np.where(x[:, 0, 0] < 0.5, 1.0, -1.0)       # element column
+    psi = T(np.repeat(sign[:, None], x.shape[1], axis=1))
+    nu = o.sensor(psi)
+    assert float(torch.max(torch.abs(nu))) == 0.0
+    R = o.precond_residual(psi, torch.zeros_like(psi))
+    n = p + 1
+    xi, w = np.polynomial.legendre.leggauss(n)
+
+    def lag(a, s):
+        return np.prod([(s - xi[c]) / (xi[a] - xi[c]) for c in range(n) if c != a])
+
+    lift = np.array([(lag(a, -1.0) + lag(a, 1.0)) / w[a] for a in range(n)])
+    h = 0.5
+    # solution points of a quad: first index (x) fastest
+    ia = np.tile(np.arange(n), n)
+    expect = -(2.0 / h) * (2.0 * prm.tau * sign[:, None]) * lift[ia][None, :]
+    assert np.abs(R.numpy() - expect).max() < 1e-12 * np.abs(expect).max()

@@ -2,7 +2,8 @@
 
 P7  mass conservation over a full run (the 16x16, p=3 advection workload, 200 steps).
 P10 return of a rotated disk after one revolution (§4.1 velocity field).
-P11 classic RK4: the amplification factor of u' = lambda u.
+P11 classic RK4: the amplification factor of u' = lambda u; P11b its stage times (fourth order
+    on a time-dependent field).
 """
 import math
 
@@ -60,3 +61,29 @@ def test_rotated_disk_returns():
     assert abs(float(o.mass_error(phi, phi0, phi0))) < 1e-12
     er = float(o.rel_error(phi, phi0))
     assert er < 0.2, er
+
+
+def test_rk4_stage_times_fourth_order_on_time_dependent_field():
+    """P11b: classic RK4 evaluates the velocity at the stage times t, t + dt/2, t + dt/2,
+    t + dt (§3.1 Step 6 with the time factor cos(pi t / T) of §4.2). On the single vortex,
+    whose amplitude changes over the run, the step error of the semi-discrete system must
+    fall 16x per halving of dt (fourth order); a stage evaluated at a wrong time breaks the
+    condition sum b_i c_i = 1/2 and leaves first order (ratio 2). Same mesh for every dt, so
+    the spatial error cancels. gamma = 0 keeps the right-hand side smooth in time (the kink
+    of max(gamma, |v|) where |v| crosses gamma costs RK4 its order: ratios 3-5 with the
+    paper's gamma), and no reset falls inside the runs."""
+    mesh, prm = W.small_case(2, 2, (6, 6), vel_kind=W.VEL_SINGLE_VORTEX, vel_period=0.5,
+                             reset_every=10 ** 9, gamma=0.0)
+    o = Oracle(2, 2, mesh, prm)
+    phi0 = T(W.ic_phi(o.coords(), (0.5, 0.6), 0.25, prm.eps_w * 4))
+    psi0, _ = o.precondition(phi0)
+    t0, span = 0.05, 0.15                     # g = cos(pi t / 0.5) falls from 0.95 to 0.59
+
+    def run(n):
+        phi, psi, t = o.run(phi0, psi0, t0, span / n, n, step0=1)
+        assert abs(t - (t0 + span)) < 1e-14
+        return phi
+
+    ref = run(256)
+    e = [float(torch.max(torch.abs(run(n) - ref))) for n in (16, 32)]
+    assert e[1] > 0 and 14.0 < e[0] / e[1] < 19.0, e
