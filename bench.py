@@ -116,6 +116,21 @@ def stage_words_of(cfg, form):
     return stage_words(cfg.ndims, cfg.order, cfg.element, lifted, tables)
 
 
+# dense MFMA peaks of MI355X (TFLOP/s) of the instructions the triangle kernel issues
+MFMA_PEAK_TFS = {"fp64": 78.6, "fp32": 157.3}
+TRI_MFMA_PER_TILE = 72          # operator products x 4 K-steps per 16-element tile
+
+
+def tri_mfma_flops(cfg, form):
+    """Matrix-core flops of one launch of the triangle MFMA grad_flux (p <= 4, FP64 and
+    FP32): 72 instructions of 16 x 16 x 4 (2048 flops each, zero padding included) per
+    tile of 16 elements; None where that kernel does not run."""
+    if cfg.element != "triangle" or cfg.order > 4 or form not in MFMA_PEAK_TFS:
+        return None
+    tiles = (cfg.nelem + 15) // 16
+    return tiles * TRI_MFMA_PER_TILE * 16 * 16 * 4 * 2
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     for f in ("pcpf_kernels.hip", "pcpf_kernels_impl.h", "pcpf_internal.h", "pcpf_device.h",
@@ -257,6 +272,12 @@ def workload_leg(name, forms, K, Wm, acc_steps, hsh):
                 kk["counter_GBs"] = kk["counter_bytes"] / (kk["avg_us"] * 1e3)
         if traffic:
             f["roofline"]["traffic_over_alg"] = traffic["stage"] / alg
+        mf = tri_mfma_flops(cfg, form)
+        if mf:
+            tf = mf / (gf_us * 1e-6) / 1e12
+            f["mfma"] = {"kernel": "k_tri_grad_flux_mf", "flops_per_launch": mf,
+                         "achieved": tf, "peak": MFMA_PEAK_TFS[form], "unit": "TFLOP/s",
+                         "frac": tf / MFMA_PEAK_TFS[form]}
         if phi_acc is not None:
             m0 = s.mass(torch.as_tensor(phi0).to("cuda:0", s.dtype))
             if ref is None:
@@ -276,7 +297,8 @@ def workload_leg(name, forms, K, Wm, acc_steps, hsh):
             f"stage {stage_us:.1f} us (grad_flux {gf_us:.1f} + update {up_us:.1f}), "
             f"{achieved:.0f} GB/s alg ({achieved / HBM_PEAK_GBS:.3f} of HBM), "
             f"reset+precond {r['pc_ms']:.2f} ms"
-            + (f", int|phi-phi64| {f['after_steps'].get('interface_l1_vs_fp64', 0):.2e}" if phi_acc is not None else ""))
+            + (f", int|phi-phi64| {f['after_steps'].get('interface_l1_vs_fp64', 0):.2e}" if phi_acc is not None else "")
+            + (f", MFMA {f['mfma']['achieved']:.1f} TFLOP/s ({f['mfma']['frac']:.3f} of peak)" if "mfma" in f else ""))
         if ref is None or s is not ref[0]:
             del s
         torch.cuda.empty_cache()

@@ -78,3 +78,18 @@ def test_triangle_stage_words(p):
     if p == 4:
         # 1024^2 cells, 2 097 152 triangles: FP64 B_alg per stage
         assert abs(w["alg"] * 8 * 2 * 1024 ** 2 / 1e9 - (210 * 8 * 2 * 1024 ** 2) / 1e9) < 1e-9
+
+
+def test_triangle_mfma_flops():
+    """The matrix-core flops of one launch of the triangle MFMA grad_flux: 18 operator
+    products per 16-element tile (Steps 1-3: M0 u and, per direction, D_k u and the lifted
+    jump, for both variables; Step 5: M0 of the two gradient components of both variables;
+    Step 6: DH_0 and DH_1 for both variables), each four 16 x 16 x 4 instructions of 2048
+    flops; none for tensor elements or orders above 4."""
+    import workloads as W
+    t2 = W.config("T2")
+    tiles = (t2.nelem + 15) // 16
+    assert bench.TRI_MFMA_PER_TILE == (2 * (1 + 2 * 2) + 2 * 2 + 2 * 2) * 4
+    assert bench.tri_mfma_flops(t2, "fp64") == tiles * 72 * 2048
+    assert bench.tri_mfma_flops(t2, "bf16") is None
+    assert bench.tri_mfma_flops(W.config("C5"), "fp64") is None
