@@ -17,14 +17,14 @@ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 // to whole 64-wide waves. The face phases split the block's face points by reference
 // direction into units of one wave (KSEG = EPB N_fa points per direction, WK waves each),
 // so that the direction, and with it every stride of the face code, is uniform in a wave.
-template <int D, int P, int TPB = 256>
+template <int D, int P, int TPB = 256, int NTO = 0>
 struct Shape {
     static constexpr int N = P + 1;
     static constexpr int NU = ipow(N, D);
     static constexpr int NFA = ipow(N, D - 1);
     static constexpr int NF = 2 * D * NFA;
     static constexpr int EPB = (TPB / NU) >= 1 ? TPB / NU : 1;
-    static constexpr int NT = (EPB * NU + 63) / 64 * 64;
+    static constexpr int NT = NTO ? NTO : (EPB * NU + 63) / 64 * 64;
     static constexpr int NW = NT / 64;
     static constexpr int KSEG = EPB * NFA;
     static constexpr int WK = (KSEG + 63) / 64;
@@ -37,6 +37,17 @@ struct Shape {
 // in FP64 (eight elements per block, so that the runs a block reads and writes in each face
 // plane span eight elements: 96^3 p4 2274 us at 256, 2206 at 512, 2056 at 1024) and 512 in
 // FP32 (1144 us; 1196 at 1024); 256 otherwise (no gain at 64 points).
+// Threads per block of the line kernel. 3D in FP32: one wave per unit of line work (D WK
+// waves), the solution-point phases looping over the block's points where those exceed the
+// threads, so that no wave of a block idles through the line phases (96^3 p4 grad_flux
+// 1135 -> 1103 us, 64^3 p3 146 -> 141 us). FP64 keeps a thread per point: with three waves
+// per block it lost (2054 -> 2072 us, 262 -> 284 us).
+template <typename R, int D, int P>
+constexpr int lines_nt() {
+    using S = Shape<D, P>;
+    return (D == 3 && sizeof(R) == 4 && 64 * S::NUNITS < S::NT) ? 64 * S::NUNITS : S::NT;
+}
+
 constexpr int update_tpb(int d, int p, int word) {
     return (d == 3 && p >= 4) ? (word == 8 ? 1024 : 512) : 256;
 }

@@ -749,10 +749,10 @@ constexpr int lines_waves(int p) { return p <= 3 ? 7 : 6; }
 // STREAM: the state planes exceed the caches; the state loads and the P stores (each value
 // read or written once per launch) go with the non-temporal hint.
 template <typename R, int D, int P, bool AXIS, bool NPHI, bool STREAM>
-__global__ __launch_bounds__((Shape<D, P>::NT))
+__global__ __launch_bounds__((lines_nt<R, D, P>()))
 __attribute__((amdgpu_waves_per_eu(lines_waves(P))))
 void k_grad_flux_lines(GFArgs<R> a) {
-    using S = Shape<D, P>;
+    using S = Shape<D, P, 256, lines_nt<R, D, P>()>;
     constexpr int N = S::N, NU = S::NU, NFA = S::NFA, EPB = S::EPB, NT = S::NT, G = S::GEO;
     constexpr int V = 2;
     constexpr int NV = NPHI ? 0 : 1;               // variable the interface normal is of
@@ -779,9 +779,6 @@ void k_grad_flux_lines(GFArgs<R> a) {
     const int tid = threadIdx.x;
     const int64_t e0 = (int64_t)block_chunk<R>(a.E * NU) * EPB;
     const int nel = (int)((a.E - e0) < EPB ? (a.E - e0) : EPB);
-    const bool pt = tid < nel * NU;
-    const int le = tid / NU;
-    const int ip = tid - le * NU;
     const uint32_t Eu = (uint32_t)a.E;
     const bool trig = a.ph.vel_kind == PCPF_VEL_SINGLE_VORTEX || a.ph.vel_kind == PCPF_VEL_LEVEQUE3D;
 
@@ -1144,8 +1141,19 @@ void k_grad_flux_lines(GFArgs<R> a) {
     // the point fluxes below overwrite the gradient the face phase reads along lines
     __syncthreads();
 
+    // solution-point phases: one pass when the block has a thread per point, else a loop
+    // over the block's points
+    auto for_points = [&](auto body) {
+        if constexpr (NT >= EPB * NU) {
+            if (tid < nel * NU) body(tid);
+        } else {
+            for (int tp = tid; tp < nel * NU; tp += NT) body(tp);
+        }
+    };
+
     // ---- B2: fluxes at the solution points (Step 4) --------------------------------------
-    if (pt) {
+    for_points([&](const int tp) {
+        const int le = tp / NU, ip = tp - le * NU;
         const R* gg = &s_geo[le * G];
         const R det = gg[D + 2 * D * D];
         const R* Ji = gg + D + D * D;            // Jinv[k][i] = Ji[k*D + i]
@@ -1163,7 +1171,7 @@ void k_grad_flux_lines(GFArgs<R> a) {
         for (int v = 0; v < V; ++v) {
             R qt[D];
 #pragma unroll
-            for (int i = 0; i < D; ++i) qt[i] = s_x[(v * D + i) * XST + tid];
+            for (int i = 0; i < D; ++i) qt[i] = s_x[(v * D + i) * XST + tp];
             to_physical(le, qt, q[v]);
         }
         R vel[D];
@@ -1176,7 +1184,7 @@ void k_grad_flux_lines(GFArgs<R> a) {
         }
         const R mm = max_sqrt(v2, a.ph.gamma);
         const R rn = M::rsqrt_(g2 + a.ph.delta_n * a.ph.delta_n);
-        const R phi = s_u[0][tid], psi = s_u[1][tid];
+        const R phi = s_u[0][tp], psi = s_u[1][tp];
         const R sharp = a.ph.gamma * phi * (R(1) - phi) * rn;
         R f0[D], f1[D];
 #pragma unroll
@@ -1200,10 +1208,10 @@ void k_grad_flux_lines(GFArgs<R> a) {
                     a1 += Ji[k * D + i] * f1[i];
                 }
             }
-            s_x[(0 * D + k) * XST + tid] = det * a0;
-            s_x[(1 * D + k) * XST + tid] = det * a1;
+            s_x[(0 * D + k) * XST + tp] = det * a0;
+            s_x[(1 * D + k) * XST + tp] = det * a1;
         }
-    }
+    });
     __syncthreads();
 
     // ---- E1: DH_K f~_K along each line (volume part of Step 6), in place, plus the
@@ -1240,15 +1248,15 @@ void k_grad_flux_lines(GFArgs<R> a) {
     __syncthreads();
 
     // ---- E2: P = sum over the directions ------------------------------------------------
-    if (pt) {
+    for_points([&](const int tp) {
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             R acc = R(0);
 #pragma unroll
-            for (int k = 0; k < D; ++k) acc += s_x[(v * D + k) * XST + tid];
-            gst_s<STREAM>(a.P[v] + e0 * NU, (uint32_t)tid, acc);
+            for (int k = 0; k < D; ++k) acc += s_x[(v * D + k) * XST + tp];
+            gst_s<STREAM>(a.P[v] + e0 * NU, (uint32_t)tp, acc);
         }
-    }
+    });
 }
 
 // ------------------------------------------------------------------------------------
@@ -1556,12 +1564,13 @@ struct Impl {
     template <int MODE, bool AXIS, bool MF, bool NPHI>
     static void gf_launch(const GFArgs<R>& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
         if constexpr (lines(MODE, MF)) {
+            constexpr int NTL = lines_nt<R, D, P>();
             if (a.E * S::NU * (int64_t)sizeof(R) > XCD_MAP_MAX_PLANE_BYTES)
                 hipExtLaunchKernelGGL((k_grad_flux_lines<R, D, P, AXIS, NPHI, true>), dim3(grid(a.E)),
-                                      dim3(S::NT), 0, st, e0, e1, 0, a);
+                                      dim3(NTL), 0, st, e0, e1, 0, a);
             else
                 hipExtLaunchKernelGGL((k_grad_flux_lines<R, D, P, AXIS, NPHI, false>), dim3(grid(a.E)),
-                                      dim3(S::NT), 0, st, e0, e1, 0, a);
+                                      dim3(NTL), 0, st, e0, e1, 0, a);
         } else {
             hipExtLaunchKernelGGL((k_grad_flux<R, D, P, MODE, AXIS, MF, NPHI>), dim3(grid(a.E)),
                                   dim3(S::NT), 0, st, e0, e1, 0, a);
