@@ -51,6 +51,10 @@ CASES = [
                                               vel_period=3.0)),
     ("3d_p3_skew", 3, 3, (4, 5, 3), dict(shear=(0.25, 0.05, 0.2), vel_kind=W.VEL_LEVEQUE3D,
                                          vel_period=3.0)),
+    # odd element counts: the last block of the 3D FP32 line kernel holds one element, and
+    # at p = 5 its 216 points take two passes of the 192-thread block
+    ("3d_p4_ragged", 3, 4, (3, 3, 3), dict(vel_kind=W.VEL_LEVEQUE3D, vel_period=3.0)),
+    ("3d_p5_copybc", 3, 5, (3, 2, 3), dict(periodic=False)),
 ]
 
 
