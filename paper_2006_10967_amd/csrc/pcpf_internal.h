@@ -33,10 +33,6 @@ struct Shape {
     static constexpr int GEO = D + 2 * D * D + 1;   // x0[D], J[D][D], Jinv[D][D], detJ
 };
 
-// Threads per block of the update kernel: for the 3D elements of 125 or more points, 1024
-// in FP64 (eight elements per block, so that the runs a block reads and writes in each face
-// plane span eight elements: 96^3 p4 2274 us at 256, 2206 at 512, 2056 at 1024) and 512 in
-// FP32 (1144 us; 1196 at 1024); 256 otherwise (no gain at 64 points).
 // Threads per block of the line kernel. 3D in FP32: one wave per unit of line work (D WK
 // waves), the solution-point phases looping over the block's points where those exceed the
 // threads, so that no wave of a block idles through the line phases (96^3 p4 grad_flux
@@ -48,8 +44,14 @@ constexpr int lines_nt() {
     return (D == 3 && sizeof(R) == 4 && 64 * S::NUNITS < S::NT) ? 64 * S::NUNITS : S::NT;
 }
 
+// Threads per block of the update kernel: for the 3D elements of 125 or more points in FP64,
+// 1024 (eight elements per block, so that the runs a block reads and writes in each face
+// plane span eight elements: 96^3 p4 2274 us at 256, 2206 at 512, 2056 at 1024, before
+// the per-XCD runs of chunks; with them 512 and 1024 are within 0.5 %); 256 otherwise
+// (FP32 96^3 p4 with the per-XCD runs: 992 us at 256, 1031 at 512, 1075 at 1024; no gain
+// from larger blocks at 64 points).
 constexpr int update_tpb(int d, int p, int word) {
-    return (d == 3 && p >= 4) ? (word == 8 ? 1024 : 512) : 256;
+    return (d == 3 && p >= 4 && word == 8) ? 1024 : 256;
 }
 
 // Lane utilisation (per mille) of nt-thread blocks holding whole elements of nu points.
