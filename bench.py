@@ -677,6 +677,62 @@ def rotation_leg(orders=(2, 3, 4, 5)):
     return out
 
 
+def dense_gemm_leg():
+    """The operator products of one RK stage in the dense form of §3.1 (M0, D_k, the
+    lifting, as dense matrices) on the tensor workloads, run as library GEMMs on the matrix
+    cores (torch.matmul / addmm, the reference operators times the values of all elements
+    at once, random data of the right shapes): a lower bound for a dense-form stage, which
+    would add the pointwise work, the face exchanges and the RK combine. A measurement of
+    the design alternative, not the product path."""
+    import torch
+    out = {}
+    for dtype, tag in ((torch.float64, "fp64"), (torch.float32, "fp32")):
+        for name, n, p in (("C3", 64, 3), ("C5", 96, 4)):
+            d, V, E = 3, 2, n ** 3
+            N = p + 1
+            NU, NF = N ** d, 2 * d * N ** (d - 1)
+            g = torch.Generator(device="cuda").manual_seed(0)
+
+            def rnd(*shape):
+                return torch.randn(*shape, device="cuda", dtype=dtype, generator=g)
+            M0, Dk, LN = rnd(NF, NU), rnd(NU, NU), rnd(NU, NF)
+            u, jf, qd = rnd(NU, V * E), rnd(NF, V * E), rnd(NU, d * V * E)
+            out_f = torch.empty(NF, d * V * E, device="cuda", dtype=dtype)
+            out_u = torch.empty(NU, V * E, device="cuda", dtype=dtype)
+            out_uf = torch.empty(NF, V * E, device="cuda", dtype=dtype)
+
+            def stage():
+                torch.matmul(M0, u, out=out_uf)                     # Step 1: traces
+                for _ in range(d):                                  # Step 3: gradient
+                    torch.matmul(Dk, u, out=out_u)
+                    torch.addmm(out_u, LN, jf, out=out_u)
+                torch.matmul(M0, qd, out=out_f)                     # Step 3: q at flux points
+                torch.matmul(M0, qd, out=out_f)                     # Step 4: normal flux
+                for k in range(d):                                  # Step 6: divergence
+                    torch.matmul(Dk, qd[:, k * V * E:(k + 1) * V * E], out=out_u)
+                torch.addmm(out_u, LN, jf, out=out_u)
+            flops = 2 * V * E * (NF * NU + d * (NU * NU + NU * NF) + 2 * d * NF * NU
+                                 + d * NU * NU + NU * NF)
+            for _ in range(3):
+                stage()
+            sync()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 10
+            e0.record()
+            for _ in range(reps):
+                stage()
+            e1.record()
+            sync()
+            us = e0.elapsed_time(e1) / reps * 1e3
+            out[f"{name}_{tag}"] = {"operator_gemm_us_per_stage": us, "gflop": flops / 1e9,
+                                    "tflops": flops / (us * 1e-6) / 1e12}
+            log(f"[bench] dense operator GEMMs {name} {tag}: {us:.0f} us per stage, "
+                f"{flops / 1e9:.1f} GFLOP at {flops / (us * 1e-6) / 1e12:.1f} TFLOP/s")
+            del M0, Dk, LN, u, jf, qd, out_f, out_u, out_uf
+            torch.cuda.empty_cache()
+    return out
+
+
 def pseudo_sweep_leg():
     """The single vortex on 128^2 quads, p = 4, to t = T (FP64) with the pseudo-time per
     reset swept: K iterations at the default pseudo step for K = 0, 5, 10, 20, 40, resets
@@ -742,6 +798,8 @@ def main():
                     help="the 3D deformation to t = T on 32^3, p = 2..5")
     ap.add_argument("--pseudo-sweep", action="store_true",
                     help="the 128^2 p=4 vortex to t = T with K = 0..40 pseudo iterations")
+    ap.add_argument("--dense-gemm", action="store_true",
+                    help="one stage's operator products in the dense form, as library GEMMs")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -820,6 +878,8 @@ def main():
         out["leveque_table"] = leveque_table_leg()
     if args.pseudo_sweep:
         out["pseudo_sweep"] = pseudo_sweep_leg()
+    if args.dense_gemm:
+        out["dense_gemm"] = dense_gemm_leg()
 
     if not args.no_small_run:
         out["small_workload_full_run"] = small_workload_run()
