@@ -732,8 +732,9 @@ void k_grad_flux(GFArgs<R> a) {
 //       registers the + face values of the line: the own trace, the neighbour's trace and
 //       the interpolated K component of the gradient.
 //   B2  line threads: the common flux of the + face point (Step 5), reading only the other
-//       gradient components at the face; all threads: the flux at their solution point
-//       (Step 4) to LDS.
+//       gradient components at the face; all threads: the flux at their solution points
+//       (Step 4) to LDS (one point per thread, or a loop over the block's points where the
+//       block has a wave per unit of line work only: 3D in FP32, lines_nt).
 //   E1  line threads: DH_K applied along the line (volume part of Step 6) plus the lifting
 //       of the line's + face common flux from B2, to LDS.
 //   E2  all threads: P = the sum over the directions (fixed order), to global; the update
