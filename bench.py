@@ -492,6 +492,60 @@ def accuracy_leg(cfg, mesh, phi0_np):
     return out
 
 
+def full_period_leg(name, forms, chunk=2000):
+    """A workload run to t = T (the LeVeque field's period, where the interface is back at
+    its start) in the FP64 form and the given reduced forms, the equal-interface-error
+    protocol at t = T: E_L1 = int|phi(T) - phi(0)| of each form, E_m, and int|phi - phi_64|,
+    "equal" when |E_L1 - E_L1,64| <= 0.02 E_L1,64 and int|phi - phi_64| <= 0.1 E_L1,64. The
+    steps run in chunks with a progress line per chunk."""
+    import torch
+    import workloads as W
+    cfg = W.config(name)
+    mesh = cfg.mesh()
+    dt = cfg.dt(mesh)
+    nsteps = int(round(cfg.params.vel_period / dt))
+    phi0_np = initial_state(cfg, mesh)
+    out = {"workload": cfg.name, "t_end": nsteps * dt, "steps": nsteps}
+    ref = None
+    for form in forms:
+        s = make_solver(cfg, mesh, form)
+        phi0 = torch.as_tensor(phi0_np).to("cuda:0", s.dtype)
+        s.set_state(phi0, None, 0.0, 0)
+        sync()
+        t0 = time.perf_counter()
+        done = 0
+        while done < nsteps:
+            k = min(chunk, nsteps - done)
+            s.step(dt, k)
+            done += k
+            log(f"[bench] {cfg.name} {form}: {done}/{nsteps} steps, {time.perf_counter() - t0:.0f} s")
+        sync()
+        wall = time.perf_counter() - t0
+        phiT = s.get_state(want_psi=False)[0].double()
+        if ref is None:
+            m0 = s.mass(phi0)
+            e64 = s.l1(phi0, phiT)
+            ref = (s, phi0.double(), phiT, e64, m0, wall)
+            out[form] = {"E_L1": e64, "E_r": e64 / m0, "E_m": (s.mass(phiT) - m0) / m0,
+                         "wall_s": wall}
+            log(f"[bench] {cfg.name} to t = T ({form}): E_L1 = {e64:.4e}, E_m = {out[form]['E_m']:.2e}, {wall:.0f} s")
+            del phiT
+            continue
+        s64, p0, phi64, e64, m0, wall64 = ref
+        e_l1 = s64.l1(p0, phiT)
+        diff = s64.l1(phi64, phiT)
+        out[form] = {"E_L1": e_l1, "E_r": e_l1 / m0, "E_m": (s64.mass(phiT) - m0) / m0,
+                     "int_abs_diff_vs_fp64": diff, "wall_s": wall,
+                     "speedup_vs_fp64": wall64 / wall,
+                     "equal_interface_error": bool(abs(e_l1 - e64) <= 0.02 * e64 and diff <= 0.1 * e64)}
+        log(f"[bench] {cfg.name} to t = T ({form}): E_L1 = {e_l1:.4e} (fp64 {e64:.4e}), "
+            f"int|phi-phi64| = {diff:.2e}, equal: {out[form]['equal_interface_error']}, "
+            f"x{out[form]['speedup_vs_fp64']:.2f}")
+        del s, phiT
+        torch.cuda.empty_cache()
+    return out
+
+
 def deformation_leg():
     """The LeVeque deformation test on 64^3 hexes, p = 3, run to t = T = 3 (§4.3), FP64:
     E_L1 = int|phi(T) - phi(0)| and E_m with the default readings and with the longer
@@ -800,6 +854,9 @@ def main():
                     help="the 128^2 p=4 vortex to t = T with K = 0..40 pseudo iterations")
     ap.add_argument("--dense-gemm", action="store_true",
                     help="one stage's operator products in the dense form, as library GEMMs")
+    ap.add_argument("--full-period", default="",
+                    help="run this workload to t = T in the forms of --full-forms (FP64 first)")
+    ap.add_argument("--full-forms", default="fp64,fp32")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -880,6 +937,11 @@ def main():
         out["pseudo_sweep"] = pseudo_sweep_leg()
     if args.dense_gemm:
         out["dense_gemm"] = dense_gemm_leg()
+    if args.full_period:
+        ff = [f for f in args.full_forms.split(",") if f]
+        if not ff or ff[0] != "fp64":
+            sys.exit("--full-forms must start with fp64 (the reference of the comparison)")
+        out["full_period"] = full_period_leg(args.full_period, ff)
 
     if not args.no_small_run:
         out["small_workload_full_run"] = small_workload_run()
