@@ -880,8 +880,13 @@ void k_grad_flux_lines(GFArgs<R> a) {
 
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
-    const R* lp = &s_ops[op_lp(N)];
-    const R* cpv = &s_ops[op_cp(N)];
+    // the line operators are read with wave-uniform indices straight from the operator block
+    // in global memory, through the constant address space (read-only for the whole launch:
+    // scalar loads into SGPRs), so that the LDS carries only element data
+    using CR = const __attribute__((address_space(4))) R;
+    CR* cops = (CR*)a.ops;
+    CR* lp = cops + op_lp(N);
+    CR* cpv = cops + op_cp(N);
     const R* xi = &s_ops[op_xi(N)];
     // line units: unit u = wave + j NW covers direction k = u / WK (uniform in the wave) and
     // the lines (u % WK) 64 + lane of that direction: element el, + face point t
@@ -910,18 +915,22 @@ void k_grad_flux_lines(GFArgs<R> a) {
         constexpr int K = decltype(KC)::value;
         constexpr int SK = st<N>(K);
         const int base = el * NU + face_base<D, N>(K, t);
-        // + face with a neighbour: the LDG jump (nb - own trace) is lifted; the own-trace
-        // part is folded into DT = D1 - cp (x) lp (boundary + faces: s_nb holds 0)
+        // the LDG jump (nb - own trace) is lifted, the own-trace part folded into
+        // DT = D1 - cp (x) lp; on a + face without a neighbour (copy boundary: no jump) the
+        // neighbour trace is taken as the own one, so that DT u + cp uf = D1 u and every line
+        // applies the same, wave-uniform operator
         const bool hk = s_nbr[el * 2 * D + 2 * K + 1] >= 0;
-        const R* Dm = &s_ops[hk ? op_dt(N) : OP_D1];
+        CR* Dm = cops + op_dt(N);
         const R jkk = AXIS ? s_geo[el * G + D + D * D + K * D + K] : R(1);
         R ul[V][N], nbv[V], uf[V], qf[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) {
 #pragma unroll
             for (int q = 0; q < N; ++q) ul[v][q] = s_u[v][base + q * SK];
-            nbv[v] = s_nb[v][el * NPF + K * NFA + t];
             uf[v] = R(0);
+#pragma unroll
+            for (int q = 0; q < N; ++q) uf[v] += lp[q] * ul[v][q];
+            nbv[v] = hk ? s_nb[v][el * NPF + K * NFA + t] : uf[v];
             qf[v] = R(0);
         }
         // one operator row at a time, applied to both variables
@@ -939,7 +948,6 @@ void k_grad_flux_lines(GFArgs<R> a) {
                 acc += c * nbv[v];
                 const R qv = AXIS ? jkk * acc : acc;
                 s_x[(v * D + K) * XST + base + q * SK] = qv;
-                uf[v] += l * ul[v][q];
                 qf[v] += l * qv;
             }
         }
@@ -1218,7 +1226,7 @@ void k_grad_flux_lines(GFArgs<R> a) {
     // ---- E1: DH_K f~_K along each line (volume part of Step 6), in place, plus the
     // lifting cp F~ of the line's + face common flux (the face part of Step 6 on the faces
     // this element owns; the update adds the - faces') ----------------------------------
-    const R* DH = &s_ops[op_dh(N)];
+    CR* DH = cops + op_dh(N);
     for_units([&](auto KC, int j, int el, int t) {
         (void)j;
         constexpr int K = decltype(KC)::value;
