@@ -107,11 +107,13 @@ def stage_words(d, p, element="tensor", lifted=False, tables=False):
 
 
 def stage_words_of(cfg, form):
-    """stage_words for a workload and form: the line kernel (3D; 2D in FP32; not the BF16
-    form) lifts the + face fluxes into P; the trigonometric fields on the workloads' box
-    meshes (axis-aligned elements) read the per-element velocity tables."""
+    """stage_words for a workload and form: the line kernel (3D; 2D in FP32, and in FP64
+    from p = 4; not the BF16 form) lifts the + face fluxes into P; the trigonometric fields
+    on the workloads' box meshes (axis-aligned elements) read the per-element velocity
+    tables."""
     import workloads as W
-    lifted = cfg.element == "tensor" and form != "bf16" and (cfg.ndims == 3 or form == "fp32")
+    lifted = cfg.element == "tensor" and form != "bf16" and (cfg.ndims == 3 or form == "fp32"
+                                                             or cfg.order >= 4)
     tables = cfg.element == "tensor" and cfg.params.vel_kind in (W.VEL_SINGLE_VORTEX, W.VEL_LEVEQUE3D)
     return stage_words(cfg.ndims, cfg.order, cfg.element, lifted, tables)
 

@@ -1565,9 +1565,10 @@ struct Impl {
     using S = Shape<D, P>;
     static unsigned grid(int64_t E) { return (unsigned)((E + S::EPB - 1) / S::EPB); }
     // the line kernel runs the physical mode, outside the BF16 form, in 3D, and in 2D in
-    // FP32 (128^2 p4: FP32 grad_flux 6.9 -> 6.2 us; FP64 9.8 against 10.0 us with the point
-    // kernel)
-    static constexpr bool LINES_DIM = D == 3 || sizeof(R) == 4;
+    // FP32 (128^2 p4: FP32 grad_flux 6.9 -> 6.2 us) and in FP64 from p = 4 (128^2 p4 with
+    // the operators in SGPRs and the + face lifting: 0.0763 -> 0.0720 ms/step; at 64^2 p3
+    // the point kernel stays ahead, 0.0307 against 0.0319)
+    static constexpr bool LINES_DIM = D == 3 || sizeof(R) == 4 || P >= 4;
     static constexpr bool lines(int mode, bool mf) { return mode == GF_PHYS && !mf && LINES_DIM; }
 
     template <int MODE, bool AXIS, bool MF, bool NPHI>

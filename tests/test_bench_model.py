@@ -48,14 +48,15 @@ def test_stage_impl_words(d, p, lifted, tables):
 
 
 def test_stage_words_of_forms():
-    """Which kernels run: the line kernel (3D in FP64 and FP32, 2D in FP32) lifts the + face
-    fluxes; the BF16 form and 2D FP64 do not; the box workloads with trigonometric fields
-    read the velocity tables, the uniform-velocity one does not."""
+    """Which kernels run: the line kernel (3D in FP64 and FP32, 2D in FP32, and in FP64 from
+    p = 4) lifts the + face fluxes; the BF16 form and 2D FP64 below p = 4 do not; the box
+    workloads with trigonometric fields read the velocity tables, the uniform-velocity one
+    does not."""
     import workloads as W
     c5, c2, c1 = W.config("C5"), W.config("C2"), W.config("C1")
     assert bench.stage_words_of(c5, "fp64") == bench.stage_words(3, 4, lifted=True, tables=True)
     assert bench.stage_words_of(c5, "bf16") == bench.stage_words(3, 4, lifted=False, tables=True)
-    assert bench.stage_words_of(c2, "fp64") == bench.stage_words(2, 4, lifted=False, tables=True)
+    assert bench.stage_words_of(c2, "fp64") == bench.stage_words(2, 4, lifted=True, tables=True)
     assert bench.stage_words_of(c2, "fp32") == bench.stage_words(2, 4, lifted=True, tables=True)
     assert bench.stage_words_of(c1, "fp64") == bench.stage_words(2, 3, lifted=False, tables=False)
 
